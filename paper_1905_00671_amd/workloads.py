@@ -1,0 +1,406 @@
+"""Seeded synthetic inputs for the stabilized implicit MPM (Zhao & Choo, arXiv 1905.00671).
+
+This module builds problem *statements* only: background grids, material points, material
+constants and the per-step boundary data (Dirichlet masks/values, nodal forces and fluxes) of
+the strong form in Sec. 2.4.  It contains none of the method's arithmetic (no basis functions,
+no constitutive law, no residuals).  Both the GPU library and the CPU oracle consume the arrays
+produced here.
+
+Workloads (sizes and physics follow the benchmark configurations of this repository):
+  * ``terzaghi``      2D plane-strain consolidation column (Sec. 5.1 problem, re-parametrized).
+  * ``footing2d``     2D displacement-controlled rigid strip footing on a half-model.
+  * ``footing3d``     3D square footing on a quarter-model.
+  * ``serving_trace`` a Poisson arrival stream of independent 2D problems.
+
+Material points are placed 2 per axis per cell at (1/4, 3/4) h, with V0 = h^d / 2^d, GIMP
+half-lengths lp0 = h/4, and mass m = rho0 V0 with the mixture density of Sec. 2.1,
+rho0 = (1 - phi0) rho_s + phi0 rho_f.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Tuple
+
+import numpy as np
+
+LINEAR, GIMP = 0, 1
+HENCKY, NEO_HOOKEAN = 0, 1
+TAU_OFF, TAU_WHITE, TAU_SUN, TAU_MONFORTE = 0, 1, 2, 3
+
+
+@dataclass
+class Grid:
+    """Fixed structured background grid (Sec. 3.5: the mesh is never moved)."""
+    dim: int
+    ncell: Tuple[int, ...]
+    h: float
+    origin: Tuple[float, ...] = (0.0, 0.0, 0.0)
+
+    @property
+    def nnode_axis(self) -> Tuple[int, ...]:
+        return tuple(n + 1 for n in self.ncell[: self.dim])
+
+    @property
+    def nnode(self) -> int:
+        return int(np.prod(self.nnode_axis))
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(self.ncell[: self.dim]))
+
+    def node_coords(self) -> np.ndarray:
+        """Node coordinates, shape (nnode, dim); node id = ix + nx1*(iy + ny1*iz)."""
+        axes = [self.origin[d] + self.h * np.arange(self.nnode_axis[d]) for d in range(self.dim)]
+        mesh = np.meshgrid(*axes, indexing="ij")
+        # natural order: x fastest
+        return np.stack([m.transpose(*reversed(range(self.dim))).reshape(-1) for m in mesh], axis=1)
+
+    def node_index(self, *idx) -> int:
+        n = self.nnode_axis
+        if self.dim == 2:
+            return idx[0] + n[0] * idx[1]
+        return idx[0] + n[0] * (idx[1] + n[1] * idx[2])
+
+
+@dataclass
+class Material:
+    """Constants of Sec. 2: skeleton elasticity (E, nu), permeability k, fluid viscosity mu_f,
+    intrinsic densities, initial porosity and gravity."""
+    model: int = NEO_HOOKEAN
+    E: float = 10e6
+    nu: float = 0.3
+    k: float = 1e-12
+    mu_f: float = 1e-3
+    rho_s: float = 2500.0
+    rho_f: float = 1000.0
+    phi0: float = 0.33
+    g: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+    @property
+    def rho0(self) -> float:
+        return (1.0 - self.phi0) * self.rho_s + self.phi0 * self.rho_f
+
+
+@dataclass
+class Options:
+    shape: int = LINEAR
+    dynamic: int = 0
+    beta: float = 0.25
+    gamma: float = 0.5
+    tau_kind: int = TAU_WHITE
+    tau_scale: float = 1.0
+    mixed: int = 0                 # 0: FP64 everywhere; 1: FP32 Jacobian/SpMV/preconditioner
+    newton_rtol: float = 1e-8
+    newton_max: int = 25
+    krylov_rtol: float = 1e-8
+    krylov_max: int = 4000
+    proj_mode: int = 0             # original MPM only: 0 particle-quadrature cell mean, 1 analytic
+
+
+@dataclass
+class Particles:
+    x: np.ndarray        # (np, dim)
+    vol: np.ndarray      # (np,)
+    mass: np.ndarray     # (np,)
+    lp: np.ndarray       # (np, dim)   GIMP half-lengths (ignored by original MPM)
+    v0: Optional[np.ndarray] = None   # (np, dim)
+    p0: Optional[np.ndarray] = None   # (np,)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+@dataclass
+class Workload:
+    name: str
+    grid: Grid
+    material: Material
+    options: Options
+    particles: Particles
+    dt: float
+    nsteps: int
+    bc: Callable[[int], Dict[str, np.ndarray]]   # step index (1-based) -> nodal BC arrays
+    meta: Dict = field(default_factory=dict)
+
+
+# ----------------------------------------------------------------------------------------------
+# particles and boundary data
+# ----------------------------------------------------------------------------------------------
+
+def fill_particles(grid: Grid, cell_lo, cell_hi, rho0: float, ppa: int = 2,
+                   jitter: float = 0.0, rng: Optional[np.random.Generator] = None) -> Particles:
+    """Uniform filling of the cell box [cell_lo, cell_hi) with ppa material points per axis
+    per cell at the centres of the ppa^d sub-cells ((1/4, 3/4) h for ppa = 2)."""
+    d, h = grid.dim, grid.h
+    sub = (np.arange(ppa) + 0.5) / ppa
+    axes = []
+    for a in range(d):
+        cells = np.arange(cell_lo[a], cell_hi[a])
+        axes.append(((cells[:, None] + sub[None, :]).reshape(-1)) * h + grid.origin[a])
+    mesh = np.meshgrid(*axes, indexing="ij")
+    x = np.stack([m.transpose(*reversed(range(d))).reshape(-1) for m in mesh], axis=1)
+    if jitter > 0.0:
+        rng = rng if rng is not None else np.random.default_rng(0)
+        x = x + (rng.random(x.shape) - 0.5) * (jitter * h / ppa)
+    n = x.shape[0]
+    v0 = (h / ppa) ** d
+    vol = np.full(n, v0)
+    lp = np.full((n, d), 0.5 * h / ppa)
+    return Particles(x=np.ascontiguousarray(x), vol=vol, mass=rho0 * vol, lp=lp)
+
+
+def empty_bc(grid: Grid) -> Dict[str, np.ndarray]:
+    n, d = grid.nnode, grid.dim
+    return {
+        "u_fixed": np.zeros((n, d), np.uint8),
+        "u_inc": np.zeros((n, d), np.float64),
+        "p_fixed": np.zeros(n, np.uint8),
+        "p_val": np.zeros(n, np.float64),
+        "f_ext": np.zeros((n, d), np.float64),
+        "q_ext": np.zeros(n, np.float64),
+    }
+
+
+def _tol(grid: Grid) -> float:
+    return 1e-9 * grid.h
+
+
+def box_supports(grid: Grid, bc: Dict[str, np.ndarray], xlim: Tuple[float, ...]):
+    """Rollers on every vertical face (normal displacement fixed on nodes at or beyond the face)
+    and a fixed base (all displacement components fixed on nodes at or below the bottom)."""
+    X = grid.node_coords()
+    t = _tol(grid)
+    d = grid.dim
+    for a in range(d - 1):
+        lo = X[:, a] <= grid.origin[a] + t
+        hi = X[:, a] >= xlim[a] - t
+        bc["u_fixed"][lo | hi, a] = 1
+    base = X[:, d - 1] <= grid.origin[d - 1] + t
+    bc["u_fixed"][base, :] = 1
+
+
+# ----------------------------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------------------------
+
+def terzaghi(ncell_x: int = 4, ncell_y: int = 40, h: float = 0.25, load: float = 10e3,
+             k: float = 1e-10, dt: float = 0.1, nsteps: int = 10, tau_scale: float = 1.0,
+             tau_kind: int = TAU_WHITE, model: int = HENCKY, E: float = 10e6, nu: float = 0.3,
+             mu_f: float = 1e-3) -> Workload:
+    """Plane-strain Terzaghi column (Sec. 5.1 set-up): rollers on both sides, fixed base,
+    drained and loaded top, all other faces impermeable, no gravity.  The top edge load w is
+    applied from the first step as consistent nodal forces of a linear edge (w h/2 at the two
+    corners, w h at interior top nodes)."""
+    grid = Grid(2, (ncell_x, ncell_y), h, (0.0, 0.0, 0.0))
+    mat = Material(model=model, E=E, nu=nu, k=k, mu_f=mu_f)
+    opt = Options(shape=LINEAR, dynamic=0, tau_kind=tau_kind, tau_scale=tau_scale)
+    parts = fill_particles(grid, (0, 0), (ncell_x, ncell_y), mat.rho0)
+    H = ncell_y * h
+    W = ncell_x * h
+
+    def bc(step: int):
+        b = empty_bc(grid)
+        box_supports(grid, b, (W,))
+        X = grid.node_coords()
+        top = np.abs(X[:, 1] - H) <= _tol(grid)
+        b["p_fixed"][top] = 1
+        for ix in range(ncell_x + 1):
+            w = h if 0 < ix < ncell_x else 0.5 * h
+            b["f_ext"][grid.node_index(ix, ncell_y), 1] = -load * w
+        return b
+
+    return Workload("terzaghi", grid, mat, opt, parts, dt, nsteps, bc,
+                    meta=dict(H=H, W=W, load=load))
+
+
+def footing2d(nx: int = 64, ny: int = 64, width: float = 10.0, empty_rows: int = 4,
+              half_b: float = 1.0, delta: float = 5e-3, nsteps: int = 100, dt: float = 1e-3,
+              k: float = 1e-16, dynamic: int = 1, shape: int = GIMP, tau_kind: int = TAU_WHITE,
+              model: int = NEO_HOOKEAN, beta: float = 0.25, gamma: float = 0.5,
+              seed: Optional[int] = None, k_range: Optional[Tuple[float, float]] = None,
+              depth: Optional[float] = None, name: str = "footing2d") -> Workload:
+    """Half-model of a rough rigid strip footing pushed down by delta per step.
+
+    Footing reading: at step n the footing base is at y_f = H - (n-1) delta; every node with
+    x <= B/2 and y >= y_f receives the Dirichlet increment (0, -delta).  Sides are rollers, the
+    base is fixed, the top outside the footing (y >= H, x > B/2) is drained, the footing itself
+    is impermeable.  When ``seed`` is given the permeability is drawn once per seed,
+    k = 10^(lo + (hi-lo) u), u ~ U(0,1) from numpy's default_rng(seed)."""
+    h = width / nx
+    depth = depth if depth is not None else ny * h
+    grid = Grid(2, (nx, ny + empty_rows), h, (0.0, 0.0, 0.0))
+    if seed is not None:
+        lo, hi = k_range if k_range is not None else (-14.0, -10.0)
+        u = np.random.default_rng(seed).random()
+        k = 10.0 ** (lo + (hi - lo) * u)
+    mat = Material(model=model, k=k)
+    opt = Options(shape=shape, dynamic=dynamic, beta=beta, gamma=gamma, tau_kind=tau_kind)
+    parts = fill_particles(grid, (0, 0), (nx, ny), mat.rho0)
+    H = ny * h
+    W = nx * h
+    X = grid.node_coords()
+    t = _tol(grid)
+
+    def bc(step: int):
+        b = empty_bc(grid)
+        box_supports(grid, b, (W,))
+        yf = H - (step - 1) * delta
+        foot = (X[:, 0] <= half_b + t) & (X[:, 1] >= yf - t)
+        b["u_fixed"][foot, :] = 1
+        b["u_inc"][foot, 0] = 0.0
+        b["u_inc"][foot, 1] = -delta
+        drained = (X[:, 1] >= H - t) & (X[:, 0] > half_b + t)
+        b["p_fixed"][drained] = 1
+        return b
+
+    return Workload(name, grid, mat, opt, parts, dt, nsteps, bc,
+                    meta=dict(H=H, W=W, half_b=half_b, delta=delta, k=k))
+
+
+def footing3d(n: int = 96, size: float = 12.0, empty_layers: int = 2, half_b: float = 1.0,
+              delta: float = 5e-3, nsteps: int = 20, dt: float = 0.1, k: float = 1e-12,
+              tau_kind: int = TAU_WHITE) -> Workload:
+    """Quarter-model of a rough rigid square footing (quarter 1 m x 1 m) on a cube of side
+    ``size``; trilinear original MPM, quasi-static.  Same footing, drainage and support
+    readings as ``footing2d`` with z vertical."""
+    h = size / n
+    grid = Grid(3, (n, n, n + empty_layers), h, (0.0, 0.0, 0.0))
+    mat = Material(model=NEO_HOOKEAN, k=k)
+    opt = Options(shape=LINEAR, dynamic=0, tau_kind=tau_kind)
+    parts = fill_particles(grid, (0, 0, 0), (n, n, n), mat.rho0)
+    H = n * h
+    X = grid.node_coords()
+    t = _tol(grid)
+
+    def bc(step: int):
+        b = empty_bc(grid)
+        box_supports(grid, b, (size, size))
+        zf = H - (step - 1) * delta
+        foot = (X[:, 0] <= half_b + t) & (X[:, 1] <= half_b + t) & (X[:, 2] >= zf - t)
+        b["u_fixed"][foot, :] = 1
+        b["u_inc"][foot, 2] = -delta
+        drained = (X[:, 2] >= H - t) & ~((X[:, 0] <= half_b + t) & (X[:, 1] <= half_b + t))
+        b["p_fixed"][drained] = 1
+        return b
+
+    return Workload("footing3d", grid, mat, opt, parts, dt, nsteps, bc,
+                    meta=dict(H=H, half_b=half_b, delta=delta, k=k))
+
+
+def consolidation2d(n: int, k: float, width: float = 10.0, load: float = 10e3, nsteps: int = 20,
+                    dt: float = 0.1) -> Workload:
+    """Square n x n consolidation problem (serving stream): original MPM, rollers on the sides,
+    fixed base, uniform top load w on the drained top."""
+    h = width / n
+    grid = Grid(2, (n, n), h, (0.0, 0.0, 0.0))
+    mat = Material(model=NEO_HOOKEAN, k=k)
+    opt = Options(shape=LINEAR, dynamic=0, tau_kind=TAU_WHITE)
+    parts = fill_particles(grid, (0, 0), (n, n), mat.rho0)
+    H = W = n * h
+
+    def bc(step: int):
+        b = empty_bc(grid)
+        box_supports(grid, b, (W,))
+        X = grid.node_coords()
+        top = np.abs(X[:, 1] - H) <= _tol(grid)
+        b["p_fixed"][top] = 1
+        for ix in range(n + 1):
+            w = h if 0 < ix < n else 0.5 * h
+            b["f_ext"][grid.node_index(ix, n), 1] = -load * w
+        return b
+
+    return Workload("consolidation2d", grid, mat, opt, parts, dt, nsteps, bc,
+                    meta=dict(H=H, W=W, load=load, k=k))
+
+
+def jittered_box(nx: int = 8, ny: int = 8, h: float = 0.25, seed: int = 0, shape: int = LINEAR,
+                 dynamic: int = 0, model: int = NEO_HOOKEAN, k: float = 1e-12,
+                 jitter: float = 0.6, empty: int = 1) -> Workload:
+    """Small test problem: a jittered particle block inside a grid with ``empty`` empty cells
+    around it (so GIMP domains stay inside), rollers/base supports on the outer grid faces only
+    where the material touches them (none here), and a downward edge load on the top nodes.
+    Used for assembly and Jacobian checks on irregular particle layouts."""
+    rng = np.random.default_rng(seed)
+    grid = Grid(2, (nx + 2 * empty, ny + 2 * empty), h, (0.0, 0.0, 0.0))
+    mat = Material(model=model, k=k)
+    opt = Options(shape=shape, dynamic=dynamic)
+    parts = fill_particles(grid, (empty, empty), (empty + nx, empty + ny), mat.rho0,
+                           jitter=jitter, rng=rng)
+
+    def bc(step: int):
+        b = empty_bc(grid)
+        X = grid.node_coords()
+        t = _tol(grid)
+        base = X[:, 1] <= empty * h + t
+        b["u_fixed"][base, :] = 1
+        top = np.abs(X[:, 1] - (empty + ny) * h) <= t
+        b["p_fixed"][top] = 1
+        b["f_ext"][top, 1] = -5e3 * h
+        return b
+
+    return Workload("jittered_box", grid, mat, opt, parts, 0.05, 3, bc, meta=dict(seed=seed))
+
+
+# ----------------------------------------------------------------------------------------------
+# the five benchmark configurations
+# ----------------------------------------------------------------------------------------------
+
+def config(idx: int, **kw) -> Workload:
+    """Benchmark configuration by index (1-based, in the order they are listed for this
+    repository's benchmark): 1 Terzaghi, 2 undrained dynamic GIMP footing, 3 large quasi-static
+    GIMP footing, 4 3D footing.  The serving stream (5) is ``serving_trace``."""
+    if idx == 1:
+        return terzaghi(**kw)
+    if idx == 2:
+        args = dict(nx=64, ny=64, width=10.0, empty_rows=4, half_b=1.0, delta=5e-3, nsteps=100,
+                    dt=1e-3, k=1e-16, dynamic=1, shape=GIMP, beta=0.25, gamma=0.5,
+                    name="footing2d_undrained")
+        args.update(kw)
+        return footing2d(**args)
+    if idx == 3:
+        args = dict(nx=512, ny=256, width=32.0, empty_rows=16, half_b=1.0, delta=5e-3,
+                    nsteps=200, dt=0.1, dynamic=0, shape=GIMP, seed=0, k_range=(-14.0, -10.0),
+                    name="footing2d_large")
+        args.update(kw)
+        return footing2d(**args)
+    if idx == 4:
+        return footing3d(**kw)
+    raise ValueError(f"unknown configuration {idx}")
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float
+    kind: str          # "consolidation" or "footing"
+    n: int
+    k: float
+    nsteps: int
+
+    def workload(self) -> Workload:
+        if self.kind == "consolidation":
+            return consolidation2d(self.n, self.k, nsteps=self.nsteps)
+        rows = max(2, int(np.ceil(0.05 * self.n)))
+        return footing2d(nx=self.n, ny=self.n, width=10.0, empty_rows=rows, half_b=1.25,
+                         delta=5e-3, nsteps=self.nsteps, dt=0.1, k=self.k, dynamic=0,
+                         shape=GIMP, name="footing2d_serve")
+
+
+def serving_trace(nreq: int = 256, rate: float = 20.0, n_range=(16, 256),
+                  k_range=(1e-16, 1e-10), steps_range=(20, 50), seed: int = 0) -> List[Request]:
+    """Poisson arrival stream of independent 2D problems: exponential inter-arrival gaps of
+    mean 1/rate, grid n = round(exp(U(ln n_lo, ln n_hi))), k = exp(U(ln k_lo, ln k_hi)),
+    steps ~ U{lo..hi}, kind 50/50 consolidation / footing."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(nreq):
+        t += rng.exponential(1.0 / rate)
+        n = int(round(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1])))))
+        k = float(np.exp(rng.uniform(np.log(k_range[0]), np.log(k_range[1]))))
+        ns = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        kind = "consolidation" if rng.random() < 0.5 else "footing"
+        out.append(Request(i, t, kind, n, k, ns))
+    return out

@@ -1,0 +1,82 @@
+"""Pins of the oracle's constitutive routines (Sec. 2.2): the Hencky model of the paper and the
+neo-Hookean reading.  Checked against finite differences, the small-strain (Hooke) limit,
+objectivity, and the closed form of a uniaxial stretch."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+LAM, G = O.lame(10e6, 0.3)
+
+
+def _rand_F(rng, d, amp=0.3):
+    F = np.eye(d) + amp * (rng.random((d, d)) - 0.5)
+    if np.linalg.det(F) <= 0.2:
+        F = np.eye(d) + 0.1 * (rng.random((d, d)) - 0.5)
+    return F
+
+
+@pytest.mark.parametrize("model,dim", [(0, 2), (1, 2), (1, 3)])
+def test_directional_derivative_vs_fd(model, dim):
+    rng = np.random.default_rng(model * 10 + dim)
+    for _ in range(10):
+        F = _rand_F(rng, dim)
+        L = rng.random((dim, dim)) - 0.5
+        eps = 1e-6
+        Fp = (np.eye(dim) + eps * L) @ F
+        Fm = (np.eye(dim) - eps * L) @ F
+        fd = (O.kirchhoff(model, LAM, G, Fp) - O.kirchhoff(model, LAM, G, Fm)) / (2 * eps)
+        an = O.dkirchhoff(model, LAM, G, F, L)
+        assert np.abs(fd - an).max() <= 1e-6 * np.abs(an).max() + 1e-3
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_small_strain_limit_is_hooke(model):
+    rng = np.random.default_rng(3)
+    eps = 1e-7 * (rng.random((2, 2)) - 0.5)
+    F = np.eye(2) + eps
+    tau = O.kirchhoff(model, LAM, G, F)
+    e = 0.5 * (eps + eps.T)
+    hooke = LAM * np.trace(e) * np.eye(2) + 2 * G * e
+    assert np.abs(tau[:2, :2] - hooke).max() < 1e-6 * np.abs(hooke).max()
+    assert tau[2, 2] == pytest.approx(LAM * np.trace(e), rel=1e-5)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_objectivity(model):
+    rng = np.random.default_rng(11)
+    F = _rand_F(rng, 2)
+    th = 0.7
+    Q = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    t1 = O.kirchhoff(model, LAM, G, Q @ F)[:2, :2]
+    t0 = O.kirchhoff(model, LAM, G, F)[:2, :2]
+    assert np.abs(t1 - Q @ t0 @ Q.T).max() < 1e-8 * np.abs(t0).max()
+
+
+def test_hencky_uniaxial_closed_form():
+    """F = diag(s, 1): tau_xx = (lam + 2G) ln s, tau_yy = tau_zz = lam ln s (log-strain Hooke)."""
+    for s in (0.5, 0.9, 1.3, 2.0):
+        tau = O.kirchhoff(0, LAM, G, np.diag([s, 1.0]))
+        assert tau[0, 0] == pytest.approx((LAM + 2 * G) * np.log(s), rel=1e-13)
+        assert tau[1, 1] == pytest.approx(LAM * np.log(s), rel=1e-13)
+        assert tau[2, 2] == pytest.approx(LAM * np.log(s), rel=1e-13)
+        assert abs(tau[0, 1]) < 1e-6
+
+
+def test_hencky_rotated_stretch():
+    """Stretch along a rotated axis: eigen-decomposition path with distinct eigenvalues."""
+    th = 0.3
+    Q = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    s = 1.4
+    F = Q @ np.diag([s, 1.0]) @ Q.T
+    tau = O.kirchhoff(0, LAM, G, F)[:2, :2]
+    ref = Q @ np.diag([(LAM + 2 * G) * np.log(s), LAM * np.log(s)]) @ Q.T
+    assert np.abs(tau - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_neo_hookean_closed_form():
+    F = np.array([[1.2, 0.1], [0.05, 0.9]])
+    b = F @ F.T
+    J = np.linalg.det(F)
+    tau = O.kirchhoff(1, LAM, G, F)
+    assert np.abs(tau[:2, :2] - (G * (b - np.eye(2)) + LAM * np.log(J) * np.eye(2))).max() < 1e-6

@@ -1,0 +1,97 @@
+"""Pin of the oracle's exact Jacobian (eq. jacobian-system, jacobian-system-stabilized-ppp) against
+central finite differences of its residual, for every term family: quasi-static and Newmark,
+original MPM and GIMP, PPP on and off, Hencky and neo-Hookean, 2D and 3D."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1905_00671_amd import workloads as W
+
+
+def _problem(dim, shape, dynamic, model, tau_kind, seed, g=(0.0, 0.0, 0.0)):
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        grid = W.Grid(2, (4, 4), 0.5, (0.0, 0.0, 0.0))
+        lo, hi = (1, 1), (3, 3)
+    else:
+        grid = W.Grid(3, (3, 3, 3), 0.5, (0.0, 0.0, 0.0))
+        lo, hi = (1, 1, 1), (2, 2, 2)
+    mat = W.Material(model=model, k=1e-9, g=g)
+    opt = W.Options(shape=shape, dynamic=dynamic, beta=0.3025, gamma=0.6, tau_kind=tau_kind)
+    parts = W.fill_particles(grid, lo, hi, mat.rho0, jitter=0.8, rng=rng)
+    pr = O.OracleProblem(grid, mat, opt, parts)
+    # a deformed, pressurized state at t_n
+    n = pr.np
+    pr.F = np.eye(dim)[None] + 0.05 * (rng.random((n, dim, dim)) - 0.5)
+    pr.V = pr.V * np.linalg.det(pr.F)
+    pr.p = 1e4 * rng.random(n)
+    pr.v = 0.1 * (rng.random((n, dim)) - 0.5)
+    pr.a = 2.0 * (rng.random((n, dim)) - 0.5)
+    pr.pd = 1e3 * (rng.random(n) - 0.5)
+    pr.pdd = 1e4 * (rng.random(n) - 0.5)
+    nodal = pr.p2g()
+    nn = grid.nnode
+    U = 2e-3 * (rng.random((nn, dim)) - 0.5) * nodal["active"][:, None]
+    P = nodal["Pn"] + 2e3 * (rng.random(nn) - 0.5) * nodal["active"]
+    return pr, nodal, U, P, rng
+
+
+CASES = [
+    (2, 0, 0, 0, 1), (2, 0, 0, 1, 1), (2, 1, 0, 1, 1), (2, 1, 1, 1, 1), (2, 0, 1, 0, 1),
+    (2, 1, 1, 0, 0), (2, 0, 0, 1, 0), (3, 0, 0, 1, 1), (3, 0, 1, 1, 1), (3, 1, 0, 1, 1),
+]
+
+
+@pytest.mark.parametrize("dim,shape,dynamic,model,tau_kind", CASES)
+def test_jacobian_matches_central_differences(dim, shape, dynamic, model, tau_kind):
+    pr, nodal, U, P, rng = _problem(dim, shape, dynamic, model, tau_kind, seed=dim * 100 + shape * 10 + dynamic,
+                                    g=(0.3, -9.81, 0.0) if dim == 2 else (0.0, 0.2, -9.81))
+    dt = 0.01
+    R, J, _ = pr.assemble(U, P, nodal, dt)
+    nn = pr.grid.nnode
+    act = np.repeat(nodal["active"], dim + 1)
+    Jd = J.toarray()
+    # scale the pressure columns so that an increment of O(1) moves U and P comparably
+    su, spp = 1e-3, 1e3
+    for trial in range(3):
+        dU = su * (rng.random((nn, dim)) - 0.5)
+        dP = spp * (rng.random(nn) - 0.5)
+        vec = np.concatenate([dU, dP[:, None]], axis=1).reshape(-1) * act
+        eps = 1e-5
+        Rp, _, _ = pr.assemble(U + eps * vec.reshape(nn, dim + 1)[:, :dim], P + eps * vec.reshape(nn, dim + 1)[:, dim], nodal, dt, want_J=False)
+        Rm, _, _ = pr.assemble(U - eps * vec.reshape(nn, dim + 1)[:, :dim], P - eps * vec.reshape(nn, dim + 1)[:, dim], nodal, dt, want_J=False)
+        fd = (Rp - Rm) / (2 * eps)
+        an = Jd @ vec
+        # compare each residual block against its own scale
+        for c in range(dim + 1):
+            sel = np.zeros((nn, dim + 1), bool)
+            sel[:, c] = True
+            sel = sel.reshape(-1)
+            scale = np.abs(an[sel]).max() + 1e-300
+            assert np.abs(fd[sel] - an[sel]).max() <= 2e-7 * scale, (c, np.abs(fd[sel] - an[sel]).max(), scale)
+    # the matrix-free product agrees with the assembled matrix
+    _, _, Jv = pr.assemble(U, P, nodal, dt, want_J=False, vin=vec)
+    assert np.abs(Jv - Jd @ vec).max() <= 1e-12 * np.abs(Jv).max()
+
+
+def test_jacobian_columns_small_problem():
+    """Column by column on a tiny GIMP dynamic problem with PPP (every entry checked)."""
+    pr, nodal, U, P, rng = _problem(2, 1, 1, 1, 1, seed=5)
+    dt = 0.02
+    R, J, _ = pr.assemble(U, P, nodal, dt)
+    Jd = J.toarray()
+    nn = pr.grid.nnode
+    act = nodal["active"]
+    for node in np.nonzero(act)[0][::3]:
+        for c in range(3):
+            e = np.zeros((nn, 3))
+            h = 1e-6 if c < 2 else 1e-1
+            e[node, c] = h
+            Rp, _, _ = pr.assemble(U + e[:, :2], P + e[:, 2], nodal, dt, want_J=False)
+            Rm, _, _ = pr.assemble(U - e[:, :2], P - e[:, 2], nodal, dt, want_J=False)
+            col = (Rp - Rm) / (2 * h)
+            ref = Jd[:, node * 3 + c]
+            for r in range(3):
+                a = ref[r::3]
+                b = col[r::3]
+                assert np.abs(a - b).max() <= 1e-6 * (np.abs(a).max() + np.abs(Jd[r::3]).max() * 1e-6)
