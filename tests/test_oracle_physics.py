@@ -253,3 +253,34 @@ def test_ppp_vanishes_with_one_point_per_cell():
     so the stabilization term vanishes identically (the motivation of Sec. 4.4)."""
     C = _stab_matrix(0, 1)
     assert np.abs(C).max() == 0.0
+
+
+def test_free_fall_newmark_closed_form():
+    """Free fall of an unsupported body from rest with zero initial acceleration, Newmark with the
+    paper's beta = 0.3025, gamma = 0.6 (Sec. 3.2): the momentum balance gives a = g at every
+    step, so the scalar Newmark recursion u += dt v + dt^2((1/2 - beta) a_n + beta a),
+    v += dt((1 - gamma) a_n + gamma a) is the exact discrete answer (FLIP update of Sec. 3.5);
+    the pore pressure and the effective stress stay zero (a = a_f, Sec. 2.1)."""
+    for shape in (0, 1):
+        grid = W.Grid(2, (12, 12), 0.25, (0.0, 0.0, 0.0))
+        gvec = np.array([0.0, -9.81])
+        mat = W.Material(model=W.NEO_HOOKEAN, k=1e-12, g=(0.0, -9.81, 0.0))
+        opt = W.Options(shape=shape, dynamic=1, beta=0.3025, gamma=0.6, tau_kind=W.TAU_WHITE)
+        parts = W.fill_particles(grid, (3, 5), (8, 9), mat.rho0)
+        v0 = np.array([0.2, 0.5])
+        parts.v0 = np.tile(v0, (parts.n, 1))
+        pr = O.OracleProblem(grid, mat, opt, parts)
+        dt, be, ga = 0.02, 0.3025, 0.6
+        u = np.zeros(2); v = v0.copy(); a = np.zeros(2)
+        bc = W.empty_bc(grid)
+        for n in range(1, 6):
+            pr.step(dt, bc, rtol=1e-12)
+            u = u + dt * v + dt * dt * ((0.5 - be) * a + be * gvec)
+            v = v + dt * ((1 - ga) * a + ga * gvec)
+            a = gvec.copy()
+        assert np.abs(pr.u - u).max() < 1e-10
+        assert np.abs(pr.v - v).max() < 1e-9
+        assert np.abs(pr.a - gvec).max() < 1e-8
+        # rounding level against the hydrostatic scale rho g h = 5e3 Pa
+        assert np.abs(pr.p).max() < 1e-4
+        assert np.abs(pr.sig).max() < 1e-4
