@@ -1,0 +1,215 @@
+/*
+ * ppmpm.h -- C ABI of libppmpm.so: the per-step hot path of the stabilized implicit material
+ * point method for coupled large-deformation poromechanics (Zhao & Choo, arXiv 1905.00671),
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the problem statement of Sec. 2.4 (given boundary data u^, t^, p^, q^ and
+ * initial u0, p0, find u and p) and the four-stage MPM step of Sec. 3.1: material points, a
+ * fixed background grid, boundary conditions and a time step go in; the updated material-point
+ * state comes out.
+ *
+ * Conventions shared by every call
+ *   - Every function returns a ppmpm_status; ppmpm_last_error() returns a thread-local message
+ *     describing the last failure.  No C++ exception or ownership crosses the ABI.
+ *   - dim is 2 (plane strain) or 3.  Grid nodes are numbered ix + nx1*(iy + ny1*iz) with
+ *     nx1 = ncell[0] + 1 etc. ("natural order").  Particle arrays are row-major: x[np*dim],
+ *     F[np*dim*dim], ... in the caller's particle order, which the library preserves on output
+ *     (it sorts particles internally).
+ *   - `where` = PPMPM_HOST or PPMPM_DEVICE says whether a caller pointer is host memory or
+ *     device memory of the problem's GPU.  The caller owns every array it passes; the library
+ *     copies inputs into its workspace and never frees caller memory.
+ *   - All device work is enqueued on the caller's HIP stream (hipStream_t passed as void*).
+ *     ppmpm_step returns after its statistics are available (it synchronizes the stream once
+ *     per Newton iteration and a few times per Krylov solve).
+ *   - A problem is not thread-safe.  Problems stepped together by ppmpm_step_batched must share
+ *     the stream of the first problem of the batch.
+ */
+#ifndef PPMPM_H
+#define PPMPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ppmpm_problem ppmpm_problem; /* opaque */
+
+typedef enum {
+    PPMPM_OK = 0,
+    PPMPM_E_INVALID = 1,     /* bad argument, unsupported combination, wrong call order */
+    PPMPM_E_OOM = 2,         /* workspace smaller than ppmpm_workspace_bytes */
+    PPMPM_E_DEVICE = 3,      /* a HIP runtime call failed */
+    PPMPM_E_NEWTON = 4,      /* Newton did not converge within newton_max iterations */
+    PPMPM_E_KRYLOV = 5,      /* Krylov breakdown (reported in the statistics, not fatal) */
+    PPMPM_E_NONFINITE = 6,   /* non-finite residual or an inverted material point (det dF <= 0) */
+    PPMPM_E_OUT_OF_GRID = 7  /* a material point left the background grid */
+} ppmpm_status;
+
+enum { PPMPM_HOST = 0, PPMPM_DEVICE = 1 };
+enum { PPMPM_LINEAR = 0, PPMPM_GIMP = 1 };              /* basis, Sec. 3.1 */
+enum { PPMPM_HENCKY = 0, PPMPM_NEO_HOOKEAN = 1 };       /* skeleton, Sec. 2.2 */
+enum { PPMPM_TAU_OFF = 0, PPMPM_TAU_WHITE = 1, PPMPM_TAU_SUN = 2, PPMPM_TAU_MONFORTE = 3 }; /* Sec. 4.3 */
+enum { PPMPM_FP64 = 0, PPMPM_MIXED = 1 };
+
+/* Fixed background grid (the mesh is never moved, Sec. 3.5).  Cells are squares/cubes of edge h;
+ * the grid spans origin .. origin + ncell*h on every axis. */
+typedef struct {
+    int dim;
+    int ncell[3];
+    double h;
+    double origin[3];
+} ppmpm_grid;
+
+/* Constants of Sec. 2: E, nu of the skeleton (Lame parameters derived from them), intrinsic
+ * permeability k and fluid viscosity mu_f (mobility k/mu_f of the Darcy law), intrinsic fluid
+ * density, gravity.  model: PPMPM_HENCKY (plane strain only) or PPMPM_NEO_HOOKEAN
+ * (tau' = G (b - 1) + lambda ln J 1). */
+typedef struct {
+    int model;
+    double E, nu, k, mu_f, rho_f;
+    double g[3];
+} ppmpm_material;
+
+/* Method options.
+ *   shape            PPMPM_LINEAR (original MPM) or PPMPM_GIMP (2D only)
+ *   dynamic          0: quasi-static, implicit Euler (eq. implicit-euler);
+ *                    1: Newmark (eq. newmark) with beta, gamma
+ *   tau_kind/scale   stabilization parameter of the PPP term (eq. tau-white/sun/monforte) times scale
+ *   precision        PPMPM_FP64, or PPMPM_MIXED: FP32 Jacobian, SpMV, preconditioner and Krylov
+ *                    vectors; FP64 residual, projection and Newton update
+ *   newton_rtol      relative residual reduction required of each residual block (momentum,
+ *                    mass; eq. newton-tolerance applied block-wise); newton_atol_u/p are
+ *                    absolute floors (<= 0: 1e-12 E h^(dim-1) and 1e-12 h^dim/dt)
+ *   newton_max       Newton iterations before PPMPM_E_NEWTON
+ *   krylov_rtol      BiCGStab stops at ||r|| <= krylov_rtol ||R^k||; krylov_max caps iterations
+ *   krylov_check     iterations between host checks of the convergence flag (>= 1)
+ *   mg_smooth        pre/post smoothing sweeps of each multigrid V-cycle (>= 1)
+ */
+typedef struct {
+    int shape;
+    int dynamic;
+    double beta, gamma;
+    int tau_kind;
+    double tau_scale;
+    int precision;
+    double newton_rtol, newton_atol_u, newton_atol_p;
+    int newton_max;
+    double krylov_rtol;
+    int krylov_max;
+    int krylov_check;
+    int mg_smooth;
+} ppmpm_options;
+
+/* Boundary data of one step on the grid nodes (natural order).
+ *   u_fixed[nnode*dim] (0/1)  Dirichlet displacement components; u_inc their prescribed
+ *                             increment over the step (the grid unknown is the incremental
+ *                             displacement, the grid being reset every step, Sec. 3.1)
+ *   p_fixed[nnode], p_val     Dirichlet pore pressure p^ at the end of the step
+ *   f_ext[nnode*dim]          nodal external forces (integrated traction t^)
+ *   q_ext[nnode]              nodal inflow (integrated flux q^ = -n.q)
+ * Any pointer may be NULL (no condition / zero).  Conditions on inactive nodes (no material
+ * point support) are ignored. */
+typedef struct {
+    const uint8_t* u_fixed;
+    const double* u_inc;
+    const uint8_t* p_fixed;
+    const double* p_val;
+    const double* f_ext;
+    const double* q_ext;
+    int where;
+} ppmpm_bc;
+
+#define PPMPM_MAX_HIST 64
+/* Per-step statistics.  res_u/res_p: L2 norms of the momentum and mass residual blocks at each
+ * Newton iteration (free degrees of freedom only); krylov_iters per Newton iteration; times in
+ * seconds measured on the host around the synchronized phases. */
+typedef struct {
+    int status;
+    int newton_iters;
+    int converged;
+    int krylov_total;
+    int krylov_iters[PPMPM_MAX_HIST];
+    double res_u[PPMPM_MAX_HIST];
+    double res_p[PPMPM_MAX_HIST];
+    double t_sort, t_assemble, t_precond, t_krylov, t_g2p, t_total;
+    int krylov_breakdowns;
+    int ngrid_levels;
+} ppmpm_step_stats;
+
+/* Device bytes of workspace a problem with this grid, particle count and options needs.
+ * Admission control (serving) compares this against free HBM. Returns 0 on invalid input. */
+size_t ppmpm_workspace_bytes(const ppmpm_grid* grid, int64_t np, const ppmpm_options* opt);
+
+/* Creates a problem on the current HIP device.  `workspace` is caller-allocated device memory
+ * of at least ppmpm_workspace_bytes bytes, 256-byte aligned, kept alive until ppmpm_destroy;
+ * `hip_stream` is the stream all work of the problem is enqueued on.  The library performs no
+ * device allocation of its own.  Errors: PPMPM_E_INVALID (bad sizes, GIMP in 3D, Hencky in 3D),
+ * PPMPM_E_OOM (workspace too small). */
+ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat,
+                          const ppmpm_options* opt, void* workspace, size_t ws_bytes,
+                          void* hip_stream, int64_t np, ppmpm_problem** out);
+
+/* Initial material-point state (Sec. 2.4 initial conditions): positions x[np*dim], volumes
+ * vol[np], masses mass[np], GIMP half-lengths lp[np*dim] (NULL: h/4), initial velocities
+ * v0[np*dim] (NULL: 0) and pore pressures p0[np] (NULL: 0).  F = 1, u = 0.  np must equal the
+ * count given to ppmpm_create.  PPMPM_E_OUT_OF_GRID if a point lies outside the grid. */
+ppmpm_status ppmpm_set_particles(ppmpm_problem* p, int64_t np, const double* x, const double* vol,
+                                 const double* mass, const double* lp, const double* v0,
+                                 const double* p0, int where);
+
+/* One implicit time step of length dt (Stages 1-4 of Sec. 3.1): counting sort of the points into
+ * cells, lumped P2G, Newton iterations (residual and fixed-stencil block-CSR Jacobian with the
+ * PPP term; BiCGStab with the block upper-triangular preconditioner), G2P update.  The step is
+ * transactional: on PPMPM_E_NEWTON, PPMPM_E_NONFINITE or PPMPM_E_OUT_OF_GRID the material-point
+ * state is left unchanged and the caller may retry (e.g. with a smaller dt).  stats may be NULL. */
+ppmpm_status ppmpm_step(ppmpm_problem* p, double dt, const ppmpm_bc* bc, ppmpm_step_stats* stats);
+
+/* Steps nprob problems together: one kernel launch per phase over all problems that share a
+ * kernel variant (dimension, basis, precision), each problem converging independently.
+ * dt[nprob], bcs[nprob], stats[nprob] (per-problem status in stats[i].status).  Returns
+ * PPMPM_OK if every problem succeeded, otherwise the first failing status; a failing problem
+ * does not affect the others. */
+ppmpm_status ppmpm_step_batched(ppmpm_problem* const* probs, int nprob, const double* dt,
+                                const ppmpm_bc* const* bcs, ppmpm_step_stats* stats);
+
+/* Material-point fields, caller's order. */
+enum {
+    PPMPM_FIELD_X = 0,     /* position        [np*dim] */
+    PPMPM_FIELD_U = 1,     /* displacement    [np*dim] accumulated since the start */
+    PPMPM_FIELD_P = 2,     /* pore pressure   [np] */
+    PPMPM_FIELD_F = 3,     /* deformation gradient [np*dim*dim] */
+    PPMPM_FIELD_VOL = 4,   /* volume          [np] */
+    PPMPM_FIELD_SIG = 5,   /* effective Cauchy stress [np*9] full 3x3 */
+    PPMPM_FIELD_V = 6,     /* velocity        [np*dim] */
+    PPMPM_FIELD_A = 7,     /* acceleration    [np*dim] */
+    PPMPM_FIELD_PD = 8,    /* pdot            [np] */
+    PPMPM_FIELD_PDD = 9,   /* pddot           [np] */
+    PPMPM_FIELD_LP = 10    /* GIMP half-lengths [np*dim] */
+};
+ppmpm_status ppmpm_get_field(const ppmpm_problem* p, int field, double* out, int where);
+
+/* Inspection of one Newton iterate, for verification.  Performs Stage 1 (sort, P2G) for the
+ * current state with boundary data bc and step dt, then evaluates the residual and assembles the
+ * Jacobian at the nodal state U[nnode*dim], P[nnode] (natural order).  R[nnode*(dim+1)] receives
+ * the residual (node-interleaved [u..., p]) with non-free degrees of freedom set to zero.  The
+ * Jacobian stays in the workspace for ppmpm_apply_jacobian. */
+ppmpm_status ppmpm_eval_residual(ppmpm_problem* p, double dt, const ppmpm_bc* bc, const double* U,
+                                 const double* P, double* R, int where);
+
+/* y = J v with the Jacobian of the last ppmpm_eval_residual (non-free rows act as identity);
+ * v, y are [nnode*(dim+1)] node-interleaved. */
+ppmpm_status ppmpm_apply_jacobian(ppmpm_problem* p, const double* v, double* y, int where);
+
+/* Nodal fields of the last Stage 1 (natural order): 0 lumped mass M, 1 P_n, 2 free-dof mask as
+ * doubles [nnode*(dim+1)]. */
+ppmpm_status ppmpm_get_nodal(const ppmpm_problem* p, int field, double* out, int where);
+
+ppmpm_status ppmpm_destroy(ppmpm_problem* p);
+const char* ppmpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

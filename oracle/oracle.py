@@ -261,7 +261,8 @@ class OracleProblem:
         fext = fext.reshape(-1)
         scale_u = self.mat.E * g.h ** (d - 1)
         scale_p = g.h ** d / dt
-        atol_u, atol_p = 1e-12 * scale_u, 1e-12 * scale_p
+        atol_u = self.opt.newton_atol_u if self.opt.newton_atol_u > 0 else 1e-12 * scale_u
+        atol_p = self.opt.newton_atol_p if self.opt.newton_atol_p > 0 else 1e-12 * scale_p
         hist = []
         t_asm = t_sol = 0.0
         umask = np.zeros((nn, d + 1), bool)

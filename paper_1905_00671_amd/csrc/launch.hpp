@@ -1,0 +1,68 @@
+// Host-side launch helpers shared by the kernel files and the runtime of libppmpm.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <initializer_list>
+#include <vector>
+
+#include "ppmpm_internal.hpp"
+
+namespace ppm {
+
+// Problems of one kernel variant stepped together, with their per-problem work sizes.
+struct Group {
+    int dim = 2, shape = 0, mixed = 0, S = 9, b = 3;
+    std::vector<const Dev*> ddev;   // device descriptors
+    std::vector<int64_t> np, nnode, ncell, ncell1, npadb, npad;
+};
+
+// Blocks of `tpb` threads covering work[q] items for every problem q.
+inline Batch make_batch(const std::vector<const Dev*>& dd, const std::vector<int64_t>& work, int tpb) {
+    Batch B{};
+    B.n = (int)dd.size();
+    B.pfx[0] = 0;
+    for (int q = 0; q < B.n; ++q) {
+        int64_t nb = (work[q] + tpb - 1) / tpb;
+        if (nb < 1) nb = 1;
+        B.pfx[q + 1] = B.pfx[q] + (int)nb;
+        B.d[q] = dd[q];
+    }
+    return B;
+}
+
+inline Batch make_batch_one_block(const std::vector<const Dev*>& dd) {
+    Batch B{};
+    B.n = (int)dd.size();
+    for (int q = 0; q <= B.n; ++q) B.pfx[q] = q;
+    for (int q = 0; q < B.n; ++q) B.d[q] = dd[q];
+    return B;
+}
+
+// kern_particles.hip
+void launch_set_particles(const Dev* dd, int64_t np, const double* x, const double* vol, const double* mass,
+                          const double* lp, const double* v0, const double* p0, hipStream_t st);
+void launch_get_field(const Dev* dd, int64_t np, int field, int ncomp, double* out, hipStream_t st);
+void launch_sort(const Group& g, hipStream_t st);
+void launch_bc(const Dev* dd, int64_t nnode, const uint8_t* uf, const double* ui, const uint8_t* pf,
+               const double* pv, const double* fe, const double* qe, hipStream_t st);
+void launch_p2g(const Group& g, hipStream_t st);
+void launch_cell_proj(const Group& g, hipStream_t st);
+void launch_g2p(const Group& g, hipStream_t st);
+
+// kern_assemble.hip
+void launch_assemble(const Group& g, bool want_J, hipStream_t st);
+
+// kern_solver.hip
+void launch_jacobian(const Group& g, hipStream_t st);
+void launch_precond_setup(const Group& g, const std::vector<const Dev*>& host_copies, hipStream_t st);
+void launch_krylov_init(const Group& g, double rtol, int maxit, hipStream_t st);
+void launch_krylov_iters(const Group& g, const std::vector<const Dev*>& host_copies, int iters, double rtol,
+                         int maxit, hipStream_t st);
+void launch_newton_update(const Group& g, hipStream_t st);
+void launch_apply_jacobian(const Dev* dd, const Dev* hd, const double* v_nat, double* y_nat, hipStream_t st);
+void launch_nodal_out(const Dev* dd, const Dev* hd, int field, double* out, hipStream_t st);
+void launch_residual_out(const Dev* dd, const Dev* hd, double* out, hipStream_t st);
+void launch_set_state(const Dev* dd, const Dev* hd, const double* U, const double* P, hipStream_t st);
+
+}  // namespace ppm

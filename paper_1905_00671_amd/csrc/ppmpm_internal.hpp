@@ -1,0 +1,347 @@
+// Internal declarations of libppmpm: the device-side problem descriptor, memory layouts and
+// the device functions shared by the kernels (basis functions of Sec. 3.1, constitutive laws of
+// Sec. 2.2).  Nothing here is part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppm {
+
+constexpr int MAXB = 64;      // problems per batched launch
+constexpr int TPB = 256;      // threads per block of the streaming kernels
+constexpr int MAXLEV = 12;    // multigrid levels
+constexpr int CMAX = 256;     // largest coarsest-level system solved by a dense inverse
+
+// Particle state, structure of arrays: field f, component c of particle i lives at
+// base[(f + c) * stride + i].  Every variant uses the same slots (2D leaves some unused).
+enum PField : int {
+    PX = 0,      // position (3)
+    PF = 3,      // deformation gradient, row-major dim x dim (9)
+    PV = 12,     // current volume V_n
+    PM = 13,     // mass
+    PP = 14,     // pore pressure
+    PU = 15,     // accumulated displacement (3)
+    PLP = 18,    // GIMP half-lengths (3)
+    PLP0 = 21,   // initial GIMP half-lengths (3)
+    PVEL = 24,   // velocity (3)
+    PACC = 27,   // acceleration (3)
+    PPD = 30,    // pdot
+    PPDD = 31,   // pddot
+    PSIG = 32,   // effective Cauchy stress xx yy zz xy yz xz (6)
+    NPF = 38
+};
+
+// Error flags (device int array, one slot per meaning)
+enum Flag : int { FL_INVERTED = 0, FL_OUTSIDE = 1, FL_NONFINITE = 2, FL_BOUNDS = 3, NFLAG = 4 };
+
+// Scalars of one problem (device double array)
+enum Scal : int {
+    SC_RU2 = 0,      // ||R_u||^2
+    SC_RP2 = 1,      // ||R_p||^2
+    SC_RHO = 2,      // BiCGStab rho
+    SC_ALPHA = 3,
+    SC_OMEGA = 4,
+    SC_BETA = 5,
+    SC_RR = 6,       // ||r||^2
+    SC_TOL2 = 7,     // (krylov tol * ||b||)^2
+    SC_RV = 8,       // (rhat, v)
+    SC_TS = 9,       // (t, s)
+    SC_TT = 10,      // (t, t)
+    SC_ITER = 11,    // iterations done (as double)
+    SC_DONE = 12,    // 1 when converged or broken down
+    SC_BREAK = 13,   // 1 on breakdown
+    NSCAL = 16
+};
+
+struct MgLevel {
+    int n[3];            // nodes per axis
+    int np[3];           // padded nodes per axis
+    int64_t nrow;        // prod n
+    int64_t npad;        // prod np
+    // operator of family A (block B = dim) and family S (block 1) on this level; level 0 uses
+    // views into the Jacobian instead (null here)
+    void* A;             // [S][dim][dim][nrow], T
+    void* Ad;            // inverse diagonal blocks [dim*dim][nrow], T
+    void* Sm;            // [S][nrow], T
+    void* Sd;            // [nrow], T
+    void* xa; void* ra; void* ba;   // family A: solution, residual, right-hand side [npad*dim]
+    void* xs; void* rs; void* bsv;  // family S: solution, residual, right-hand side [npad]
+};
+
+// Device-side descriptor of one problem.  Lives in the problem's workspace; kernels of a batch
+// receive pointers to the descriptors of all its problems.
+struct Dev {
+    int dim, shape, dyn, mixed, model;
+    int R;        // stencil radius (= grid padding): 1 original MPM, 2 GIMP
+    int W;        // basis nodes per axis and particle: 2 original MPM, 3 GIMP
+    int S;        // stencil points (2R+1)^dim
+    int b;        // dofs per node dim+1
+    int nc[3];    // cells per axis
+    int nn[3];    // real nodes per axis
+    int np1[3];   // padded nodes per axis
+    int64_t Np, Ncell, Nnode, Npad;
+    double h, x0[3], hi[3];
+    double lam, G, kappa, rho_f, g[3];
+    // per-step parameters
+    double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
+    int nlev;
+    int mg_nsm;
+    // particles
+    double* pc;   // committed state
+    double* pw;   // working copy of the step (sorted)
+    int* idc;
+    int* idw;
+    int64_t ps;   // particle stride (= Np)
+    // counting sort
+    int* key;
+    int* slot;
+    int* ccount;  // [Ncell + 1]
+    int* cstart;  // [Ncell + 1]
+    int* order;   // [Np]
+    // nodal fields on the padded grid
+    double* M;
+    double* Pn;
+    double* vn;   // [Npad*3]
+    double* an;   // [Npad*3]
+    double* pdn;
+    double* pddn;
+    double* Mp;   // lumped pressure mass sum V_n S (fixed-stress Schur approximation)
+    uint8_t* dfree;   // [Npad*b] 1 = free dof
+    uint8_t* bcfix;   // [Npad*b]
+    double* bcval;    // [Npad*b] u increment / p value
+    double* fext;     // [Npad*b] f_ext, -q_ext
+    double* X;        // [Npad*b] Newton iterate U, P
+    double* Rv;       // [Npad*b] residual
+    double* cellpi;   // [Ncell * 2^dim] original-MPM projection Pi N
+    // quadrature-point records
+    double* rec;      // [NREC][Np]
+    int* rbase;       // [dim][Np] window base node per axis
+    // Jacobian, fixed stencil block rows: J[((s*b + a)*b + c)*Nnode + row], precision T
+    void* J;
+    // Krylov vectors [Npad*b], precision T
+    void* kx; void* kr; void* kh; void* kp; void* kv; void* ks; void* kt; void* kph; void* ksh;
+    void* kbt;        // [Npad*dim] rhs of the A cycle (r_u - B1 z_p)
+    // multigrid hierarchy
+    MgLevel lev[MAXLEV];
+    void* cinvA;      // dense inverse of the coarsest A [nA*nA], precision T
+    void* cinvS;      // dense inverse of the coarsest S [nS*nS], precision T
+    double* cwork;    // FP64 Gauss-Jordan work matrix [CMAX*CMAX]
+    // reductions
+    double* partial;  // [maxblocks * 4]
+    double* scal;     // [NSCAL]
+    int* flags;       // [NFLAG]
+    int64_t maxblocks;
+};
+
+// Batch of problems of one kernel variant, passed by value to every kernel.
+struct Batch {
+    int n;
+    int pfx[MAXB + 1];         // block prefix: problem q owns blocks [pfx[q], pfx[q+1])
+    const Dev* d[MAXB];
+};
+
+__device__ __forceinline__ int batch_find(const Batch& B, int blk) {
+    // problems are few: linear scan on uniform data
+    int q = 0;
+    while (q + 1 < B.n && blk >= B.pfx[q + 1]) ++q;
+    return q;
+}
+
+// ------------------------------------------------------------------------------------------------
+// record layout (quadrature-point data written once per Newton iteration)
+// ------------------------------------------------------------------------------------------------
+template <int DIM, int WB>
+struct RecLayout {
+    static constexpr int W_ = 0;                      // 1D weights [DIM][WB]
+    static constexpr int DW_ = W_ + DIM * WB;          // 1D gradients [DIM][WB]
+    static constexpr int S0_ = DW_ + DIM * WB;         // GIMP constant basis [DIM][WB]
+    static constexpr int FI_ = S0_ + DIM * WB;         // dF^{-1} [DIM*DIM]
+    static constexpr int AB_ = FI_ + DIM * DIM;        // tangent Abar [DIM^4]
+    static constexpr int DV_ = AB_ + DIM * DIM * DIM * DIM;   // dv
+    static constexpr int CM_ = DV_ + 1;                // m / (beta dt^2)
+    static constexpr int BV_ = CM_ + 1;                // volumetric coupling coefficient
+    static constexpr int LV_ = BV_ + 1;                // dv * velocity gradient [DIM*DIM]
+    static constexpr int DK_ = LV_ + DIM * DIM;        // dv kappa
+    static constexpr int GP_ = DK_ + 1;                // grad p [DIM]
+    static constexpr int QW_ = GP_ + DIM;              // w = grad p - rho_f (g - a) [DIM]
+    static constexpr int EE_ = QW_ + DIM;              // dv kappa rho_f / (beta dt^2)
+    static constexpr int TC_ = EE_ + 1;                // tau c_t V_n
+    static constexpr int SG_ = TC_ + 1;                // -V0 tau' + dv p 1 [DIM*DIM]
+    static constexpr int BF_ = SG_ + DIM * DIM;        // m (g - a) [DIM]
+    static constexpr int DT_ = BF_ + DIM;              // dv theta
+    static constexpr int ST_ = DT_ + 1;                // tau V_n (pdot - Pi pdot)
+    static constexpr int N = ST_ + 1;
+};
+
+// ------------------------------------------------------------------------------------------------
+// basis functions (Sec. 3.1)
+// ------------------------------------------------------------------------------------------------
+
+// Antiderivative of the unit hat of half-width h, int_{-inf}^{r} N: clamp-based form.
+__device__ __forceinline__ double hat_prim(double r, double h) {
+    double c = fmin(fmax(r, -h), h);
+    return 0.5 * h + c - c * fabs(c) / (2.0 * h);
+}
+__device__ __forceinline__ double hat_val(double r, double h) { return fmax(0.0, 1.0 - fabs(r) / h); }
+
+// 1D basis of one particle along one axis.  Original MPM: the two nodes of the containing cell
+// (clamped), hat weights.  GIMP: the domain [x-lp, x+lp] clipped to the grid, three nodes from
+// the one at or left of its lower end; weight = domain average of the hat, gradient = domain
+// average of its derivative (= (N(b) - N(a)) / |[a,b]|), constant basis S0 = half the share of
+// the domain inside the node's support.
+template <int SHAPE>
+__device__ __forceinline__ int basis_1d(double x, double lp, double x0, double h, int nc, double* w,
+                                        double* dw, double* s0) {
+    if (SHAPE == 0) {
+        int c = (int)floor((x - x0) / h);
+        c = c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+        double xi = (x - (x0 + h * c)) / h;
+        w[0] = 1.0 - xi;
+        w[1] = xi;
+        dw[0] = -1.0 / h;
+        dw[1] = 1.0 / h;
+        s0[0] = s0[1] = 0.5;
+        return c;
+    } else {
+        double lo = x0, hi = x0 + h * nc;
+        double a = fmax(x - lp, lo), bb = fmin(x + lp, hi);
+        double len = bb - a;
+        int base = (int)floor((a - x0) / h);
+        base = base < 0 ? 0 : (base > nc - 1 ? nc - 1 : base);
+        for (int k = 0; k < 3; ++k) {
+            double xn = x0 + h * (base + k);
+            w[k] = (hat_prim(bb - xn, h) - hat_prim(a - xn, h)) / len;
+            dw[k] = (hat_val(bb - xn, h) - hat_val(a - xn, h)) / len;
+            double ov = fmin(bb, xn + h) - fmax(a, xn - h);
+            s0[k] = ov > 0.0 ? 0.5 * ov / len : 0.0;
+        }
+        return base;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// small dense helpers
+// ------------------------------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ double det(const double* A) {
+    if (D == 2) return A[0] * A[3] - A[1] * A[2];
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+template <int D>
+__device__ __forceinline__ void inverse(const double* A, double* B) {
+    double id = 1.0 / det<D>(A);
+    if (D == 2) {
+        B[0] = A[3] * id; B[1] = -A[1] * id; B[2] = -A[2] * id; B[3] = A[0] * id;
+    } else {
+        B[0] = (A[4] * A[8] - A[5] * A[7]) * id;
+        B[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+        B[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+        B[3] = (A[5] * A[6] - A[3] * A[8]) * id;
+        B[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+        B[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+        B[6] = (A[3] * A[7] - A[4] * A[6]) * id;
+        B[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+        B[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+    }
+}
+
+// (ln x - ln y)/(x - y) for positive x, y, continuous across x = y.
+__device__ __forceinline__ double log_divdiff(double x, double y) {
+    double t = (x - y) / y;
+    if (fabs(t) < 1e-4) {
+        // log1p(t)/t = 1 - t/2 + t^2/3 - t^3/4 + t^4/5
+        return (1.0 + t * (-0.5 + t * (1.0 / 3.0 + t * (-0.25 + t * 0.2)))) / y;
+    }
+    return log1p(t) / (x - y);
+}
+
+// Effective Kirchhoff stress tau' (full DIM x DIM block, plus tau'_zz in plane strain) and the
+// tangent T with d tau' = T : L for dF -> (1 + L) dF (L = d(grad u) in the current configuration):
+//   neo-Hookean: tau' = G (b - 1) + lam ln J 1,   T_abef = G (d_ae b_fb + b_af d_be) + lam d_ab d_ef
+//   Hencky:      tau' = lam ln J 1 + G ln b,      T = lam 1(x)1 + G D(ln b)[L b + b L^T]
+// (the Hencky derivative by the Daleckii-Krein formula in the eigenframe of b; plane strain only).
+template <int D>
+__device__ __forceinline__ void kirchhoff_tangent(int model, double lam, double G, const double* F,
+                                                  double* tau, double* tauzz, double* T) {
+    double b[9];
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < D; ++k) s += F[i * D + k] * F[j * D + k];
+            b[i * D + j] = s;
+        }
+    double lnJ = log(det<D>(F));
+    if (model == 1 || D == 3) {
+        for (int i = 0; i < D * D; ++i) tau[i] = G * b[i];
+        for (int i = 0; i < D; ++i) tau[i * D + i] += lam * lnJ - G;
+        *tauzz = lam * lnJ;
+        if (T) {
+            for (int a = 0; a < D; ++a)
+                for (int bb = 0; bb < D; ++bb)
+                    for (int e = 0; e < D; ++e)
+                        for (int f = 0; f < D; ++f) {
+                            double v = 0.0;
+                            if (a == e) v += G * b[f * D + bb];
+                            if (bb == e) v += G * b[a * D + f];
+                            if (a == bb && e == f) v += lam;
+                            T[((a * D + bb) * D + e) * D + f] = v;
+                        }
+        }
+        return;
+    }
+    // Hencky, 2x2: principal frame of b by the half angle
+    double th = 0.5 * atan2(2.0 * b[1], b[0] - b[3]);
+    double cs = cos(th), sn = sin(th);
+    double Q[4] = {cs, -sn, sn, cs};   // columns: n1 = (cs, sn), n2 = (-sn, cs)
+    double l1 = b[0] * cs * cs + 2.0 * b[1] * cs * sn + b[3] * sn * sn;
+    double l2 = b[0] * sn * sn - 2.0 * b[1] * cs * sn + b[3] * cs * cs;
+    double e1 = log(l1), e2 = log(l2);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            tau[i * 2 + j] = G * (Q[i * 2] * e1 * Q[j * 2] + Q[i * 2 + 1] * e2 * Q[j * 2 + 1]) +
+                             (i == j ? lam * lnJ : 0.0);
+    *tauzz = lam * lnJ;
+    if (!T) return;
+    double ev[2] = {l1, l2};
+    double gdd[4];
+    gdd[0] = 1.0 / l1;
+    gdd[3] = 1.0 / l2;
+    gdd[1] = gdd[2] = log_divdiff(l1, l2);
+    // eigenframe tangent T'_ABEF = lam d_AB d_EF + G g_AB (l_B d_AE d_BF + l_A d_BE d_AF)
+    double Tp[16];
+    for (int A = 0; A < 2; ++A)
+        for (int Bq = 0; Bq < 2; ++Bq)
+            for (int E = 0; E < 2; ++E)
+                for (int Fq = 0; Fq < 2; ++Fq) {
+                    double v = (A == Bq && E == Fq) ? lam : 0.0;
+                    double gg = gdd[A * 2 + Bq];
+                    if (A == E && Bq == Fq) v += G * gg * ev[Bq];
+                    if (Bq == E && A == Fq) v += G * gg * ev[A];
+                    Tp[((A * 2 + Bq) * 2 + E) * 2 + Fq] = v;
+                }
+    for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb)
+            for (int e = 0; e < 2; ++e)
+                for (int f = 0; f < 2; ++f) {
+                    double v = 0.0;
+                    for (int A = 0; A < 2; ++A)
+                        for (int Bq = 0; Bq < 2; ++Bq) {
+                            double qab = Q[a * 2 + A] * Q[bb * 2 + Bq];
+                            for (int E = 0; E < 2; ++E)
+                                for (int Fq = 0; Fq < 2; ++Fq)
+                                    v += qab * Q[e * 2 + E] * Q[f * 2 + Fq] * Tp[((A * 2 + Bq) * 2 + E) * 2 + Fq];
+                        }
+                    T[((a * 2 + bb) * 2 + e) * 2 + f] = v;
+                }
+}
+
+// padded node index of a real node
+__device__ __forceinline__ int64_t pad_index(const Dev* d, int ix, int iy, int iz) {
+    int R = d->R;
+    if (d->dim == 2) return (int64_t)(ix + R) + (int64_t)d->np1[0] * (iy + R);
+    return (int64_t)(ix + R) + (int64_t)d->np1[0] * ((iy + R) + (int64_t)d->np1[1] * (iz + R));
+}
+
+}  // namespace ppm

@@ -1,0 +1,736 @@
+// Host runtime and C ABI of libppmpm: workspace layout, problem descriptors, the time step of
+// Sec. 3.1 (Stages 1-4) with the Newton loop of Sec. 3.4 driven from the host over a batch of
+// problems, and the inspection entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ppmpm.h"
+#include "launch.hpp"
+#include "ppmpm_internal.hpp"
+
+using namespace ppm;
+
+static thread_local std::string g_err;
+
+static ppmpm_status fail(ppmpm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(PPMPM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct ppmpm_problem {
+    Dev h{};                 // host copy of the device descriptor
+    Dev* d = nullptr;        // device copy (inside the workspace)
+    Dev* hpin = nullptr;     // pinned staging of the descriptor
+    double* spin = nullptr;  // pinned: scalars (NSCAL) + flags (as doubles after)
+    int* fpin = nullptr;     // pinned flags
+    hipStream_t st = nullptr;
+    ppmpm_grid grid{};
+    ppmpm_material mat{};
+    ppmpm_options opt{};
+    int64_t np = 0;
+    char* ws = nullptr;
+    size_t wsb = 0;
+    char* io = nullptr;      // staging for host inputs/outputs
+    size_t iob = 0;
+    bool have_particles = false;
+    bool have_jacobian = false;
+    int nrec = 0;
+};
+
+// ---------------------------------------------------------------------------------------------
+// layout
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int rec_fields(int dim, int shape) {
+    int wb = shape ? 3 : 2;
+    if (dim == 2) return wb == 3 ? RecLayout<2, 3>::N : RecLayout<2, 2>::N;
+    return RecLayout<3, 2>::N;
+}
+
+ppmpm_status validate(const ppmpm_grid* g, const ppmpm_options* o, int64_t np) {
+    if (!g || !o) return fail(PPMPM_E_INVALID, "null grid or options");
+    if (g->dim != 2 && g->dim != 3) return fail(PPMPM_E_INVALID, "dim must be 2 or 3");
+    for (int a = 0; a < g->dim; ++a)
+        if (g->ncell[a] < 1 || g->ncell[a] > 100000) return fail(PPMPM_E_INVALID, "bad ncell");
+    if (!(g->h > 0)) return fail(PPMPM_E_INVALID, "h must be positive");
+    if (o->shape == PPMPM_GIMP && g->dim != 2) return fail(PPMPM_E_INVALID, "GIMP is supported in 2D only");
+    if (o->shape != PPMPM_LINEAR && o->shape != PPMPM_GIMP) return fail(PPMPM_E_INVALID, "bad shape");
+    if (np < 1 || np > (int64_t)1 << 30) return fail(PPMPM_E_INVALID, "bad particle count");
+    if (o->dynamic && !(o->beta > 0 && o->gamma > 0)) return fail(PPMPM_E_INVALID, "bad Newmark parameters");
+    return PPMPM_OK;
+}
+
+// Fill sizes/levels of the host descriptor and carve the workspace (base may be null: sizing).
+size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, char* base, int* nrec_out) {
+    const int D = g->dim;
+    h.dim = D;
+    h.shape = o->shape;
+    h.dyn = o->dynamic;
+    h.mixed = o->precision == PPMPM_MIXED;
+    h.R = o->shape ? 2 : 1;
+    h.W = o->shape ? 3 : 2;
+    h.b = D + 1;
+    int SW = 2 * h.R + 1;
+    h.S = D == 2 ? SW * SW : SW * SW * SW;
+    h.Np = np;
+    h.Ncell = 1;
+    h.Nnode = 1;
+    h.Npad = 1;
+    for (int a = 0; a < 3; ++a) {
+        h.nc[a] = a < D ? g->ncell[a] : 1;
+        h.nn[a] = a < D ? g->ncell[a] + 1 : 1;
+        h.np1[a] = a < D ? h.nn[a] + 2 * h.R : 1;
+        h.x0[a] = a < D ? g->origin[a] : 0.0;
+        h.hi[a] = a < D ? g->origin[a] + g->h * g->ncell[a] : 0.0;
+        h.Ncell *= h.nc[a];
+        h.Nnode *= h.nn[a];
+        h.Npad *= h.np1[a];
+    }
+    h.h = g->h;
+    // multigrid levels
+    int nl = 0;
+    int n[3] = {h.nn[0], h.nn[1], h.nn[2]};
+    while (true) {
+        MgLevel& L = h.lev[nl];
+        int64_t rows = 1, pads = 1;
+        for (int a = 0; a < 3; ++a) {
+            L.n[a] = n[a];
+            L.np[a] = a < D ? n[a] + 2 * h.R : 1;
+            rows *= L.n[a];
+            pads *= L.np[a];
+        }
+        L.nrow = rows;
+        L.npad = pads;
+        ++nl;
+        int mn = 1 << 30;
+        for (int a = 0; a < D; ++a) mn = std::min(mn, n[a]);
+        if (rows * D <= CMAX || mn <= 3 || nl == MAXLEV) break;
+        for (int a = 0; a < D; ++a) n[a] = (n[a] - 1) / 2 + 1 + ((n[a] - 1) % 2);
+    }
+    h.nlev = nl;
+    // the coarsest level is solved by a dense inverse of at most CMAX unknowns
+    if (h.lev[nl - 1].nrow * D > CMAX) return 0;
+    const size_t TS = h.mixed ? sizeof(float) : sizeof(double);
+    const int nrec = rec_fields(D, o->shape);
+    if (nrec_out) *nrec_out = nrec;
+    Carver c{base};
+    c.take<Dev>(1);  // device descriptor first
+    h.pc = c.take<double>((size_t)NPF * np);
+    h.pw = c.take<double>((size_t)NPF * np);
+    h.idc = c.take<int>(np);
+    h.idw = c.take<int>(np);
+    h.ps = np;
+    h.key = c.take<int>(np);
+    h.slot = c.take<int>(np);
+    h.order = c.take<int>(np);
+    h.ccount = c.take<int>(h.Ncell + 1);
+    h.cstart = c.take<int>(h.Ncell + 1);
+    const int64_t P = h.Npad, bs = h.b;
+    h.M = c.take<double>(P);
+    h.Pn = c.take<double>(P);
+    h.vn = c.take<double>(P * 3);
+    h.an = c.take<double>(P * 3);
+    h.pdn = c.take<double>(P);
+    h.pddn = c.take<double>(P);
+    h.Mp = c.take<double>(P);
+    h.dfree = c.take<uint8_t>(P * bs);
+    h.bcfix = c.take<uint8_t>(P * bs);
+    h.bcval = c.take<double>(P * bs);
+    h.fext = c.take<double>(P * bs);
+    h.X = c.take<double>(P * bs);
+    h.Rv = c.take<double>(P * bs);
+    h.cellpi = c.take<double>(h.Ncell * (1 << D));
+    h.rec = c.take<double>((size_t)nrec * np);
+    h.rbase = c.take<int>((size_t)D * np);
+    h.J = c.take<char>((size_t)h.S * bs * bs * h.Nnode * TS);
+    void** kv[9] = {&h.kx, &h.kr, &h.kh, &h.kp, &h.kv, &h.ks, &h.kt, &h.kph, &h.ksh};
+    for (auto* p : kv) *p = c.take<char>((size_t)P * bs * TS);
+    h.kbt = c.take<char>((size_t)P * D * TS);
+    for (int l = 0; l < nl; ++l) {
+        MgLevel& L = h.lev[l];
+        if (l > 0) {
+            L.A = c.take<char>((size_t)h.S * D * D * L.nrow * TS);
+            L.Sm = c.take<char>((size_t)h.S * L.nrow * TS);
+        } else {
+            L.A = L.Sm = nullptr;
+        }
+        L.Ad = c.take<char>((size_t)D * D * L.nrow * TS);
+        L.Sd = c.take<char>((size_t)L.nrow * TS);
+        L.xa = c.take<char>((size_t)L.npad * D * TS);
+        L.ra = c.take<char>((size_t)L.npad * D * TS);
+        L.ba = c.take<char>((size_t)L.npad * D * TS);
+        L.xs = c.take<char>((size_t)L.npad * TS);
+        L.rs = c.take<char>((size_t)L.npad * TS);
+        L.bsv = c.take<char>((size_t)L.npad * TS);
+    }
+    const int64_t nA = h.lev[nl - 1].nrow * D, nS = h.lev[nl - 1].nrow;
+    h.cinvA = c.take<char>((size_t)std::min<int64_t>(nA * nA, CMAX * CMAX) * TS);
+    h.cinvS = c.take<char>((size_t)std::min<int64_t>(nS * nS, CMAX * CMAX) * TS);
+    h.cwork = c.take<double>((size_t)CMAX * CMAX);
+    int64_t maxrows = std::max<int64_t>(h.Nnode, np);
+    h.maxblocks = (maxrows + TPB - 1) / TPB + 1;
+    h.partial = c.take<double>((size_t)h.maxblocks * 4);
+    h.scal = c.take<double>(NSCAL);
+    h.flags = c.take<int>(NFLAG);
+    return c.off + 256;
+}
+
+size_t io_bytes(const Dev& h) {
+    const int D = h.dim;
+    size_t a = (size_t)h.Np * (3 * D + 3) * sizeof(double);
+    size_t b = (size_t)h.Np * 9 * sizeof(double);
+    size_t c = (size_t)h.Nnode * (D + 1) * 34 + 8192;   // boundary data + state + residual
+    size_t e = (size_t)h.Nnode * (D + 1) * sizeof(double) * 2;
+    return std::max(std::max(a, b), std::max(c, e)) + 4096;
+}
+
+double stab_tau(const ppmpm_options* o, double lam, double G, double kappa, double h, double dt) {
+    if (o->tau_kind == PPMPM_TAU_OFF) return 0.0;
+    if (o->tau_kind == PPMPM_TAU_WHITE) return o->tau_scale / (2.0 * G);
+    const double Mp = lam + 2.0 * G, cv = Mp * kappa, r = cv * dt / (h * h);
+    if (o->tau_kind == PPMPM_TAU_SUN) {
+        double t = (1.0 - 3.0 * r) * (1.0 + std::tanh(2.0 - 12.0 * r)) / Mp;
+        return o->tau_scale * std::max(t, 0.0);
+    }
+    double t = 2.0 * kappa / cv - (o->beta / o->gamma) * 12.0 * kappa * dt / (h * h);
+    return o->tau_scale * std::max(t, 0.0);
+}
+
+ppmpm_status upload_desc(ppmpm_problem* p) {
+    *p->hpin = p->h;
+    HIPCHK(hipMemcpyAsync(p->d, p->hpin, sizeof(Dev), hipMemcpyHostToDevice, p->st));
+    return PPMPM_OK;
+}
+
+// copy a caller array of `bytes` into device memory: device pointers pass through, host ones
+// are staged in the io region at byte offset `off`
+const void* to_device(ppmpm_problem* p, const void* src, size_t bytes, int where, size_t& off) {
+    if (!src) return nullptr;
+    if (where == PPMPM_DEVICE) return src;
+    off = (off + 255) & ~size_t(255);
+    char* dst = p->io + off;
+    off += bytes;
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, p->st) != hipSuccess) return nullptr;
+    return dst;
+}
+
+Group make_group(const std::vector<ppmpm_problem*>& ps) {
+    Group g;
+    g.dim = ps[0]->h.dim;
+    g.shape = ps[0]->h.shape;
+    g.mixed = ps[0]->h.mixed;
+    g.S = ps[0]->h.S;
+    g.b = ps[0]->h.b;
+    for (auto* p : ps) {
+        g.ddev.push_back(p->d);
+        g.np.push_back(p->h.Np);
+        g.nnode.push_back(p->h.Nnode);
+        g.ncell.push_back(p->h.Ncell);
+        g.ncell1.push_back(p->h.Ncell + 1);
+        g.npad.push_back(p->h.Npad);
+        g.npadb.push_back(p->h.Npad * p->h.b);
+    }
+    return g;
+}
+
+std::vector<const Dev*> host_copies(const std::vector<ppmpm_problem*>& ps) {
+    std::vector<const Dev*> v;
+    for (auto* p : ps) v.push_back(&p->h);
+    return v;
+}
+
+using clk = std::chrono::steady_clock;
+double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+ppmpm_status read_scalars(const std::vector<ppmpm_problem*>& ps, hipStream_t st) {
+    for (auto* p : ps) {
+        HIPCHK(hipMemcpyAsync(p->spin, p->h.scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(p->fpin, p->h.flags, sizeof(int) * NFLAG, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return PPMPM_OK;
+}
+
+// Stage 1 for a group: descriptor upload (per-step parameters), boundary data, sort, projection
+// cells, P2G.  BC staging happens per problem.
+ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, const ppmpm_bc* const* bcs) {
+    hipStream_t st = ps[0]->st;
+    for (size_t i = 0; i < ps.size(); ++i) {
+        ppmpm_problem* p = ps[i];
+        Dev& h = p->h;
+        const ppmpm_options* o = &p->opt;
+        double t = dt[i];
+        if (!(t > 0)) return fail(PPMPM_E_INVALID, "dt must be positive");
+        h.dt = t;
+        h.beta = o->beta;
+        h.gamma = o->gamma;
+        h.ct = o->dynamic ? o->gamma / (o->beta * t) : 1.0 / t;
+        h.hc1 = o->dynamic ? 1.0 - o->gamma / o->beta : 0.0;
+        h.hc2 = o->dynamic ? (1.0 - 0.5 * o->gamma / o->beta) * t : 0.0;
+        h.tau = stab_tau(o, h.lam, h.G, h.kappa, h.h, t);
+        h.Kfs = h.lam + 2.0 * h.G / h.dim;
+        h.omega = 0.7;
+        h.mg_nsm = std::max(1, o->mg_smooth);
+        ppmpm_status s = upload_desc(p);
+        if (s) return s;
+        HIPCHK(hipMemsetAsync(h.flags, 0, sizeof(int) * NFLAG, st));
+        const ppmpm_bc* bc = bcs ? bcs[i] : nullptr;
+        size_t off = 0;
+        const int64_t nn = h.Nnode;
+        const int D = h.dim;
+        int where = bc ? bc->where : PPMPM_HOST;
+        const uint8_t* uf = bc ? (const uint8_t*)to_device(p, bc->u_fixed, nn * D, where, off) : nullptr;
+        const double* ui = bc ? (const double*)to_device(p, bc->u_inc, nn * D * 8, where, off) : nullptr;
+        const uint8_t* pf = bc ? (const uint8_t*)to_device(p, bc->p_fixed, nn, where, off) : nullptr;
+        const double* pv = bc ? (const double*)to_device(p, bc->p_val, nn * 8, where, off) : nullptr;
+        const double* fe = bc ? (const double*)to_device(p, bc->f_ext, nn * D * 8, where, off) : nullptr;
+        const double* qe = bc ? (const double*)to_device(p, bc->q_ext, nn * 8, where, off) : nullptr;
+        if (off > p->iob) return fail(PPMPM_E_OOM, "io staging too small");
+        launch_bc(p->d, nn, uf, ui, pf, pv, fe, qe, st);
+    }
+    Group g = make_group(ps);
+    launch_sort(g, st);
+    if (g.shape == 0) launch_cell_proj(g, st);
+    launch_p2g(g, st);
+    return PPMPM_OK;
+}
+
+struct NState {
+    int phase = 0;  // 0 Newton, 1 converged, 2 failed
+    int status = PPMPM_OK;
+    double ru0 = 0, rp0 = 0, atol_u = 0, atol_p = 0;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+size_t ppmpm_workspace_bytes(const ppmpm_grid* grid, int64_t np, const ppmpm_options* opt) {
+    if (validate(grid, opt, np) != PPMPM_OK) return 0;
+    Dev h{};
+    size_t core = layout(h, grid, opt, np, nullptr, nullptr);
+    if (core == 0) {
+        g_err = "grid too elongated: the multigrid cannot coarsen it to a dense coarsest level";
+        return 0;
+    }
+    return core + io_bytes(h) + 256;
+}
+
+ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, const ppmpm_options* opt,
+                          void* workspace, size_t ws_bytes, void* hip_stream, int64_t np, ppmpm_problem** out) {
+    if (!out) return fail(PPMPM_E_INVALID, "null out");
+    *out = nullptr;
+    ppmpm_status s = validate(grid, opt, np);
+    if (s) return s;
+    if (!mat) return fail(PPMPM_E_INVALID, "null material");
+    if (mat->model == PPMPM_HENCKY && grid->dim == 3) return fail(PPMPM_E_INVALID, "Hencky is plane strain only");
+    if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->mu_f > 0) || !(mat->k >= 0))
+        return fail(PPMPM_E_INVALID, "bad material constants");
+    if (((uintptr_t)workspace & 255) != 0) return fail(PPMPM_E_INVALID, "workspace must be 256-byte aligned");
+    size_t need = ppmpm_workspace_bytes(grid, np, opt);
+    if (need == 0) return PPMPM_E_INVALID;   // message set by ppmpm_workspace_bytes
+    if (!workspace || ws_bytes < need) return fail(PPMPM_E_OOM, "workspace smaller than ppmpm_workspace_bytes");
+    ppmpm_problem* p = new ppmpm_problem();
+    p->grid = *grid;
+    p->mat = *mat;
+    p->opt = *opt;
+    if (p->opt.newton_max <= 0) p->opt.newton_max = 25;
+    if (p->opt.krylov_max <= 0) p->opt.krylov_max = 1000;
+    if (p->opt.krylov_check <= 0) p->opt.krylov_check = 4;
+    if (!(p->opt.newton_rtol > 0)) p->opt.newton_rtol = 1e-8;
+    if (!(p->opt.krylov_rtol > 0)) p->opt.krylov_rtol = 1e-8;
+    p->np = np;
+    p->ws = (char*)workspace;
+    p->wsb = ws_bytes;
+    p->st = (hipStream_t)hip_stream;
+    size_t used = layout(p->h, grid, opt, np, p->ws, &p->nrec);
+    p->d = (Dev*)p->ws;
+    p->io = p->ws + ((used + 255) & ~size_t(255));
+    p->iob = ws_bytes - (size_t)(p->io - p->ws);
+    Dev& h = p->h;
+    h.model = mat->model;
+    h.lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
+    h.G = mat->E / (2.0 * (1.0 + mat->nu));
+    h.kappa = mat->k / mat->mu_f;
+    h.rho_f = mat->rho_f;
+    for (int a = 0; a < 3; ++a) h.g[a] = a < grid->dim ? mat->g[a] : 0.0;
+    h.dt = 1.0;
+    h.beta = opt->beta;
+    h.gamma = opt->gamma;
+    h.omega = 0.7;
+    h.mg_nsm = std::max(1, opt->mg_smooth);
+    if (hipHostMalloc((void**)&p->hpin, sizeof(Dev)) != hipSuccess ||
+        hipHostMalloc((void**)&p->spin, sizeof(double) * NSCAL) != hipSuccess ||
+        hipHostMalloc((void**)&p->fpin, sizeof(int) * NFLAG) != hipSuccess) {
+        ppmpm_destroy(p);
+        return fail(PPMPM_E_DEVICE, "pinned host allocation failed");
+    }
+    if (hipMemsetAsync(p->ws, 0, used, p->st) != hipSuccess) {
+        ppmpm_destroy(p);
+        return fail(PPMPM_E_DEVICE, "workspace clear failed");
+    }
+    s = upload_desc(p);
+    if (s) {
+        ppmpm_destroy(p);
+        return s;
+    }
+    *out = p;
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_set_particles(ppmpm_problem* p, int64_t np, const double* x, const double* vol, const double* mass,
+                                 const double* lp, const double* v0, const double* p0, int where) {
+    if (!p || np != p->np || !x || !vol || !mass) return fail(PPMPM_E_INVALID, "bad set_particles arguments");
+    const int D = p->h.dim;
+    size_t off = 0;
+    const double* dx = (const double*)to_device(p, x, np * D * 8, where, off);
+    const double* dvol = (const double*)to_device(p, vol, np * 8, where, off);
+    const double* dm = (const double*)to_device(p, mass, np * 8, where, off);
+    const double* dlp = (const double*)to_device(p, lp, np * D * 8, where, off);
+    const double* dv0 = (const double*)to_device(p, v0, np * D * 8, where, off);
+    const double* dp0 = (const double*)to_device(p, p0, np * 8, where, off);
+    if (off > p->iob) return fail(PPMPM_E_OOM, "io staging too small");
+    HIPCHK(hipMemsetAsync(p->h.flags, 0, sizeof(int) * NFLAG, p->st));
+    launch_set_particles(p->d, np, dx, dvol, dm, dlp, dv0, dp0, p->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(p->fpin, p->h.flags, sizeof(int) * NFLAG, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    if (p->fpin[FL_OUTSIDE]) return fail(PPMPM_E_OUT_OF_GRID, "a material point lies outside the grid (or lp > h/2)");
+    p->have_particles = true;
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_step_batched(ppmpm_problem* const* probs, int nprob, const double* dt, const ppmpm_bc* const* bcs,
+                                ppmpm_step_stats* stats) {
+    if (!probs || nprob < 1 || !dt) return fail(PPMPM_E_INVALID, "bad batch");
+    for (int i = 0; i < nprob; ++i)
+        if (!probs[i] || !probs[i]->have_particles) return fail(PPMPM_E_INVALID, "problem without particles");
+    hipStream_t st = probs[0]->st;
+    auto t0 = clk::now();
+    std::vector<ppmpm_step_stats> S(nprob);
+    for (auto& s : S) {
+        std::memset(&s, 0, sizeof(s));
+        s.status = PPMPM_OK;
+    }
+    // group by kernel variant, chunks of MAXB
+    std::vector<std::vector<int>> groups;
+    {
+        std::vector<int> used(nprob, 0);
+        for (int i = 0; i < nprob; ++i) {
+            if (used[i]) continue;
+            std::vector<int> gidx;
+            for (int j = i; j < nprob && (int)gidx.size() < MAXB; ++j) {
+                if (used[j]) continue;
+                const Dev &a = probs[i]->h, &b = probs[j]->h;
+                if (a.dim == b.dim && a.shape == b.shape && a.mixed == b.mixed) {
+                    gidx.push_back(j);
+                    used[j] = 1;
+                }
+            }
+            groups.push_back(gidx);
+        }
+    }
+    ppmpm_status first_err = PPMPM_OK;
+    for (auto& gi : groups) {
+        std::vector<ppmpm_problem*> ps;
+        std::vector<double> dts;
+        std::vector<const ppmpm_bc*> bcv;
+        for (int i : gi) {
+            ps.push_back(probs[i]);
+            dts.push_back(dt[i]);
+            bcv.push_back(bcs ? bcs[i] : nullptr);
+        }
+        auto ta = clk::now();
+        ppmpm_status s = stage1(ps, dts.data(), bcv.data());
+        if (s) return s;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        auto tb = clk::now();
+        for (int i : gi) S[i].t_sort = secs(ta, tb);
+        std::vector<NState> ns(ps.size());
+        for (size_t k = 0; k < ps.size(); ++k) {
+            const Dev& h = ps[k]->h;
+            const ppmpm_options& o = ps[k]->opt;
+            ns[k].atol_u = o.newton_atol_u > 0 ? o.newton_atol_u : 1e-12 * ps[k]->mat.E * std::pow(h.h, h.dim - 1);
+            ns[k].atol_p = o.newton_atol_p > 0 ? o.newton_atol_p : 1e-12 * std::pow(h.h, h.dim) / h.dt;
+        }
+        for (int it = 0;; ++it) {
+            std::vector<ppmpm_problem*> act;
+            std::vector<int> actk;
+            for (size_t k = 0; k < ps.size(); ++k)
+                if (ns[k].phase == 0) {
+                    act.push_back(ps[k]);
+                    actk.push_back((int)k);
+                }
+            if (act.empty()) break;
+            auto t1 = clk::now();
+            Group ga = make_group(act);
+            launch_assemble(ga, false, st);
+            HIPCHK(hipGetLastError());
+            s = read_scalars(act, st);
+            if (s) return s;
+            auto t2 = clk::now();
+            std::vector<ppmpm_problem*> cont;
+            std::vector<int> contk;
+            for (size_t j = 0; j < act.size(); ++j) {
+                int k = actk[j];
+                ppmpm_problem* p = act[j];
+                int qi = gi[k];
+                ppmpm_step_stats& so = S[qi];
+                so.t_assemble += secs(t1, t2);
+                double ru = std::sqrt(p->spin[SC_RU2]), rp = std::sqrt(p->spin[SC_RP2]);
+                if (it < PPMPM_MAX_HIST) {
+                    so.res_u[it] = ru;
+                    so.res_p[it] = rp;
+                }
+                so.newton_iters = it;
+                if (p->fpin[FL_INVERTED] || p->fpin[FL_NONFINITE] || !std::isfinite(ru) || !std::isfinite(rp)) {
+                    ns[k].phase = 2;
+                    ns[k].status = PPMPM_E_NONFINITE;
+                    continue;
+                }
+                if (p->fpin[FL_BOUNDS]) {
+                    ns[k].phase = 2;
+                    ns[k].status = PPMPM_E_DEVICE;
+                    continue;
+                }
+                if (it == 0) {
+                    ns[k].ru0 = ru;
+                    ns[k].rp0 = rp;
+                }
+                const double rt = p->opt.newton_rtol;
+                bool cu = ru <= std::max(rt * ns[k].ru0, ns[k].atol_u);
+                bool cp = rp <= std::max(rt * ns[k].rp0, ns[k].atol_p);
+                if (cu && cp) {
+                    ns[k].phase = 1;
+                    so.converged = 1;
+                    continue;
+                }
+                if (it >= p->opt.newton_max) {
+                    ns[k].phase = 2;
+                    ns[k].status = PPMPM_E_NEWTON;
+                    continue;
+                }
+                cont.push_back(p);
+                contk.push_back(k);
+            }
+            if (cont.empty()) continue;
+            Group gc = make_group(cont);
+            auto hcs = host_copies(cont);
+            auto t3 = clk::now();
+            launch_jacobian(gc, st);
+            launch_precond_setup(gc, hcs, st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(st));
+            auto t4 = clk::now();
+            double krtol = cont[0]->opt.krylov_rtol;
+            if (gc.mixed) krtol = std::max(krtol, 1e-6);
+            int kmax = cont[0]->opt.krylov_max;
+            int kcheck = std::max(1, cont[0]->opt.krylov_check);
+            launch_krylov_init(gc, krtol, kmax, st);
+            int done_iters = 0;
+            while (true) {
+                launch_krylov_iters(gc, hcs, kcheck, krtol, kmax, st);
+                HIPCHK(hipGetLastError());
+                s = read_scalars(cont, st);
+                if (s) return s;
+                done_iters += kcheck;
+                bool all = true;
+                for (auto* p : cont)
+                    if (p->spin[SC_DONE] == 0.0) all = false;
+                if (all || done_iters >= kmax) break;
+            }
+            launch_newton_update(gc, st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(st));
+            auto t5 = clk::now();
+            for (size_t j = 0; j < cont.size(); ++j) {
+                int qi = gi[contk[j]];
+                ppmpm_step_stats& so = S[qi];
+                int kit = (int)cont[j]->spin[SC_ITER];
+                if (it < PPMPM_MAX_HIST) so.krylov_iters[it] = kit;
+                so.krylov_total += kit;
+                if (cont[j]->spin[SC_BREAK] != 0.0) so.krylov_breakdowns++;
+                so.t_precond += secs(t3, t4);
+                so.t_krylov += secs(t4, t5);
+            }
+        }
+        // Stages 3-4 for the converged problems
+        std::vector<ppmpm_problem*> okp;
+        std::vector<int> okk;
+        for (size_t k = 0; k < ps.size(); ++k)
+            if (ns[k].phase == 1) {
+                okp.push_back(ps[k]);
+                okk.push_back((int)k);
+            }
+        auto t6 = clk::now();
+        if (!okp.empty()) {
+            Group go = make_group(okp);
+            launch_g2p(go, st);
+            HIPCHK(hipGetLastError());
+            s = read_scalars(okp, st);
+            if (s) return s;
+            for (size_t j = 0; j < okp.size(); ++j) {
+                ppmpm_problem* p = okp[j];
+                int k = okk[j];
+                if (p->fpin[FL_INVERTED]) {
+                    ns[k].status = PPMPM_E_NONFINITE;
+                    continue;
+                }
+                if (p->fpin[FL_OUTSIDE]) {
+                    ns[k].status = PPMPM_E_OUT_OF_GRID;
+                    continue;
+                }
+                // commit: the working buffer becomes the state
+                std::swap(p->h.pc, p->h.pw);
+                std::swap(p->h.idc, p->h.idw);
+                s = upload_desc(p);
+                if (s) return s;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        auto t7 = clk::now();
+        for (size_t k = 0; k < ps.size(); ++k) {
+            int qi = gi[k];
+            S[qi].t_g2p = secs(t6, t7);
+            S[qi].status = ns[k].status;
+            S[qi].ngrid_levels = ps[k]->h.nlev;
+            if (ns[k].status != PPMPM_OK && first_err == PPMPM_OK) first_err = (ppmpm_status)ns[k].status;
+        }
+    }
+    auto tend = clk::now();
+    for (int i = 0; i < nprob; ++i) {
+        S[i].t_total = secs(t0, tend);
+        if (stats) stats[i] = S[i];
+    }
+    if (first_err) {
+        const char* names[] = {"ok", "invalid", "oom", "device", "Newton did not converge", "krylov",
+                               "non-finite residual or inverted material point", "material point left the grid"};
+        g_err = std::string("step failed: ") + names[first_err];
+    }
+    return first_err;
+}
+
+ppmpm_status ppmpm_step(ppmpm_problem* p, double dt, const ppmpm_bc* bc, ppmpm_step_stats* stats) {
+    ppmpm_problem* probs[1] = {p};
+    const ppmpm_bc* bcs[1] = {bc};
+    return ppmpm_step_batched(probs, 1, &dt, bcs, stats);
+}
+
+ppmpm_status ppmpm_get_field(const ppmpm_problem* pc, int field, double* out, int where) {
+    ppmpm_problem* p = const_cast<ppmpm_problem*>(pc);
+    if (!p || !out || field < 0 || field > 10) return fail(PPMPM_E_INVALID, "bad get_field arguments");
+    const int D = p->h.dim;
+    int ncomp = 1;
+    switch (field) {
+        case PPMPM_FIELD_X: case PPMPM_FIELD_U: case PPMPM_FIELD_V: case PPMPM_FIELD_A: case PPMPM_FIELD_LP: ncomp = D; break;
+        case PPMPM_FIELD_F: ncomp = D * D; break;
+        case PPMPM_FIELD_SIG: ncomp = 9; break;
+        default: ncomp = 1;
+    }
+    size_t bytes = (size_t)p->np * ncomp * sizeof(double);
+    double* dst = where == PPMPM_DEVICE ? out : (double*)p->io;
+    if (where != PPMPM_DEVICE && bytes > p->iob) return fail(PPMPM_E_OOM, "io staging too small");
+    launch_get_field(p->d, p->np, field, ncomp, dst, p->st);
+    HIPCHK(hipGetLastError());
+    if (where != PPMPM_DEVICE) HIPCHK(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_eval_residual(ppmpm_problem* p, double dt, const ppmpm_bc* bc, const double* U, const double* P,
+                                 double* R, int where) {
+    if (!p || !p->have_particles || !U || !P || !R) return fail(PPMPM_E_INVALID, "bad eval_residual arguments");
+    std::vector<ppmpm_problem*> ps{p};
+    const ppmpm_bc* bcs[1] = {bc};
+    ppmpm_status s = stage1(ps, &dt, bcs);
+    if (s) return s;
+    const int64_t nn = p->h.Nnode;
+    const int D = p->h.dim;
+    // stage1 used the front of the io region for the boundary data; stage the state after it
+    size_t off = (size_t)nn * (D + 1) * (2 * sizeof(double) + 2) + 4096;
+    const double* dU = (const double*)to_device(p, U, nn * D * 8, where, off);
+    const double* dP = (const double*)to_device(p, P, nn * 8, where, off);
+    double* dR = where == PPMPM_DEVICE ? R : (double*)(p->io + ((off + 255) & ~size_t(255)));
+    launch_set_state(p->d, &p->h, dU, dP, p->st);
+    Group g = make_group(ps);
+    launch_assemble(g, true, p->st);
+    launch_residual_out(p->d, &p->h, dR, p->st);
+    HIPCHK(hipGetLastError());
+    if (where != PPMPM_DEVICE) HIPCHK(hipMemcpyAsync(R, dR, nn * (D + 1) * 8, hipMemcpyDeviceToHost, p->st));
+    s = read_scalars(ps, p->st);
+    if (s) return s;
+    p->have_jacobian = true;
+    if (p->fpin[FL_INVERTED]) return fail(PPMPM_E_NONFINITE, "inverted material point");
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_apply_jacobian(ppmpm_problem* p, const double* v, double* y, int where) {
+    if (!p || !p->have_jacobian || !v || !y) return fail(PPMPM_E_INVALID, "no Jacobian assembled");
+    const int64_t n = p->h.Nnode * p->h.b;
+    size_t off = 0;
+    const double* dv = (const double*)to_device(p, v, n * 8, where, off);
+    off = (off + 255) & ~size_t(255);
+    double* dy = where == PPMPM_DEVICE ? y : (double*)(p->io + off);
+    launch_apply_jacobian(p->d, &p->h, dv, dy, p->st);
+    HIPCHK(hipGetLastError());
+    if (where != PPMPM_DEVICE) HIPCHK(hipMemcpyAsync(y, dy, n * 8, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_get_nodal(const ppmpm_problem* pc, int field, double* out, int where) {
+    ppmpm_problem* p = const_cast<ppmpm_problem*>(pc);
+    if (!p || !out || field < 0 || field > 2) return fail(PPMPM_E_INVALID, "bad get_nodal arguments");
+    const int64_t n = field == 2 ? p->h.Nnode * p->h.b : p->h.Nnode;
+    double* dst = where == PPMPM_DEVICE ? out : (double*)p->io;
+    launch_nodal_out(p->d, &p->h, field, dst, p->st);
+    HIPCHK(hipGetLastError());
+    if (where != PPMPM_DEVICE) HIPCHK(hipMemcpyAsync(out, dst, n * 8, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_destroy(ppmpm_problem* p) {
+    if (!p) return PPMPM_OK;
+    if (p->st) (void)hipStreamSynchronize(p->st);
+    if (p->hpin) (void)hipHostFree(p->hpin);
+    if (p->spin) (void)hipHostFree(p->spin);
+    if (p->fpin) (void)hipHostFree(p->fpin);
+    delete p;
+    return PPMPM_OK;
+}
+
+const char* ppmpm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -92,6 +92,8 @@ class Options:
     tau_scale: float = 1.0
     mixed: int = 0                 # 0: FP64 everywhere; 1: FP32 Jacobian/SpMV/preconditioner
     newton_rtol: float = 1e-8
+    newton_atol_u: float = 0.0     # <= 0: 1e-12 E h^(dim-1)
+    newton_atol_p: float = 0.0     # <= 0: 1e-12 h^dim / dt
     newton_max: int = 25
     krylov_rtol: float = 1e-8
     krylov_max: int = 4000

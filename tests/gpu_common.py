@@ -1,0 +1,63 @@
+"""Shared helpers of the GPU parity tests: the same seeded inputs go to the HIP library (through
+the C ABI) and to the CPU oracle; comparisons follow the element-wise / per-block rules of the
+parity tests."""
+import numpy as np
+
+from oracle import oracle as O
+from paper_1905_00671_amd import workloads as W
+
+
+def oracle_masked_residual(pr, nodal, U, P, bc, dt):
+    """Oracle residual with the nodal loads and the Dirichlet / inactive rows removed, in the
+    node-interleaved layout of the library."""
+    g, d = pr.grid, pr.grid.dim
+    nn = g.nnode
+    R, J, _ = pr.assemble(U, P, nodal, dt, want_J=True)
+    fext = np.zeros((nn, d + 1))
+    fext[:, :d] = bc["f_ext"].reshape(nn, d)
+    fext[:, d] = -bc["q_ext"]
+    free = free_mask(nodal, bc, d)
+    return (R + fext.reshape(-1)) * free, J, free
+
+
+def free_mask(nodal, bc, d):
+    nn = nodal["active"].shape[0]
+    fixed = np.zeros((nn, d + 1), bool)
+    fixed[:, :d] = bc["u_fixed"].astype(bool).reshape(nn, d)
+    fixed[:, d] = bc["p_fixed"].astype(bool)
+    return ((~fixed) & nodal["active"][:, None]).reshape(-1)
+
+
+def oracle_jv(J, free, v):
+    """J v with non-free rows/columns replaced by the identity."""
+    vf = v * free
+    y = J @ vf
+    return np.where(free, y, v)
+
+
+def block_err(a, b, d):
+    """max |a - b| / max |b| per dof block (u components together, p separately)."""
+    a = a.reshape(-1, d + 1)
+    b = b.reshape(-1, d + 1)
+    out = []
+    for sl in (slice(0, d), slice(d, d + 1)):
+        den = np.abs(b[:, sl]).max()
+        out.append(np.abs(a[:, sl] - b[:, sl]).max() / (den if den > 0 else 1.0))
+    return out
+
+
+def rel_l2(a, b, floor=0.0):
+    den = max(np.linalg.norm(b), floor)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def dyn_oracle_nodal(pr, bc):
+    nodal = pr.p2g()
+    g, d = pr.grid, pr.grid.dim
+    if pr.opt.dynamic:
+        ufix = bc["u_fixed"].astype(bool).reshape(g.nnode, d)
+        for k in ("vn", "an"):
+            v = nodal[k].reshape(g.nnode, d)
+            v[ufix] = 0.0
+            nodal[k] = v.reshape(-1)
+    return nodal

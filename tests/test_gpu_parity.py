@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Assembly parity compares the masked residual element by element and J v for random v at a shared
+random nodal state (FP64: 1e-11 of each block's scale; mixed: FP32 Jacobian, 1e-5).  Step parity
+runs whole time steps on both sides and compares the material-point displacement and pore
+pressure after every step with the relative L2 metric (FP64 1e-10, mixed 1e-6; pressure error
+measured against max(|p|, |sigma'|) so that drained steps with p -> 0 stay meaningful)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1905_00671_amd import workloads as W
+from tests.gpu_common import block_err, dyn_oracle_nodal, free_mask, oracle_jv, oracle_masked_residual, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _binding():
+    from paper_1905_00671_amd import binding as B
+    return B
+
+
+def _assembly_case(name):
+    rng = np.random.default_rng(abs(hash(name)) % 1000)
+    if name == "box_linear_qs":
+        w = W.jittered_box(8, 8, shape=W.LINEAR, seed=1)
+    elif name == "box_gimp_qs":
+        w = W.jittered_box(8, 8, shape=W.GIMP, seed=2)
+    elif name == "box_gimp_dyn":
+        w = W.jittered_box(8, 8, shape=W.GIMP, dynamic=1, seed=3)
+        w.particles.v0 = 0.05 * (rng.random((w.particles.n, 2)) - 0.5)
+    elif name == "box_linear_dyn_hencky":
+        w = W.jittered_box(8, 8, shape=W.LINEAR, dynamic=1, model=W.HENCKY, seed=4)
+        w.particles.v0 = 0.05 * (rng.random((w.particles.n, 2)) - 0.5)
+    elif name == "terzaghi":
+        w = W.config(1)
+    elif name == "footing_gimp":
+        w = W.config(3, nx=32, ny=16, width=2.0, empty_rows=3, nsteps=2)
+    elif name == "footing3d":
+        w = W.footing3d(n=5, size=1.25, half_b=0.25, nsteps=2)
+    elif name == "footing3d_dyn":
+        w = W.footing3d(n=4, size=1.0, half_b=0.25, nsteps=2)
+        w.options.dynamic = 1
+        w.particles.v0 = 0.05 * (rng.random((w.particles.n, 3)) - 0.5)
+    else:
+        raise ValueError(name)
+    w.particles.p0 = 1e4 * rng.random(w.particles.n)
+    return w, rng
+
+
+ASSEMBLY_CASES = ["box_linear_qs", "box_gimp_qs", "box_gimp_dyn", "box_linear_dyn_hencky", "terzaghi",
+                  "footing_gimp", "footing3d", "footing3d_dyn"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", ASSEMBLY_CASES)
+def test_assembly_parity(name, precision):
+    B = _binding()
+    w, rng = _assembly_case(name)
+    print(f"[assembly] case={name} precision={precision} np={w.particles.n}", flush=True)
+    g, d = w.grid, w.grid.dim
+    pr = O.from_workload(w)
+    bc = w.bc(1)
+    nodal = dyn_oracle_nodal(pr, bc)
+    act = nodal["active"]
+    U = 2e-3 * w.grid.h * (rng.random((g.nnode, d)) - 0.5) * act[:, None]
+    P = (nodal["Pn"] + 3e3 * (rng.random(g.nnode) - 0.5)) * act
+    R_or, J, free = oracle_masked_residual(pr, nodal, U, P, bc, w.dt)
+    gp = B.Problem.from_workload(w, precision=precision)
+    try:
+        R_gpu = gp.eval_residual(w.dt, bc, U, P)
+        # P2G and the dof masks agree exactly (same decisions) and to rounding (values)
+        assert np.array_equal(gp.get_nodal(2).astype(bool), free)
+        M_gpu = gp.get_nodal(0)
+        assert np.abs(M_gpu - nodal["M"]).max() <= 1e-13 * nodal["M"].max()
+        eu, ep = block_err(R_gpu, R_or, d)
+        assert eu < 1e-11 and ep < 1e-11, (eu, ep)
+        tol = 1e-11 if precision == 0 else 2e-6
+        for trial in range(3):
+            v = rng.random(g.nnode * (d + 1)) - 0.5
+            v.reshape(-1, d + 1)[:, d] *= 1e6      # pressure increments are O(1e6) x displacement ones
+            y_or = oracle_jv(J, free, v)
+            y_gpu = gp.apply_jacobian(v)
+            eu, ep = block_err(y_gpu, y_or, d)
+            assert eu < tol and ep < tol, (trial, eu, ep)
+    finally:
+        gp.close()
+
+
+def _run_steps(w, nsteps, precision, **over):
+    B = _binding()
+    pr = O.from_workload(w)
+    gp = B.Problem.from_workload(w, precision=precision, **over)
+    errs = []
+    try:
+        for n in range(1, nsteps + 1):
+            bc = w.bc(n)
+            st_o = pr.step(w.dt, bc)
+            st_g = gp.step(w.dt, bc)
+            u_g, p_g = gp.get("u"), gp.get("p")
+            sig_scale = np.abs(pr.sig).max()
+            eu = rel_l2(u_g, pr.u)
+            ep = rel_l2(p_g, pr.p, floor=np.sqrt(pr.np) * sig_scale * 1e-3 + 1e-300)
+            errs.append((eu, ep, st_o["newton_iters"], st_g["newton_iters"], st_g["krylov_total"]))
+            print(f"  step {n}: e_u={eu:.2e} e_p={ep:.2e} newton oracle/gpu={st_o['newton_iters']}/"
+                  f"{st_g['newton_iters']} krylov={st_g['krylov_total']}", flush=True)
+        x_g = gp.get("x")
+        F_g = gp.get("F")
+        assert np.abs(x_g - pr.x).max() <= 1e-9 * np.abs(pr.x).max()
+        assert np.abs(F_g - pr.F).max() <= 1e-8
+    finally:
+        gp.close()
+    return errs
+
+
+STEP_CASES = {
+    "terzaghi": (lambda: W.config(1), 10),
+    "footing2d_dyn_gimp": (lambda: W.config(2, nx=16, ny=16, width=2.5, empty_rows=2, nsteps=4), 4),
+    "footing2d_qs_gimp": (lambda: W.config(3, nx=32, ny=16, width=2.0, empty_rows=2, nsteps=4), 4),
+    "consolidation_linear": (lambda: W.consolidation2d(16, 1e-13, nsteps=3), 3),
+    "footing3d": (lambda: W.footing3d(n=6, size=1.5, half_b=0.25, nsteps=2), 2),
+}
+
+
+@pytest.mark.parametrize("name", list(STEP_CASES))
+def test_step_parity_fp64(name):
+    make, nsteps = STEP_CASES[name]
+    w = make()
+    w.options.newton_rtol = 1e-10
+    w.options.krylov_rtol = 1e-12
+    print(f"[steps fp64] case={name} np={w.particles.n}", flush=True)
+    errs = _run_steps(w, nsteps, 0)
+    for eu, ep, no, ng, kt in errs:
+        assert eu < 1e-10 and ep < 1e-10, errs
+
+
+@pytest.mark.parametrize("name", ["terzaghi", "footing2d_qs_gimp", "footing3d"])
+def test_step_parity_mixed(name):
+    make, nsteps = STEP_CASES[name]
+    w = make()
+    w.options.newton_rtol = 1e-8
+    print(f"[steps mixed] case={name} np={w.particles.n}", flush=True)
+    errs = _run_steps(w, nsteps, 1)
+    for eu, ep, no, ng, kt in errs:
+        assert eu < 1e-6 and ep < 1e-6, errs
+
+
+def test_step_parity_default_tolerances():
+    """At the paper's tolerances (Newton 1e-8, Krylov 1e-8 |R|) the FP64 path still matches."""
+    w = W.config(3, nx=32, ny=16, width=2.0, empty_rows=2, nsteps=3)
+    print("[steps default tol]", flush=True)
+    errs = _run_steps(w, 3, 0)
+    for eu, ep, no, ng, kt in errs:
+        assert eu < 1e-8 and ep < 1e-8, errs
+
+
+def test_batched_equals_alone():
+    """Problems stepped together (one launch per phase) give bit-identical results to the same
+    problems stepped alone."""
+    B = _binding()
+    ws = [W.consolidation2d(12, 1e-12, nsteps=2), W.consolidation2d(20, 1e-14, nsteps=2),
+          W.config(3, nx=16, ny=8, width=1.0, empty_rows=2, nsteps=2)]
+    alone = []
+    for w in ws:
+        p = B.Problem.from_workload(w)
+        for n in (1, 2):
+            p.step(w.dt, w.bc(n))
+        alone.append((p.get("u"), p.get("p")))
+        p.close()
+    ps = [B.Problem.from_workload(w) for w in ws]
+    try:
+        for n in (1, 2):
+            st = B.step_batched(ps, [w.dt for w in ws], [w.bc(n) for w in ws])
+            assert all(s["status"] == 0 for s in st), st
+        for (u0, p0), p in zip(alone, ps):
+            assert np.array_equal(p.get("u"), u0)
+            assert np.array_equal(p.get("p"), p0)
+    finally:
+        for p in ps:
+            p.close()
+
+
+def test_transactional_failure_leaves_state():
+    """A step that cannot converge (one Newton iteration allowed on a loaded step that needs two)
+    reports PPMPM_E_NEWTON and leaves the material points untouched."""
+    B = _binding()
+    w = W.config(1)
+    p = B.Problem.from_workload(w, newton_max=1)
+    try:
+        x0 = p.get("x").copy()
+        st = p.step(w.dt, w.bc(1), raise_on_error=False)
+        assert st["status"] == B.E_NEWTON
+        assert np.array_equal(p.get("x"), x0)
+    finally:
+        p.close()
