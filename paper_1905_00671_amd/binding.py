@@ -280,6 +280,36 @@ def step_batched(problems: Sequence[Problem], dts: Sequence[float], bcs: Sequenc
     return [stats[i].as_dict() for i in range(n)]
 
 
+KERNELS = ["spmv", "jacobian", "records", "residual", "mg0_resid", "p2g", "g2p", "permute", "rap"]
+
+
+def timing_enable(on: bool = True):
+    L = lib()
+    L.ppmpm_timing_enable.restype = ctypes.c_int
+    L.ppmpm_timing_enable.argtypes = [ctypes.c_int]
+    _check(L.ppmpm_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    L = lib()
+    L.ppmpm_timing_reset.restype = ctypes.c_int
+    _check(L.ppmpm_timing_reset())
+
+
+def timing_get() -> Dict[str, Dict[str, float]]:
+    """Launch counts and summed HIP-event durations (ms) of the instrumented kernels."""
+    L = lib()
+    L.ppmpm_timing_get.restype = ctypes.c_int
+    L.ppmpm_timing_get.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    for i, name in enumerate(KERNELS):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(L.ppmpm_timing_get(i, ctypes.byref(n), ctypes.byref(ms)))
+        out[name] = dict(launches=int(n.value), total_ms=float(ms.value))
+    return out
+
+
 def header_symbols() -> List[str]:
     """Function names declared in include/ppmpm.h."""
     import re

@@ -460,14 +460,14 @@ void launch_assemble(const Group& g, bool want_J, hipStream_t st) {
     Batch Bp = make_batch(g.ddev, g.np, TPB);
     Batch Bn = make_batch(g.ddev, g.nnode, TPB);
     if (g.dim == 2 && g.shape == 0) {
-        hipLaunchKernelGGL((k_records<2, 0>), dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp);
-        hipLaunchKernelGGL((k_residual<2, 0>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn);
+        PPM_TIMED(KT_RECORDS, st, hipLaunchKernelGGL((k_records<2, 0>), dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp));
+        PPM_TIMED(KT_RESIDUAL, st, hipLaunchKernelGGL((k_residual<2, 0>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn));
     } else if (g.dim == 2 && g.shape == 1) {
-        hipLaunchKernelGGL((k_records<2, 1>), dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp);
-        hipLaunchKernelGGL((k_residual<2, 1>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn);
+        PPM_TIMED(KT_RECORDS, st, hipLaunchKernelGGL((k_records<2, 1>), dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp));
+        PPM_TIMED(KT_RESIDUAL, st, hipLaunchKernelGGL((k_residual<2, 1>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn));
     } else {
-        hipLaunchKernelGGL((k_records<3, 0>), dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp);
-        hipLaunchKernelGGL((k_residual<3, 0>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn);
+        PPM_TIMED(KT_RECORDS, st, hipLaunchKernelGGL((k_records<3, 0>), dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp));
+        PPM_TIMED(KT_RESIDUAL, st, hipLaunchKernelGGL((k_residual<3, 0>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn));
     }
     hipLaunchKernelGGL(k_finalize_norms, dim3(Bn.n), dim3(TPB), 0, st, Bn);
     if (want_J) launch_jacobian(g, st);
@@ -477,14 +477,14 @@ void launch_jacobian(const Group& g, hipStream_t st) {
     Batch Bn = make_batch(g.ddev, g.nnode, TPB);
     const dim3 gr(Bn.pfx[Bn.n], g.S), tb(TPB);
     if (g.dim == 2 && g.shape == 0) {
-        if (g.mixed) hipLaunchKernelGGL((k_jacobian<2, 0, float>), gr, tb, 0, st, Bn);
-        else hipLaunchKernelGGL((k_jacobian<2, 0, double>), gr, tb, 0, st, Bn);
+        if (g.mixed) PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 0, float>), gr, tb, 0, st, Bn));
+        else PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 0, double>), gr, tb, 0, st, Bn));
     } else if (g.dim == 2 && g.shape == 1) {
-        if (g.mixed) hipLaunchKernelGGL((k_jacobian<2, 1, float>), gr, tb, 0, st, Bn);
-        else hipLaunchKernelGGL((k_jacobian<2, 1, double>), gr, tb, 0, st, Bn);
+        if (g.mixed) PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 1, float>), gr, tb, 0, st, Bn));
+        else PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 1, double>), gr, tb, 0, st, Bn));
     } else {
-        if (g.mixed) hipLaunchKernelGGL((k_jacobian<3, 0, float>), gr, tb, 0, st, Bn);
-        else hipLaunchKernelGGL((k_jacobian<3, 0, double>), gr, tb, 0, st, Bn);
+        if (g.mixed) PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<3, 0, float>), gr, tb, 0, st, Bn));
+        else PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<3, 0, double>), gr, tb, 0, st, Bn));
     }
 }
 

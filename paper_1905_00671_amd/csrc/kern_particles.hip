@@ -447,7 +447,7 @@ void launch_sort(const Group& g, hipStream_t st) {
     hipLaunchKernelGGL(k_scatter, dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp);
     Batch Bn = make_batch(g.ddev, g.ncell, TPB);
     hipLaunchKernelGGL(k_cell_sort, dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn);
-    hipLaunchKernelGGL(k_permute, dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp);
+    PPM_TIMED(KT_PERMUTE, st, hipLaunchKernelGGL(k_permute, dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp));
 }
 
 void launch_bc(const Dev* dd, int64_t nnode, const uint8_t* uf, const double* ui, const uint8_t* pf,
@@ -458,9 +458,9 @@ void launch_bc(const Dev* dd, int64_t nnode, const uint8_t* uf, const double* ui
 
 void launch_p2g(const Group& g, hipStream_t st) {
     Batch B = make_batch(g.ddev, g.nnode, TPB);
-    if (g.dim == 2 && g.shape == 0) hipLaunchKernelGGL((k_p2g<2, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
-    else if (g.dim == 2 && g.shape == 1) hipLaunchKernelGGL((k_p2g<2, 1>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
-    else hipLaunchKernelGGL((k_p2g<3, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
+    if (g.dim == 2 && g.shape == 0) PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<2, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
+    else if (g.dim == 2 && g.shape == 1) PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<2, 1>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
+    else PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<3, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
 }
 
 void launch_cell_proj(const Group& g, hipStream_t st) {
@@ -471,9 +471,9 @@ void launch_cell_proj(const Group& g, hipStream_t st) {
 
 void launch_g2p(const Group& g, hipStream_t st) {
     Batch B = make_batch(g.ddev, g.np, TPB);
-    if (g.dim == 2 && g.shape == 0) hipLaunchKernelGGL((k_g2p<2, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
-    else if (g.dim == 2 && g.shape == 1) hipLaunchKernelGGL((k_g2p<2, 1>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
-    else hipLaunchKernelGGL((k_g2p<3, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
+    if (g.dim == 2 && g.shape == 0) PPM_TIMED(KT_G2P, st, hipLaunchKernelGGL((k_g2p<2, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
+    else if (g.dim == 2 && g.shape == 1) PPM_TIMED(KT_G2P, st, hipLaunchKernelGGL((k_g2p<2, 1>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
+    else PPM_TIMED(KT_G2P, st, hipLaunchKernelGGL((k_g2p<3, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
 }
 
 }  // namespace ppm

@@ -767,7 +767,7 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, h
         hipLaunchKernelGGL((k_mg_dinv<1, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 1, l);
         if (l + 1 < Lmax) {
             Batch Bc = make_batch(g.ddev, level_rows(hc, l + 1), TPB);
-            hipLaunchKernelGGL((k_mg_rap<DIM, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l);
+            PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l));
             hipLaunchKernelGGL((k_mg_rap<1, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l);
         }
     }
@@ -802,10 +802,10 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
         const dim3 gl(Bl.pfx[Bl.n]);
         hipLaunchKernelGGL((k_mg_smooth0<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, rhs, x);
         for (int k = 1; k < nsm; ++k) {
-            hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, rhs, x, LR);
+            PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st, hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, rhs, x, LR));
             hipLaunchKernelGGL((k_mg_update<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, x, LR);
         }
-        hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, rhs, x, LR);
+        PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st, hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, rhs, x, LR));
         Batch Bc = make_batch(g.ddev, level_rows(hc, l + 1), TPB);
         hipLaunchKernelGGL((k_mg_restrict<BB, T>), dim3(Bc.pfx[Bc.n]), dim3(TPB), 0, st, Bc, fam, l, LR, LB);
     }
@@ -815,7 +815,7 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
         const dim3 gl(Bl.pfx[Bl.n]);
         hipLaunchKernelGGL((k_mg_prolong<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, LX, x);
         for (int k = 0; k < nsm; ++k) {
-            hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, rhs, x, LR);
+            PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st, hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, rhs, x, LR));
             hipLaunchKernelGGL((k_mg_update<BB, T>), gl, dim3(TPB), 0, st, Bl, fam, l, x, LR);
         }
     }
@@ -841,11 +841,11 @@ static void krylov_iters_t(const Group& g, const std::vector<const Dev*>& hc, in
     for (int it = 0; it < iters; ++it) {
         hipLaunchKernelGGL(k_bicg_p<T>, gN, tb, 0, st, Bn);
         precond_apply<DIM, T>(g, hc, 3, 7, st);
-        hipLaunchKernelGGL((k_spmv<DIM, R, T>), gN, tb, 0, st, Bn, 7, 4, 2, 1, 1);
+        PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gN, tb, 0, st, Bn, 7, 4, 2, 1, 1));
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 1, rtol, maxit);
         hipLaunchKernelGGL(k_bicg_s<T>, gN, tb, 0, st, Bn);
         precond_apply<DIM, T>(g, hc, 5, 8, st);
-        hipLaunchKernelGGL((k_spmv<DIM, R, T>), gN, tb, 0, st, Bn, 8, 6, 5, 2, 1);
+        PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gN, tb, 0, st, Bn, 8, 6, 5, 2, 1));
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 2, rtol, maxit);
         hipLaunchKernelGGL(k_bicg_xr<T>, gN, tb, 0, st, Bn);
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 3, rtol, maxit);

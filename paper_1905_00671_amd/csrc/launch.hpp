@@ -17,6 +17,25 @@ struct Group {
     std::vector<int64_t> np, nnode, ncell, ncell1, npadb, npad;
 };
 
+// Per-kernel timing with HIP events recorded on the launching stream (off unless enabled).
+enum KernelId : int { KT_SPMV = 0, KT_JACOBIAN, KT_RECORDS, KT_RESIDUAL, KT_MG0_RESID, KT_P2G, KT_G2P, KT_PERMUTE,
+                      KT_RAP, KT_COUNT };
+bool timing_on();
+void timing_begin(hipStream_t st, int id, hipEvent_t* a, hipEvent_t* b);
+void timing_end(hipStream_t st, hipEvent_t b);
+
+#define PPM_TIMED(id, st, ...)                          \
+    do {                                                \
+        if (timing_on() && (id) >= 0) {                 \
+            hipEvent_t ea_, eb_;                        \
+            timing_begin((st), (id), &ea_, &eb_);       \
+            __VA_ARGS__;                                \
+            timing_end((st), eb_);                      \
+        } else {                                        \
+            __VA_ARGS__;                                \
+        }                                               \
+    } while (0)
+
 // Blocks of `tpb` threads covering work[q] items for every problem q.
 inline Batch make_batch(const std::vector<const Dev*>& dd, const std::vector<int64_t>& work, int tpb) {
     Batch B{};

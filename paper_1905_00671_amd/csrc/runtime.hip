@@ -19,6 +19,58 @@ using namespace ppm;
 
 static thread_local std::string g_err;
 
+// ---------------------------------------------------------------------------------------------
+// per-kernel timing: HIP events recorded on the launching stream around instrumented launches
+// ---------------------------------------------------------------------------------------------
+namespace ppm {
+namespace {
+struct PendingEv {
+    int id;
+    hipEvent_t a, b;
+};
+bool g_timing = false;
+std::vector<PendingEv> g_pending;
+std::vector<hipEvent_t> g_pool;
+int64_t g_count[KT_COUNT] = {};
+double g_ms[KT_COUNT] = {};
+
+hipEvent_t pool_get() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void timing_collect() {
+    for (auto& p : g_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g_count[p.id] += 1;
+            g_ms[p.id] += ms;
+        }
+        g_pool.push_back(p.a);
+        g_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+}  // namespace
+
+bool timing_on() { return g_timing; }
+
+void timing_begin(hipStream_t st, int id, hipEvent_t* a, hipEvent_t* b) {
+    *a = pool_get();
+    *b = pool_get();
+    (void)hipEventRecord(*a, st);
+    g_pending.push_back({id, *a, *b});
+}
+
+void timing_end(hipStream_t st, hipEvent_t b) { (void)hipEventRecord(b, st); }
+}  // namespace ppm
+
 static ppmpm_status fail(ppmpm_status s, const std::string& msg) {
     g_err = msg;
     return s;
@@ -628,6 +680,7 @@ ppmpm_status ppmpm_step_batched(ppmpm_problem* const* probs, int nprob, const do
             if (ns[k].status != PPMPM_OK && first_err == PPMPM_OK) first_err = (ppmpm_status)ns[k].status;
         }
     }
+    if (ppm::g_timing) ppm::timing_collect();
     auto tend = clk::now();
     for (int i = 0; i < nprob; ++i) {
         S[i].t_total = secs(t0, tend);
@@ -732,5 +785,28 @@ ppmpm_status ppmpm_destroy(ppmpm_problem* p) {
 }
 
 const char* ppmpm_last_error(void) { return g_err.c_str(); }
+
+ppmpm_status ppmpm_timing_enable(int on) {
+    ppm::timing_collect();
+    ppm::g_timing = on != 0;
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_timing_reset(void) {
+    ppm::timing_collect();
+    for (int i = 0; i < KT_COUNT; ++i) {
+        ppm::g_count[i] = 0;
+        ppm::g_ms[i] = 0.0;
+    }
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_timing_get(int kernel, int64_t* launches, double* total_ms) {
+    if (kernel < 0 || kernel >= KT_COUNT || !launches || !total_ms) return fail(PPMPM_E_INVALID, "bad kernel id");
+    ppm::timing_collect();
+    *launches = ppm::g_count[kernel];
+    *total_ms = ppm::g_ms[kernel];
+    return PPMPM_OK;
+}
 
 }  // extern "C"

@@ -159,7 +159,7 @@ def test_batched_equals_alone():
     problems stepped alone."""
     B = _binding()
     ws = [W.consolidation2d(12, 1e-12, nsteps=2), W.consolidation2d(20, 1e-14, nsteps=2),
-          W.config(3, nx=16, ny=8, width=1.0, empty_rows=2, nsteps=2)]
+          W.config(3, nx=16, ny=8, width=4.0, empty_rows=2, nsteps=2)]
     alone = []
     for w in ws:
         p = B.Problem.from_workload(w)
@@ -190,6 +190,32 @@ def test_transactional_failure_leaves_state():
         x0 = p.get("x").copy()
         st = p.step(w.dt, w.bc(1), raise_on_error=False)
         assert st["status"] == B.E_NEWTON
+        assert np.array_equal(p.get("x"), x0)
+    finally:
+        p.close()
+
+
+def test_failure_parity_overconstrained():
+    """A rigid footing as wide as an undrained, laterally confined box forces a volume change the
+    incompressible mixture cannot take: the oracle inverts a material point, and the HIP path
+    reports PPMPM_E_NONFINITE (or E_NEWTON) and leaves the state unchanged."""
+    B = _binding()
+    w = W.config(3, nx=16, ny=8, width=1.0, empty_rows=2, nsteps=2)
+    pr = O.from_workload(w)
+    with pytest.raises(O.NewtonFailure):
+        for n in (1, 2):
+            pr.step(w.dt, w.bc(n))
+    p = B.Problem.from_workload(w)
+    try:
+        x0 = p.get("x").copy()
+        status = 0
+        for n in (1, 2):
+            st = p.step(w.dt, w.bc(n), raise_on_error=False)
+            status = st["status"]
+            if status:
+                break
+            x0 = p.get("x").copy()
+        assert status in (B.E_NONFINITE, B.E_NEWTON)
         assert np.array_equal(p.get("x"), x0)
     finally:
         p.close()
