@@ -192,6 +192,9 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--calibrate-mb", type=int, default=0,
+                    help="before the run, stream a float32 tensor of this many MiB through one elementwise "
+                         "kernel (read once, write once): the reference for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one MI355X: --gpus {args.gpus} is not supported (this build runs the hot path "
@@ -201,6 +204,14 @@ def main():
     assert torch.cuda.is_available(), "a GPU is required"
     from paper_1905_00671_amd import binding as B
     B.lib()
+    if args.calibrate_mb > 0:
+        a = torch.ones(args.calibrate_mb * 262144, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        b = a.mul(2.0)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {a.numel() * 4} bytes read, {b.numel() * 4} bytes written",
+              file=sys.stderr, flush=True)
+        del a, b
     w = workload()
     bcs = device_bcs(w, range(1, args.warmup + args.steps + 1))
     res = {}

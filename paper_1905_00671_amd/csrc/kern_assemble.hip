@@ -3,13 +3,14 @@
 // Two passes per Newton iteration:
 //   k_records   one thread per (sorted) material point: basis at x_n, relative deformation
 //               dF = 1 + sum U (x) grad_n S, stress, tangent and every per-point coefficient the
-//               residual and the Jacobian need ("quadrature record", SoA in HBM);
-//   k_residual  one thread per grid node: gathers R_i from the points whose basis reaches node i
-//               (no atomics, fixed summation order), applies the boundary conditions and writes
-//               per-block partial norms;
-//   k_jacobian  one thread per (grid node i, stencil neighbour k): gathers the 3x3 / 4x4 block
-//               J_ik from the points shared by both nodes and writes it once into the
-//               fixed-stencil block rows (no atomics).
+//               residual and the Jacobian need (one contiguous "quadrature record" per point);
+//   k_residual  one thread per grid node (blocks cover 16x16 / 8x8x4 node tiles): gathers R_i
+//               from the points whose basis reaches node i (no atomics, fixed summation order),
+//               applies the boundary conditions and writes per-block partial norms;
+//   k_jacobian  one thread per (grid node i, row component, column component), the component
+//               pair uniform per block: for each point reaching node i, the entries of all its
+//               column blocks J_ik come from one set of record loads; the node's fixed-stencil
+//               block row is accumulated in registers and written once (no atomics).
 // Residual terms (current configuration, dv = det(dF) V_n, grad S = dF^{-T} grad_n S):
 //   R_mom_i  = -(V_n/J_n) tau' grad S_i + dv p^h grad S_i + m S_i (g - a^h)       eq. residual-momentum
 //   R_mass_i = dv S_i theta + dv kappa grad S_i.(grad p^h - rho_f (g - a^h))       eq. residual-mass
@@ -39,7 +40,7 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     const double* P = d->pw;
     const int64_t s = d->ps, Np = d->Np;
     const int64_t i = tid;
-    double* rec = d->rec;
+    double* rec = d->rec + i * L::N;
     double w[DIM][3], dw[DIM][3], s0v[DIM][3];
     int base[3] = {0, 0, 0};
     for (int a = 0; a < DIM; ++a) {
@@ -47,9 +48,9 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
                                   dw[a], s0v[a]);
         d->rbase[a * Np + i] = base[a];
         for (int k = 0; k < WB; ++k) {
-            rec[(L::W_ + a * WB + k) * Np + i] = w[a][k];
-            rec[(L::DW_ + a * WB + k) * Np + i] = dw[a][k];
-            rec[(L::S0_ + a * WB + k) * Np + i] = s0v[a][k];
+            rec[L::W_ + a * WB + k] = w[a][k];
+            rec[L::DW_ + a * WB + k] = dw[a][k];
+            rec[L::S0_ + a * WB + k] = s0v[a][k];
         }
     }
     int64_t cid = 0;
@@ -150,71 +151,62 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
                     if (bb == c) v += V0 * tau[a * DIM + e];
                     if (a == bb && c == e) v += dv * ph;
                     if (a == e && bb == c) v -= dv * ph;
-                    rec[(L::AB_ + ((a * DIM + bb) * DIM + c) * DIM + e) * Np + i] = v;
+                    rec[L::AB_ + ((a * DIM + bb) * DIM + c) * DIM + e] = v;
                 }
     for (int k = 0; k < DIM * DIM; ++k) {
-        rec[(L::FI_ + k) * Np + i] = f[k];
-        rec[(L::LV_ + k) * Np + i] = dyn ? dv * l[k] : 0.0;
+        rec[L::FI_ + k] = f[k];
+        rec[L::LV_ + k] = dyn ? dv * l[k] : 0.0;
         int a = k / DIM, c = k % DIM;
-        rec[(L::SG_ + k) * Np + i] = -V0 * tau[k] + (a == c ? dv * ph : 0.0);
+        rec[L::SG_ + k] = -V0 * tau[k] + (a == c ? dv * ph : 0.0);
     }
-    rec[L::DV_ * Np + i] = dv;
-    rec[L::CM_ * Np + i] = dyn ? m / (be * dt * dt) : 0.0;
-    rec[L::BV_ * Np + i] = dyn ? dv * (theta + ga / (be * dt)) : dv * (1.0 + log(dJ)) / dt;
-    rec[L::DK_ * Np + i] = dv * d->kappa;
+    rec[L::DV_] = dv;
+    rec[L::CM_] = dyn ? m / (be * dt * dt) : 0.0;
+    rec[L::BV_] = dyn ? dv * (theta + ga / (be * dt)) : dv * (1.0 + log(dJ)) / dt;
+    rec[L::DK_] = dv * d->kappa;
     for (int a = 0; a < DIM; ++a) {
-        rec[(L::GP_ + a) * Np + i] = gp[a];
-        rec[(L::QW_ + a) * Np + i] = wv[a];
-        rec[(L::BF_ + a) * Np + i] = m * (d->g[a] - ah[a]);
+        rec[L::GP_ + a] = gp[a];
+        rec[L::QW_ + a] = wv[a];
+        rec[L::BF_ + a] = m * (d->g[a] - ah[a]);
     }
-    rec[L::EE_ * Np + i] = dyn ? dv * d->kappa * d->rho_f / (be * dt * dt) : 0.0;
-    rec[L::TC_ * Np + i] = d->tau * d->ct * Vn;
-    rec[L::DT_ * Np + i] = dv * theta;
-    rec[L::ST_ * Np + i] = d->tau * Vn * pst;
+    rec[L::EE_] = dyn ? dv * d->kappa * d->rho_f / (be * dt * dt) : 0.0;
+    rec[L::TC_] = d->tau * d->ct * Vn;
+    rec[L::DT_] = dv * theta;
+    rec[L::ST_] = d->tau * Vn * pst;
 }
 
-// S, grad_n S of node (li) from a record, for a point with window-local node index li[]
-template <int DIM, int WB>
-__device__ __forceinline__ void rec_basis(const double* __restrict__ rec, int64_t Np, int64_t p,
-                                          const int* li, double& Sv, double* G, double& s0) {
-    using L = RecLayout<DIM, WB>;
-    double w[DIM], dw[DIM];
-    Sv = 1.0;
-    s0 = 1.0;
-    for (int a = 0; a < DIM; ++a) {
-        w[a] = rec[(L::W_ + a * WB + li[a]) * Np + p];
-        dw[a] = rec[(L::DW_ + a * WB + li[a]) * Np + p];
-        s0 *= rec[(L::S0_ + a * WB + li[a]) * Np + p];
-        Sv *= w[a];
-    }
-    for (int a = 0; a < DIM; ++a) {
-        double g = 1.0;
-        for (int c = 0; c < DIM; ++c) g *= (c == a) ? dw[c] : w[c];
-        G[a] = g;
-    }
-}
-
+// Node of tile lane t: blocks cover tiles of TILE_X x TILE_Y (x TILE_Z) nodes so that the
+// lanes of a wavefront gather from overlapping particle sets.
 template <int DIM>
-__device__ __forceinline__ void node_coords(const Dev* d, int64_t row, int* n) {
-    n[0] = (int)(row % d->nn[0]);
-    n[1] = (int)((row / d->nn[0]) % d->nn[1]);
-    n[2] = DIM == 3 ? (int)(row / ((int64_t)d->nn[0] * d->nn[1])) : 0;
+__device__ __forceinline__ bool tile_node(const Dev* d, int64_t tile, int t, int* n, int64_t* row) {
+    constexpr int tx = DIM == 2 ? TILE2X : TILE3X, ty = DIM == 2 ? TILE2Y : TILE3Y;
+    const int ntx = (d->nn[0] + tx - 1) / tx, nty = (d->nn[1] + ty - 1) / ty;
+    const int64_t bx = tile % ntx, by = (tile / ntx) % nty, bz = tile / ((int64_t)ntx * nty);
+    n[0] = (int)(bx * tx + t % tx);
+    n[1] = (int)(by * ty + (t / tx) % ty);
+    n[2] = DIM == 3 ? (int)(bz * TILE3Z + t / (tx * ty)) : 0;
+    for (int a = 0; a < DIM; ++a)
+        if (n[a] >= d->nn[a]) return false;
+    *row = n[0] + (int64_t)d->nn[0] * (n[1] + (int64_t)d->nn[1] * n[2]);
+    return true;
 }
 
 template <int DIM, int SHAPE>
 __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
-    PROB_PROLOGUE
+    const int q = batch_find(B, blockIdx.x);
+    const Dev* __restrict__ d = B.d[q];
+    const int64_t lb = blockIdx.x - B.pfx[q];
     constexpr int WB = SHAPE ? 3 : 2;
     using L = RecLayout<DIM, WB>;
     const int bs = DIM + 1;
     double ru2 = 0.0, rp2 = 0.0;
     bool bad = false;
-    if (tid < d->Nnode) {
-        int n[3];
-        node_coords<DIM>(d, tid, n);
+    int n[3];
+    int64_t row;
+    if (tile_node<DIM>(d, lb, threadIdx.x, n, &row)) {
         const int64_t pn = pad_index(d, n[0], n[1], n[2]);
-        const double* __restrict__ rec = d->rec;
         const int64_t Np = d->Np;
+        // cells holding points whose window reaches node n (a GIMP window starts at the point's
+        // cell or the one left of it)
         int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
         for (int a = 0; a < DIM; ++a) {
             clo[a] = max(n[a] - (SHAPE ? 2 : 1), 0);
@@ -222,29 +214,41 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
         }
         double r[DIM + 1];
         for (int c = 0; c <= DIM; ++c) r[c] = 0.0;
-        for (int cz = (DIM == 3 ? clo[2] : 0); cz <= (DIM == 3 ? chi[2] : 0); ++cz)
+        for (int cz = clo[2]; cz <= chi[2]; ++cz)
             for (int cy = clo[1]; cy <= chi[1]; ++cy) {
-                int64_t rowc = (int64_t)d->nc[0] * (cy + (int64_t)d->nc[1] * cz);
-                int p0 = d->cstart[rowc + clo[0]], p1 = d->cstart[rowc + chi[0] + 1];
+                const int64_t rowc = (int64_t)d->nc[0] * (cy + (int64_t)d->nc[1] * cz);
+                const int p0 = d->cstart[rowc + clo[0]], p1 = d->cstart[rowc + chi[0] + 1];
                 for (int p = p0; p < p1; ++p) {
-                    int li[3] = {0, 0, 0};
+                    int li[3] = {0, 0, 0}, bse[3] = {0, 0, 0};
                     bool in = true;
                     for (int a = 0; a < DIM; ++a) {
-                        li[a] = n[a] - d->rbase[a * Np + p];
+                        bse[a] = d->rbase[a * Np + p];
+                        li[a] = n[a] - bse[a];
                         if (li[a] < 0 || li[a] >= WB) in = false;
                     }
                     if (!in) continue;
-                    double Sv, G[DIM], s0;
-                    rec_basis<DIM, WB>(rec, Np, p, li, Sv, G, s0);
-                    double gS[DIM];
+                    const double* __restrict__ rc = d->rec + (int64_t)p * L::N;
+                    double w[DIM], dw[DIM], Sv = 1.0, s0 = 1.0;
+                    for (int a = 0; a < DIM; ++a) {
+                        w[a] = rc[L::W_ + a * WB + li[a]];
+                        dw[a] = rc[L::DW_ + a * WB + li[a]];
+                        if (SHAPE) s0 *= rc[L::S0_ + a * WB + li[a]];
+                        Sv *= w[a];
+                    }
+                    double G[DIM], gS[DIM];
+                    for (int a = 0; a < DIM; ++a) {
+                        double g = 1.0;
+                        for (int c = 0; c < DIM; ++c) g *= (c == a) ? dw[c] : w[c];
+                        G[a] = g;
+                    }
                     for (int a = 0; a < DIM; ++a) {
                         double t = 0.0;
-                        for (int c = 0; c < DIM; ++c) t += rec[(L::FI_ + c * DIM + a) * Np + p] * G[c];
+                        for (int c = 0; c < DIM; ++c) t += rc[L::FI_ + c * DIM + a] * G[c];
                         gS[a] = t;
                     }
                     for (int a = 0; a < DIM; ++a) {
-                        double t = rec[(L::BF_ + a) * Np + p] * Sv;
-                        for (int c = 0; c < DIM; ++c) t += rec[(L::SG_ + a * DIM + c) * Np + p] * gS[c];
+                        double t = rc[L::BF_ + a] * Sv;
+                        for (int c = 0; c < DIM; ++c) t += rc[L::SG_ + a * DIM + c] * gS[c];
                         r[a] += t;
                     }
                     double Pi;
@@ -253,15 +257,15 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
                     } else {
                         int64_t cid = 0, mul = 1, lin = 0;
                         for (int a = 0; a < DIM; ++a) {
-                            cid += d->rbase[a * Np + p] * mul;
+                            cid += bse[a] * mul;
                             mul *= d->nc[a];
                             lin += (int64_t)li[a] << a;
                         }
                         Pi = d->cellpi[cid * (1 << DIM) + lin];
                     }
                     double gw = 0.0;
-                    for (int a = 0; a < DIM; ++a) gw += gS[a] * rec[(L::QW_ + a) * Np + p];
-                    r[DIM] += Sv * rec[L::DT_ * Np + p] + rec[L::DK_ * Np + p] * gw + rec[L::ST_ * Np + p] * (Sv - Pi);
+                    for (int a = 0; a < DIM; ++a) gw += gS[a] * rc[L::QW_ + a];
+                    r[DIM] += Sv * rc[L::DT_] + rc[L::DK_] * gw + rc[L::ST_] * (Sv - Pi);
                 }
             }
         for (int c = 0; c <= DIM; ++c) {
@@ -292,140 +296,230 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
     }
 }
 
-// Jacobian block J_ik for row node i and stencil neighbour k = i + offset(blockIdx.y).
-template <int DIM, int SHAPE, typename T>
-__global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
-    PROB_PROLOGUE
-    if (tid >= d->Nnode) return;
+// Contribution of one point to the (ca, cc) entries of row node i, for every column node k of
+// the point's window; LI is node i's window-local index (compile-time, so that the stencil slot
+// of each k is a constant and the accumulators stay in registers).  With gi = dF^{-T} grad_n S_i,
+// gk likewise, the (ca, cc) entry of J_ik is
+//   ca, cc <  dim : gi . Abar_{ca . cc .} gk - d_ac m/(beta dt^2) S_i S_k
+//   ca <  dim = cc: dv S_k gi_ca
+//   ca = dim > cc : S_i (bv gk_cc - (LV^T gk)_cc) + dv kappa (gk_cc gi.w - gi_cc gk.w - gi.gk gp_cc)
+//                   + dv kappa rho_f/(beta dt^2) gi_cc S_k
+//   ca = cc = dim : dv kappa gi.gk + tau c_t V_n (S_i - Pi_i)(S_k - Pi_k)
+// each written as u . gk + alpha S_k - gamma Pi_k = (f u) . grad_n S_k + alpha S_k - gamma Pi_k.
+template <int DIM, int SHAPE, int LI>
+__device__ __forceinline__ void jac_point(const Dev* __restrict__ d, const double* __restrict__ rc, int64_t cid,
+                                          int ca, int cc, double* acc) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int RR = SHAPE ? 2 : 1;
     constexpr int SW = 2 * RR + 1;
+    constexpr int NN = DIM == 2 ? WB * WB : WB * WB * WB;
+    constexpr int li[3] = {LI % WB, (LI / WB) % WB, DIM == 3 ? LI / (WB * WB) : 0};
+    using L = RecLayout<DIM, WB>;
+    double w[DIM][WB], dw[DIM][WB];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int k = 0; k < WB; ++k) {
+            w[a][k] = rc[L::W_ + a * WB + k];
+            dw[a][k] = rc[L::DW_ + a * WB + k];
+        }
+    double Si = 1.0, Gi[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) Si *= w[a][li[a]];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double g = 1.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) g *= (c == a) ? dw[c][li[c]] : w[c][li[c]];
+        Gi[a] = g;
+    }
+    double f[DIM * DIM], gi[DIM];
+#pragma unroll
+    for (int e = 0; e < DIM * DIM; ++e) f[e] = rc[L::FI_ + e];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) t += f[c * DIM + a] * Gi[c];
+        gi[a] = t;
+    }
+    double u[DIM], alpha = 0.0, gamma = 0.0, pik[NN];
+#pragma unroll
+    for (int k = 0; k < NN; ++k) pik[k] = 0.0;
+    const bool ppp = ca == DIM && cc == DIM;
+    if (ca < DIM && cc < DIM) {
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+            double t = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < DIM; ++bb) t += gi[bb] * rc[L::AB_ + ((ca * DIM + bb) * DIM + cc) * DIM + e];
+            u[e] = t;
+        }
+        if (ca == cc) alpha = -rc[L::CM_] * Si;
+    } else if (ca < DIM) {
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) u[e] = 0.0;
+        alpha = rc[L::DV_] * gi[ca];
+    } else if (cc < DIM) {
+        const double bv = rc[L::BV_], dk = rc[L::DK_];
+        double qw[DIM], giq = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+            qw[e] = rc[L::QW_ + e];
+            giq += gi[e] * qw[e];
+        }
+        const double gpc = rc[L::GP_ + cc];
+        double gic = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) gic += (e == cc) ? gi[e] : 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e)
+            u[e] = Si * ((e == cc ? bv : 0.0) - rc[L::LV_ + e * DIM + cc]) +
+                   dk * ((e == cc ? giq : 0.0) - gic * qw[e] - gi[e] * gpc);
+        alpha = rc[L::EE_] * gic;
+    } else {
+        const double dk = rc[L::DK_];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) u[e] = dk * gi[e];
+        if (SHAPE) {
+            double s0[DIM][WB];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int k = 0; k < WB; ++k) s0[a][k] = rc[L::S0_ + a * WB + k];
+#pragma unroll
+            for (int k = 0; k < NN; ++k) {
+                const int lk[3] = {k % WB, (k / WB) % WB, DIM == 3 ? k / (WB * WB) : 0};
+                double v = 1.0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) v *= s0[a][lk[a]];
+                pik[k] = v;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NN; ++k) pik[k] = d->cellpi[cid * NN + k];
+        }
+        // Pi of the row node: the window index LI in the basis order of S0 / the cell's corner
+        // order (x fastest, two nodes per axis), which coincide for WB = 2
+        gamma = rc[L::TC_] * (Si - pik[LI]);
+        alpha = gamma;
+    }
+    double ut[DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) t += f[m * DIM + e] * u[e];
+        ut[m] = t;
+    }
+#pragma unroll
+    for (int kz = 0; kz < (DIM == 3 ? WB : 1); ++kz)
+#pragma unroll
+        for (int ky = 0; ky < WB; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < WB; ++kx) {
+                const int s = (kx - li[0] + RR) + SW * (ky - li[1] + RR) +
+                              (DIM == 3 ? SW * SW * (kz - li[2] + RR) : 0);
+                const int kk = kx + WB * (ky + WB * kz);
+                double val;
+                if constexpr (DIM == 2) {
+                    val = ut[0] * dw[0][kx] * w[1][ky] + ut[1] * w[0][kx] * dw[1][ky] + alpha * w[0][kx] * w[1][ky];
+                } else {
+                    val = ut[0] * dw[0][kx] * w[1][ky] * w[2][kz] + ut[1] * w[0][kx] * dw[1][ky] * w[2][kz] +
+                          ut[2] * w[0][kx] * w[1][ky] * dw[2][kz] + alpha * w[0][kx] * w[1][ky] * w[2][kz];
+                }
+                if (ppp) val -= gamma * pik[kk];
+                acc[s] += val;
+            }
+}
+
+template <int DIM, int SHAPE, int LI>
+__device__ __forceinline__ void jac_case(const Dev* d, const double* rc, int64_t cid, int ca, int cc, double* acc) {
+    constexpr int WB = SHAPE ? 3 : 2;
+    constexpr int NN = DIM == 2 ? WB * WB : WB * WB * WB;
+    if constexpr (LI < NN) jac_point<DIM, SHAPE, LI>(d, rc, cid, ca, cc, acc);
+}
+
+// Jacobian, one thread per (row node, ca, cc): grid = (node tiles, b*b), blockIdx.y = ca*b + cc.
+// The node's block row over the fixed stencil is accumulated in registers and written once,
+// with the rows and columns of constrained dofs replaced by identity rows.
+template <int DIM, int SHAPE, typename T>
+__global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
+    const int q = batch_find(B, blockIdx.x);
+    const Dev* __restrict__ d = B.d[q];
+    const int64_t lb = blockIdx.x - B.pfx[q];
+    constexpr int WB = SHAPE ? 3 : 2;
+    constexpr int RR = SHAPE ? 2 : 1;
+    constexpr int SW = 2 * RR + 1;
+    constexpr int S = DIM == 2 ? SW * SW : SW * SW * SW;
     constexpr int BS = DIM + 1;
     using L = RecLayout<DIM, WB>;
-    const int sidx = blockIdx.y;
-    int off[3] = {sidx % SW - RR, (sidx / SW) % SW - RR, DIM == 3 ? sidx / (SW * SW) - RR : 0};
-    int n[3], k[3];
-    node_coords<DIM>(d, tid, n);
-    bool valid = true;
+    const int ca = blockIdx.y / BS, cc = blockIdx.y % BS;
+    int n[3];
+    int64_t row;
+    if (!tile_node<DIM>(d, lb, threadIdx.x, n, &row)) return;
+    double acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = 0.0;
+    const int64_t Np = d->Np;
+    int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
     for (int a = 0; a < DIM; ++a) {
-        k[a] = n[a] + off[a];
-        if (k[a] < 0 || k[a] >= d->nn[a]) valid = false;
+        clo[a] = max(n[a] - (SHAPE ? 2 : 1), 0);
+        chi[a] = min(n[a] + (SHAPE ? 1 : 0), d->nc[a] - 1);
     }
-    double blk[BS][BS];
-    for (int a = 0; a < BS; ++a)
-        for (int c = 0; c < BS; ++c) blk[a][c] = 0.0;
-    T* J = (T*)d->J;
-    const int64_t Nn = d->Nnode;
-    if (valid) {
-        const double* __restrict__ rec = d->rec;
-        const int64_t Np = d->Np;
-        int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
-        for (int a = 0; a < DIM; ++a) {
-            clo[a] = max(max(n[a], k[a]) - (SHAPE ? 2 : 1), 0);
-            chi[a] = min(min(n[a], k[a]) + (SHAPE ? 1 : 0), d->nc[a] - 1);
-        }
-        for (int cz = (DIM == 3 ? clo[2] : 0); cz <= (DIM == 3 ? chi[2] : 0); ++cz)
-            for (int cy = clo[1]; cy <= chi[1]; ++cy) {
-                if (clo[0] > chi[0]) continue;
-                int64_t rowc = (int64_t)d->nc[0] * (cy + (int64_t)d->nc[1] * cz);
-                int p0 = d->cstart[rowc + clo[0]], p1 = d->cstart[rowc + chi[0] + 1];
-                for (int p = p0; p < p1; ++p) {
-                    int li[3] = {0, 0, 0}, lk[3] = {0, 0, 0};
-                    bool in = true;
-                    for (int a = 0; a < DIM; ++a) {
-                        int bse = d->rbase[a * Np + p];
-                        li[a] = n[a] - bse;
-                        lk[a] = k[a] - bse;
-                        if (li[a] < 0 || li[a] >= WB || lk[a] < 0 || lk[a] >= WB) in = false;
-                    }
-                    if (!in) continue;
-                    double Si, Sk, Gi[DIM], Gk[DIM], s0i, s0k;
-                    rec_basis<DIM, WB>(rec, Np, p, li, Si, Gi, s0i);
-                    rec_basis<DIM, WB>(rec, Np, p, lk, Sk, Gk, s0k);
-                    double fi[DIM * DIM];
-                    for (int e = 0; e < DIM * DIM; ++e) fi[e] = rec[(L::FI_ + e) * Np + p];
-                    double gi[DIM], gk[DIM];
-                    for (int a = 0; a < DIM; ++a) {
-                        double t1 = 0.0, t2 = 0.0;
-                        for (int c = 0; c < DIM; ++c) {
-                            t1 += fi[c * DIM + a] * Gi[c];
-                            t2 += fi[c * DIM + a] * Gk[c];
-                        }
-                        gi[a] = t1;
-                        gk[a] = t2;
-                    }
-                    // displacement-displacement block
-                    const double cm = rec[L::CM_ * Np + p];
-                    for (int a = 0; a < DIM; ++a)
-                        for (int c = 0; c < DIM; ++c) {
-                            double t = 0.0;
-                            for (int bb = 0; bb < DIM; ++bb) {
-                                double u = 0.0;
-                                for (int e = 0; e < DIM; ++e)
-                                    u += rec[(L::AB_ + ((a * DIM + bb) * DIM + c) * DIM + e) * Np + p] * gk[e];
-                                t += gi[bb] * u;
-                            }
-                            if (a == c) t -= cm * Si * Sk;
-                            blk[a][c] += t;
-                        }
-                    // displacement-pressure
-                    const double dvp = rec[L::DV_ * Np + p];
-                    for (int a = 0; a < DIM; ++a) blk[a][DIM] += dvp * Sk * gi[a];
-                    // pressure-displacement
-                    const double bv = rec[L::BV_ * Np + p], dk = rec[L::DK_ * Np + p], ee = rec[L::EE_ * Np + p];
-                    double qw[DIM], gpv[DIM];
-                    for (int a = 0; a < DIM; ++a) {
-                        qw[a] = rec[(L::QW_ + a) * Np + p];
-                        gpv[a] = rec[(L::GP_ + a) * Np + p];
-                    }
-                    double giq = 0.0, gkq = 0.0, gik = 0.0;
-                    for (int a = 0; a < DIM; ++a) {
-                        giq += gi[a] * qw[a];
-                        gkq += gk[a] * qw[a];
-                        gik += gi[a] * gk[a];
-                    }
-                    for (int c = 0; c < DIM; ++c) {
-                        double lt = 0.0;
-                        for (int a = 0; a < DIM; ++a) lt += gk[a] * rec[(L::LV_ + a * DIM + c) * Np + p];
-                        blk[DIM][c] += Si * (bv * gk[c] - lt) + dk * (gk[c] * giq - gi[c] * gkq - gik * gpv[c]) +
-                                       ee * gi[c] * Sk;
-                    }
-                    // pressure-pressure with the PPP term
-                    double Pii, Pik;
-                    if (SHAPE) {
-                        Pii = s0i;
-                        Pik = s0k;
-                    } else {
-                        int64_t cid = 0, mul = 1, lin_i = 0, lin_k = 0;
-                        for (int a = 0; a < DIM; ++a) {
-                            cid += d->rbase[a * Np + p] * mul;
-                            mul *= d->nc[a];
-                            lin_i += (int64_t)li[a] << a;
-                            lin_k += (int64_t)lk[a] << a;
-                        }
-                        Pii = d->cellpi[cid * (1 << DIM) + lin_i];
-                        Pik = d->cellpi[cid * (1 << DIM) + lin_k];
-                    }
-                    blk[DIM][DIM] += dk * gik + rec[L::TC_ * Np + p] * (Si - Pii) * (Sk - Pik);
+    for (int cz = clo[2]; cz <= chi[2]; ++cz)
+        for (int cy = clo[1]; cy <= chi[1]; ++cy) {
+            const int64_t rowc = (int64_t)d->nc[0] * (cy + (int64_t)d->nc[1] * cz);
+            const int p0 = d->cstart[rowc + clo[0]], p1 = d->cstart[rowc + chi[0] + 1];
+            for (int p = p0; p < p1; ++p) {
+                int li[3] = {0, 0, 0};
+                int64_t cid = 0, mul = 1;
+                bool in = true;
+                for (int a = 0; a < DIM; ++a) {
+                    const int bse = d->rbase[a * Np + p];
+                    li[a] = n[a] - bse;
+                    if (li[a] < 0 || li[a] >= WB) in = false;
+                    cid += bse * mul;
+                    mul *= d->nc[a];
+                }
+                if (!in) continue;
+                const double* rc = d->rec + (int64_t)p * L::N;
+                switch (li[0] + WB * (li[1] + WB * li[2])) {
+                    case 0: jac_case<DIM, SHAPE, 0>(d, rc, cid, ca, cc, acc); break;
+                    case 1: jac_case<DIM, SHAPE, 1>(d, rc, cid, ca, cc, acc); break;
+                    case 2: jac_case<DIM, SHAPE, 2>(d, rc, cid, ca, cc, acc); break;
+                    case 3: jac_case<DIM, SHAPE, 3>(d, rc, cid, ca, cc, acc); break;
+                    case 4: jac_case<DIM, SHAPE, 4>(d, rc, cid, ca, cc, acc); break;
+                    case 5: jac_case<DIM, SHAPE, 5>(d, rc, cid, ca, cc, acc); break;
+                    case 6: jac_case<DIM, SHAPE, 6>(d, rc, cid, ca, cc, acc); break;
+                    case 7: jac_case<DIM, SHAPE, 7>(d, rc, cid, ca, cc, acc); break;
+                    case 8: jac_case<DIM, SHAPE, 8>(d, rc, cid, ca, cc, acc); break;
+                    default: break;
                 }
             }
-    }
-    int64_t pni = 0, pnk = 0;
-    if (valid) {
-        pni = pad_index(d, n[0], n[1], n[2]);
-        pnk = pad_index(d, k[0], k[1], k[2]);
-    }
-    const bool diag = valid && (sidx == (d->S - 1) / 2);
-    for (int a = 0; a < BS; ++a)
-        for (int c = 0; c < BS; ++c) {
-            double v = blk[a][c];
-            if (valid) {
-                bool fr = d->dfree[pni * BS + a] != 0;
-                bool fc = d->dfree[pnk * BS + c] != 0;
-                if (!(fr && fc)) v = (diag && a == c) ? 1.0 : 0.0;
-            }
-            J[((int64_t)(sidx * BS + a) * BS + c) * Nn + tid] = (T)v;
         }
+    const int64_t pni = pad_index(d, n[0], n[1], n[2]);
+    const bool fr = d->dfree[pni * BS + ca] != 0;
+    T* J = (T*)d->J;
+    const int64_t Nn = d->Nnode;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int off[3] = {s % SW - RR, (s / SW) % SW - RR, DIM == 3 ? s / (SW * SW) - RR : 0};
+        bool valid = true;
+        int k[3] = {0, 0, 0};
+        for (int a = 0; a < DIM; ++a) {
+            k[a] = n[a] + off[a];
+            if (k[a] < 0 || k[a] >= d->nn[a]) valid = false;
+        }
+        double v = 0.0;
+        if (valid) {
+            v = acc[s];
+            const int64_t pnk = pad_index(d, k[0], k[1], k[2]);
+            const bool fc = d->dfree[pnk * BS + cc] != 0;
+            if (!(fr && fc)) v = (s == (S - 1) / 2 && ca == cc) ? 1.0 : 0.0;
+        }
+        J[((int64_t)(s * BS + ca) * BS + cc) * Nn + row] = (T)v;
+    }
 }
 
 // sum of the residual partials of each problem (one block per problem)
@@ -434,7 +528,7 @@ __global__ void k_finalize_norms(Batch B) {
     const Dev* d = B.d[q];
     __shared__ double sh[2][TPB];
     double a = 0.0, b2 = 0.0;
-    const int64_t nblk = (d->Nnode + TPB - 1) / TPB;   // blocks of k_residual for this problem
+    const int64_t nblk = B.pfx[q + 1] - B.pfx[q];   // blocks of k_residual for this problem
     for (int64_t i = threadIdx.x; i < nblk; i += TPB) {
         a += d->partial[i * 4 + 0];
         b2 += d->partial[i * 4 + 1];
@@ -458,7 +552,7 @@ __global__ void k_finalize_norms(Batch B) {
 // ---------------------------------------------------------------------------------------------
 void launch_assemble(const Group& g, bool want_J, hipStream_t st) {
     Batch Bp = make_batch(g.ddev, g.np, TPB);
-    Batch Bn = make_batch(g.ddev, g.nnode, TPB);
+    Batch Bn = make_batch_blocks(g.ddev, g.ntile);
     if (g.dim == 2 && g.shape == 0) {
         PPM_TIMED(KT_RECORDS, st, hipLaunchKernelGGL((k_records<2, 0>), dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp));
         PPM_TIMED(KT_RESIDUAL, st, hipLaunchKernelGGL((k_residual<2, 0>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn));
@@ -474,8 +568,8 @@ void launch_assemble(const Group& g, bool want_J, hipStream_t st) {
 }
 
 void launch_jacobian(const Group& g, hipStream_t st) {
-    Batch Bn = make_batch(g.ddev, g.nnode, TPB);
-    const dim3 gr(Bn.pfx[Bn.n], g.S), tb(TPB);
+    Batch Bn = make_batch_blocks(g.ddev, g.ntile);
+    const dim3 gr(Bn.pfx[Bn.n], g.b * g.b), tb(TPB);
     if (g.dim == 2 && g.shape == 0) {
         if (g.mixed) PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 0, float>), gr, tb, 0, st, Bn));
         else PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 0, double>), gr, tb, 0, st, Bn));

@@ -1,0 +1,666 @@
+// Geometric multigrid for the two sub-blocks of the block upper-triangular preconditioner of
+// the Newton-Krylov solver (Sec. 3.4): family A (displacement block, dim x dim node blocks) and
+// family S (fixed-stress Schur approximation C + C_stab + (c_t/K) M_p, scalar).
+//
+// Hierarchy: the structured background grid, coarsened by two along every axis that still has
+// more than three nodes (semi-coarsening keeps elongated grids solvable); bilinear/trilinear
+// transfer; Galerkin coarse operators P^T A P built on the device; level-0 operators are views
+// into the stored Jacobian blocks (no copy).  Smoother: damped block Jacobi, V(nsm, nsm).
+// Coarsest level: dense inverse (Gauss-Jordan in LDS, at most CMAX unknowns).
+//
+// Launch structure: levels with more than TAILMAX nodes use one kernel per operation (pre-smooth
+// fused with the residual, restriction, prolongation, post-smooth); all smaller levels of a
+// problem run inside one block of a single "tail" kernel, which removes most of the launches of
+// a V-cycle.  Every kernel serves a whole batch of problems.
+#include "solver_common.hpp"
+#include "launch.hpp"
+
+namespace ppm {
+
+// 1D weight of fine node i from coarse node I: linear interpolation between the coarse
+// positions min(2I, nf - 1) (the last coarse node sits on the last fine node)
+__device__ __forceinline__ double pw1(int i, int I, int nf) {
+    if ((i & 1) == 0) return I == (i >> 1) ? 1.0 : 0.0;
+    int lo = (i - 1) >> 1, hi = lo + 1;
+    int phi = min(2 * hi, nf - 1);
+    if (phi == i) return I == hi ? 1.0 : 0.0;
+    return (I == lo || I == hi) ? 0.5 : 0.0;
+}
+// same, with the identity on axes that are not coarsened
+__device__ __forceinline__ double pwa(int i, int I, int nf, int cz) {
+    return cz ? pw1(i, I, nf) : (i == I ? 1.0 : 0.0);
+}
+// k-th fine candidate (k = 0, 1, 2) of coarse index I along one axis; -1 if none
+__device__ __forceinline__ int cand(int I, int k, int cz) { return cz ? 2 * I - 1 + k : (k == 1 ? I : -1); }
+
+template <int BB>
+__device__ __forceinline__ void invert_small(const double* A, double* Ai) {
+    if (BB == 1) {
+        Ai[0] = (A[0] == 0.0 || !isfinite(A[0])) ? 1.0 : 1.0 / A[0];
+        return;
+    }
+    double dt = BB == 2 ? det<2>(A) : det<3>(A);
+    if (dt == 0.0 || !isfinite(dt)) {
+        for (int i = 0; i < BB * BB; ++i) Ai[i] = (i % (BB + 1) == 0) ? 1.0 : 0.0;
+        return;
+    }
+    if (BB == 2) inverse<2>(A, Ai);
+    else inverse<3>(A, Ai);
+}
+
+// ---------------------------------------------------------------------------------------------
+// row operations (one grid node of one level)
+// ---------------------------------------------------------------------------------------------
+template <int BB, typename T>
+__device__ __forceinline__ void dinv_apply(const Dev* d, int fam, int l, int64_t row, const double* v, double* out) {
+    const MgLevel& L = d->lev[l];
+    const T* Di = (const T*)(fam == 0 ? L.Ad : L.Sd);
+    for (int a = 0; a < BB; ++a) {
+        double t = 0.0;
+        for (int c = 0; c < BB; ++c) t += (double)Di[(int64_t)(a * BB + c) * L.nrow + row] * v[c];
+        out[a] = t;
+    }
+}
+
+// x = omega Dinv rhs
+template <int BB, typename T>
+__device__ __forceinline__ void row_smooth0(const Dev* d, int fam, int l, int64_t row, View<T> rhs, View<T> x) {
+    const MgLevel& L = d->lev[l];
+    int c[3];
+    real_coords(row, L.n, d->dim, c);
+    int64_t pn = padded(c, L.np, d->R, d->dim);
+    double r[BB], y[BB];
+    for (int a = 0; a < BB; ++a) r[a] = (double)rhs.at(pn, a);
+    dinv_apply<BB, T>(d, fam, l, row, r, y);
+    for (int a = 0; a < BB; ++a) x.at(pn, a) = (T)(d->omega * y[a]);
+}
+
+// r = rhs - A x
+template <int BB, typename T>
+__device__ __forceinline__ void row_resid(const Dev* d, int fam, int l, int64_t row, View<T> rhs, View<T> x, View<T> r) {
+    const MgLevel& L = d->lev[l];
+    const int dim = d->dim, R = d->R;
+    int c[3];
+    real_coords(row, L.n, dim, c);
+    int64_t pn = padded(c, L.np, R, dim);
+    Op<T> o = op_of<T>(d, fam, l);
+    double acc[BB];
+    for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
+    for (int s = 0; s < d->S; ++s) {
+        int64_t pk = pn + stencil_offset(s, R, dim, L.np);
+        for (int cc = 0; cc < BB; ++cc) {
+            double xv = (double)x.at(pk, cc);
+            for (int a = 0; a < BB; ++a) acc[a] -= o.at(s, a, cc, row) * xv;
+        }
+    }
+    if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * (double)x.at(pn, 0);
+    for (int a = 0; a < BB; ++a) r.at(pn, a) = (T)acc[a];
+}
+
+// first sweep from a zero guess fused with the residual:
+//   x_i = omega Dinv_i rhs_i,   r_i = rhs_i - sum_k A_ik (omega Dinv_k rhs_k)
+template <int BB, typename T>
+__device__ __forceinline__ void row_pre(const Dev* d, int fam, int l, int64_t row, View<T> rhs, View<T> x, View<T> r) {
+    const MgLevel& L = d->lev[l];
+    const int dim = d->dim, R = d->R;
+    int c[3];
+    real_coords(row, L.n, dim, c);
+    int64_t pn = padded(c, L.np, R, dim);
+    Op<T> o = op_of<T>(d, fam, l);
+    const T* Di = (const T*)(fam == 0 ? L.Ad : L.Sd);
+    const int64_t stride_pad = 1;
+    (void)stride_pad;
+    double acc[BB], xi[BB];
+    for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
+    for (int s = 0; s < d->S; ++s) {
+        int off[3] = {0, 0, 0};
+        const int SW = 2 * R + 1;
+        off[0] = s % SW - R;
+        off[1] = (s / SW) % SW - R;
+        off[2] = dim == 3 ? s / (SW * SW) - R : 0;
+        int ck[3];
+        bool inside = true;
+        for (int a = 0; a < dim; ++a) {
+            ck[a] = c[a] + off[a];
+            if (ck[a] < 0 || ck[a] >= L.n[a]) inside = false;
+        }
+        if (!inside) continue;   // no coupling outside the grid
+        if (dim == 2) ck[2] = 0;
+        int64_t krow = ck[0] + (int64_t)L.n[0] * (ck[1] + (int64_t)L.n[1] * ck[2]);
+        int64_t pk = pn + stencil_offset(s, R, dim, L.np);
+        double bk[BB], xk[BB];
+        for (int a = 0; a < BB; ++a) bk[a] = (double)rhs.at(pk, a);
+        for (int a = 0; a < BB; ++a) {
+            double t = 0.0;
+            for (int cc = 0; cc < BB; ++cc) t += (double)Di[(int64_t)(a * BB + cc) * L.nrow + krow] * bk[cc];
+            xk[a] = d->omega * t;
+        }
+        if (s == (d->S - 1) / 2)
+            for (int a = 0; a < BB; ++a) xi[a] = xk[a];
+        for (int cc = 0; cc < BB; ++cc)
+            for (int a = 0; a < BB; ++a) acc[a] -= o.at(s, a, cc, row) * xk[cc];
+    }
+    if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * xi[0];
+    for (int a = 0; a < BB; ++a) {
+        x.at(pn, a) = (T)xi[a];
+        r.at(pn, a) = (T)acc[a];
+    }
+}
+
+// x += omega Dinv r
+template <int BB, typename T>
+__device__ __forceinline__ void row_update(const Dev* d, int fam, int l, int64_t row, View<T> x, View<T> r) {
+    const MgLevel& L = d->lev[l];
+    int c[3];
+    real_coords(row, L.n, d->dim, c);
+    int64_t pn = padded(c, L.np, d->R, d->dim);
+    double rr[BB], y[BB];
+    for (int a = 0; a < BB; ++a) rr[a] = (double)r.at(pn, a);
+    dinv_apply<BB, T>(d, fam, l, row, rr, y);
+    for (int a = 0; a < BB; ++a) x.at(pn, a) = (T)((double)x.at(pn, a) + d->omega * y[a]);
+}
+
+// coarse rhs of node I on level l+1 = (P^T r)_I (level-0 fine dofs masked by the free mask)
+template <int BB, typename T>
+__device__ __forceinline__ void row_restrict(const Dev* d, int fam, int l, int64_t Irow, View<T> r, View<T> bc) {
+    const MgLevel& F = d->lev[l];
+    const MgLevel& C = d->lev[l + 1];
+    const int dim = d->dim, R = d->R;
+    int I[3];
+    real_coords(Irow, C.n, dim, I);
+    double acc[BB];
+    for (int a = 0; a < BB; ++a) acc[a] = 0.0;
+    const int nI = dim == 3 ? 27 : 9;
+    for (int ii = 0; ii < nI; ++ii) {
+        int kk[3] = {ii % 3, (ii / 3) % 3, ii / 9};
+        int fi[3] = {0, 0, 0};
+        double w = 1.0;
+        for (int a = 0; a < dim; ++a) {
+            fi[a] = cand(I[a], kk[a], F.cz[a]);
+            if (fi[a] < 0 || fi[a] >= F.n[a]) { w = 0.0; break; }
+            w *= pwa(fi[a], I[a], F.n[a], F.cz[a]);
+        }
+        if (w == 0.0) continue;
+        int64_t fpn = padded(fi, F.np, R, dim);
+        for (int a = 0; a < BB; ++a) {
+            double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
+            acc[a] += w * m * (double)r.at(fpn, a);
+        }
+    }
+    int64_t cpn = padded(I, C.np, R, dim);
+    for (int a = 0; a < BB; ++a) bc.at(cpn, a) = (T)acc[a];
+}
+
+// x(fine node) += (P xc) (level-0 fine dofs masked)
+template <int BB, typename T>
+__device__ __forceinline__ void row_prolong(const Dev* d, int fam, int l, int64_t frow, View<T> xc, View<T> x) {
+    const MgLevel& F = d->lev[l];
+    const MgLevel& C = d->lev[l + 1];
+    const int dim = d->dim, R = d->R;
+    int fi[3];
+    real_coords(frow, F.n, dim, fi);
+    int64_t fpn = padded(fi, F.np, R, dim);
+    double acc[BB];
+    for (int a = 0; a < BB; ++a) acc[a] = 0.0;
+    const int nI = dim == 3 ? 8 : 4;
+    for (int jj = 0; jj < nI; ++jj) {
+        int I[3] = {0, 0, 0};
+        double w = 1.0;
+        for (int a = 0; a < dim; ++a) {
+            int bit = (jj >> a) & 1;
+            if (F.cz[a]) {
+                I[a] = (fi[a] >> 1) + bit;
+                if (I[a] >= C.n[a]) { w = 0.0; break; }
+                w *= pw1(fi[a], I[a], F.n[a]);
+            } else {
+                if (bit) { w = 0.0; break; }
+                I[a] = fi[a];
+            }
+        }
+        if (w == 0.0) continue;
+        int64_t cpn = padded(I, C.np, R, dim);
+        for (int a = 0; a < BB; ++a) acc[a] += w * (double)xc.at(cpn, a);
+    }
+    for (int a = 0; a < BB; ++a) {
+        double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
+        x.at(fpn, a) = (T)((double)x.at(fpn, a) + m * acc[a]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------------------------
+template <int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_dinv(Batch B, int fam, int l) {
+    PROB_PROLOGUE
+    if (l >= d->nlev) return;
+    const MgLevel& L = d->lev[l];
+    if (tid >= L.nrow) return;
+    Op<T> o = op_of<T>(d, fam, l);
+    const int sc = (d->S - 1) / 2;
+    double A[BB * BB], Ai[BB * BB];
+    for (int a = 0; a < BB; ++a)
+        for (int c = 0; c < BB; ++c) A[a * BB + c] = o.at(sc, a, c, tid);
+    if (fam == 1 && l == 0) {
+        int cc[3];
+        real_coords(tid, L.n, d->dim, cc);
+        A[0] += fs_term(d, padded(cc, L.np, d->R, d->dim));
+    }
+    invert_small<BB>(A, Ai);
+    T* out = (T*)(fam == 0 ? L.Ad : L.Sd);
+    for (int k = 0; k < BB * BB; ++k) out[(int64_t)k * L.nrow + tid] = (T)Ai[k];
+}
+
+// Galerkin coarse operator of level l+1: thread per (coarse row, stencil entry)
+template <int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_rap(Batch B, int fam, int l) {
+    PROB_PROLOGUE
+    if (l + 1 >= d->nlev) return;
+    const MgLevel& F = d->lev[l];
+    const MgLevel& C = d->lev[l + 1];
+    if (tid >= C.nrow) return;
+    const int s = blockIdx.y;
+    const int dim = d->dim, R = d->R, SW = 2 * R + 1;
+    int I[3], Jc[3] = {0, 0, 0}, off[3] = {s % SW - R, (s / SW) % SW - R, dim == 3 ? s / (SW * SW) - R : 0};
+    real_coords(tid, C.n, dim, I);
+    bool valid = true;
+    for (int a = 0; a < dim; ++a) {
+        Jc[a] = I[a] + off[a];
+        if (Jc[a] < 0 || Jc[a] >= C.n[a]) valid = false;
+    }
+    double blk[BB * BB];
+    for (int k = 0; k < BB * BB; ++k) blk[k] = 0.0;
+    if (valid) {
+        Op<T> o = op_of<T>(d, fam, l);
+        const int nI = dim == 3 ? 27 : 9;
+        for (int ii = 0; ii < nI; ++ii) {
+            int ki[3] = {ii % 3, (ii / 3) % 3, ii / 9};
+            int fi[3] = {0, 0, 0};
+            double wi = 1.0;
+            for (int a = 0; a < dim; ++a) {
+                fi[a] = cand(I[a], ki[a], F.cz[a]);
+                if (fi[a] < 0 || fi[a] >= F.n[a]) { wi = 0.0; break; }
+                wi *= pwa(fi[a], I[a], F.n[a], F.cz[a]);
+            }
+            if (wi == 0.0) continue;
+            int64_t frow = fi[0] + (int64_t)F.n[0] * (fi[1] + (int64_t)F.n[1] * fi[2]);
+            int64_t fpn = padded(fi, F.np, R, dim);
+            for (int jj = 0; jj < nI; ++jj) {
+                int kj[3] = {jj % 3, (jj / 3) % 3, jj / 9};
+                int fj[3] = {0, 0, 0};
+                double wj = 1.0;
+                int fs = 0, mul = 1;
+                for (int a = 0; a < dim; ++a) {
+                    fj[a] = cand(Jc[a], kj[a], F.cz[a]);
+                    if (fj[a] < 0 || fj[a] >= F.n[a]) { wj = 0.0; break; }
+                    int dd = fj[a] - fi[a];
+                    if (dd < -R || dd > R) { wj = 0.0; break; }
+                    wj *= pwa(fj[a], Jc[a], F.n[a], F.cz[a]);
+                    fs += (dd + R) * mul;
+                    mul *= SW;
+                }
+                if (wj == 0.0) continue;
+                int64_t fpnj = padded(fj, F.np, R, dim);
+                double w = wi * wj;
+                for (int a = 0; a < BB; ++a) {
+                    double mi = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
+                    if (mi == 0.0) continue;
+                    for (int c = 0; c < BB; ++c) {
+                        double mj = l == 0 ? mask0(d, fam, fpnj, c) : 1.0;
+                        if (mj == 0.0) continue;
+                        double v = o.at(fs, a, c, frow);
+                        if (fam == 1 && l == 0 && fs == (d->S - 1) / 2) v += fs_term(d, fpn);
+                        blk[a * BB + c] += w * v;
+                    }
+                }
+            }
+        }
+        if (s == (d->S - 1) / 2)
+            for (int a = 0; a < BB; ++a)
+                if (blk[a * BB + a] == 0.0) blk[a * BB + a] = 1.0;
+    }
+    T* out = (T*)(fam == 0 ? C.A : C.Sm);
+    for (int a = 0; a < BB; ++a)
+        for (int c = 0; c < BB; ++c) out[((int64_t)(s * BB + a) * BB + c) * C.nrow + tid] = (T)blk[a * BB + c];
+}
+
+// Dense inverse of the coarsest operator, Gauss-Jordan with partial pivoting in FP64 in LDS,
+// one block per problem (n <= CMAX).
+template <int BB, typename T>
+__global__ void __launch_bounds__(256) k_mg_coarse_setup(Batch B, int fam) {
+    const int q = blockIdx.x;
+    const Dev* d = B.d[q];
+    const int l = d->nlev - 1;
+    const MgLevel& L = d->lev[l];
+    const int dim = d->dim, R = d->R;
+    const int n = (int)(L.nrow * BB);
+    if (n > CMAX) return;
+    __shared__ double M[CMAX][CMAX + 1];
+    __shared__ int perm[CMAX];
+    __shared__ int piv;
+    Op<T> o = op_of<T>(d, fam, l);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e / n][e % n] = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = i;
+    __syncthreads();
+    for (int e = threadIdx.x; e < L.nrow * d->S; e += blockDim.x) {
+        int64_t row = e % L.nrow;
+        int s = (int)(e / L.nrow);
+        int c0[3], c1[3] = {0, 0, 0};
+        real_coords(row, L.n, dim, c0);
+        const int SW = 2 * R + 1;
+        int off[3] = {s % SW - R, (s / SW) % SW - R, dim == 3 ? s / (SW * SW) - R : 0};
+        bool ok = true;
+        for (int a = 0; a < dim; ++a) {
+            c1[a] = c0[a] + off[a];
+            if (c1[a] < 0 || c1[a] >= L.n[a]) ok = false;
+        }
+        if (!ok) continue;
+        int64_t col = c1[0] + (int64_t)L.n[0] * (c1[1] + (int64_t)L.n[1] * c1[2]);
+        for (int a = 0; a < BB; ++a)
+            for (int c = 0; c < BB; ++c) {
+                double v = o.at(s, a, c, row);
+                if (fam == 1 && l == 0 && s == (d->S - 1) / 2) v += fs_term(d, padded(c0, L.np, R, dim));
+                M[row * BB + a][col * BB + c] = v;
+            }
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) {
+            int best = k;
+            double bv = fabs(M[k][k]);
+            for (int r = k + 1; r < n; ++r)
+                if (fabs(M[r][k]) > bv) { bv = fabs(M[r][k]); best = r; }
+            piv = best;
+        }
+        __syncthreads();
+        const int pr = piv;
+        if (pr != k) {
+            for (int c = threadIdx.x; c < n; c += blockDim.x) {
+                double t = M[k][c]; M[k][c] = M[pr][c]; M[pr][c] = t;
+            }
+            if (threadIdx.x == 0) { int t = perm[k]; perm[k] = perm[pr]; perm[pr] = t; }
+        }
+        __syncthreads();
+        double pv = M[k][k];
+        if (pv == 0.0 || !isfinite(pv)) pv = 1.0;
+        __syncthreads();
+        for (int c = threadIdx.x; c < n; c += blockDim.x)
+            if (c != k) M[k][c] /= pv;
+        __syncthreads();
+        if (threadIdx.x == 0) M[k][k] = 1.0 / pv;
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            int r = e / n, c = e % n;
+            if (r == k || c == k) continue;
+            M[r][c] -= M[r][k] * M[k][c];
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < n; r += blockDim.x)
+            if (r != k) M[r][k] = -M[r][k] * M[k][k];
+        __syncthreads();
+    }
+    // the row swaps of the factorization permute the columns of the inverse
+    T* out = (T*)(fam == 0 ? d->cinvA : d->cinvS);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        int r = e / n, c = e % n;
+        out[(int64_t)r * n + perm[c]] = (T)M[r][c];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// cycle kernels of the large levels (one thread per row, batched)
+// ---------------------------------------------------------------------------------------------
+template <int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_pre(Batch B, int fam, int l, VRef rv, VRef xv, VRef resv) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
+    row_pre<BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB),
+                   resolve<T>(d, resv, fam, l, BB));
+}
+
+template <int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_smooth0(Batch B, int fam, int l, VRef rv, VRef xv) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
+    row_smooth0<BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB));
+}
+
+template <int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_resid(Batch B, int fam, int l, VRef rv, VRef xv, VRef resv) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
+    row_resid<BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB),
+                     resolve<T>(d, resv, fam, l, BB));
+}
+
+template <int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_update(Batch B, int fam, int l, VRef xv, VRef resv) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
+    row_update<BB, T>(d, fam, l, tid, resolve<T>(d, xv, fam, l, BB), resolve<T>(d, resv, fam, l, BB));
+}
+
+template <int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_restrict(Batch B, int fam, int l, VRef rv, VRef bv) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || l >= d->ltail || l + 1 >= d->nlev || tid >= d->lev[l + 1].nrow) return;
+    row_restrict<BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, bv, fam, l + 1, BB));
+}
+
+template <int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_prolong(Batch B, int fam, int l, VRef xcv, VRef xv) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || l >= d->ltail || l + 1 >= d->nlev || tid >= d->lev[l].nrow) return;
+    row_prolong<BB, T>(d, fam, l, tid, resolve<T>(d, xcv, fam, l + 1, BB), resolve<T>(d, xv, fam, l, BB));
+}
+
+// All levels from the problem's ltail down to the coarsest and back up, in one block.
+template <int BB, typename T>
+__global__ void __launch_bounds__(1024) k_mg_tail(Batch B, int fam, VRef rhs0, VRef out0) {
+    const int q = blockIdx.x;
+    const Dev* d = B.d[q];
+    if (krylov_done(d)) return;
+    const int L0 = d->ltail, L = d->nlev, nsm = d->mg_nsm;
+    const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0};
+    const int nt = blockDim.x;
+    for (int l = L0; l < L - 1; ++l) {
+        View<T> rhs = resolve<T>(d, l == 0 ? rhs0 : LB, fam, l, BB);
+        View<T> x = resolve<T>(d, l == 0 ? out0 : LX, fam, l, BB);
+        View<T> r = resolve<T>(d, LR, fam, l, BB);
+        const int64_t n = d->lev[l].nrow;
+        if (nsm == 1) {
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_pre<BB, T>(d, fam, l, i, rhs, x, r);
+            __syncthreads();
+        } else {
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_smooth0<BB, T>(d, fam, l, i, rhs, x);
+            __syncthreads();
+            for (int k = 1; k < nsm; ++k) {
+                for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<BB, T>(d, fam, l, i, rhs, x, r);
+                __syncthreads();
+                for (int64_t i = threadIdx.x; i < n; i += nt) row_update<BB, T>(d, fam, l, i, x, r);
+                __syncthreads();
+            }
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<BB, T>(d, fam, l, i, rhs, x, r);
+            __syncthreads();
+        }
+        View<T> bc = resolve<T>(d, LB, fam, l + 1, BB);
+        const int64_t nc = d->lev[l + 1].nrow;
+        for (int64_t i = threadIdx.x; i < nc; i += nt) row_restrict<BB, T>(d, fam, l, i, r, bc);
+        __syncthreads();
+    }
+    {
+        const int l = L - 1;
+        const MgLevel& C = d->lev[l];
+        View<T> rhs = resolve<T>(d, l == 0 ? rhs0 : LB, fam, l, BB);
+        View<T> x = resolve<T>(d, l == 0 ? out0 : LX, fam, l, BB);
+        const int n = (int)(C.nrow * BB);
+        const T* Ci = (const T*)(fam == 0 ? d->cinvA : d->cinvS);
+        __shared__ double bv[CMAX];
+        const int dim = d->dim, R = d->R;
+        if (n <= CMAX) {
+            for (int e = threadIdx.x; e < n; e += nt) {
+                int c[3];
+                real_coords(e / BB, C.n, dim, c);
+                bv[e] = (double)rhs.at(padded(c, C.np, R, dim), e % BB);
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < n; e += nt) {
+                double t = 0.0;
+                for (int k = 0; k < n; ++k) t += (double)Ci[(int64_t)e * n + k] * bv[k];
+                int c[3];
+                real_coords(e / BB, C.n, dim, c);
+                x.at(padded(c, C.np, R, dim), e % BB) = (T)t;
+            }
+        }
+        __syncthreads();
+    }
+    for (int l = L - 2; l >= L0; --l) {
+        View<T> rhs = resolve<T>(d, l == 0 ? rhs0 : LB, fam, l, BB);
+        View<T> x = resolve<T>(d, l == 0 ? out0 : LX, fam, l, BB);
+        View<T> r = resolve<T>(d, LR, fam, l, BB);
+        View<T> xc = resolve<T>(d, LX, fam, l + 1, BB);
+        const int64_t n = d->lev[l].nrow;
+        for (int64_t i = threadIdx.x; i < n; i += nt) row_prolong<BB, T>(d, fam, l, i, xc, x);
+        __syncthreads();
+        for (int k = 0; k < nsm; ++k) {
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<BB, T>(d, fam, l, i, rhs, x, r);
+            __syncthreads();
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_update<BB, T>(d, fam, l, i, x, r);
+            __syncthreads();
+        }
+    }
+}
+
+// t_u = y_u - B1 z_p on level 0 (B1 = displacement rows, pressure columns of J)
+template <int DIM, typename T>
+__global__ void __launch_bounds__(TPB) k_b1(Batch B, VRef yv, VRef zv) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || tid >= d->Nnode) return;
+    View<T> y = resolve<T>(d, yv, 0, 0, DIM), z = resolve<T>(d, zv, 0, 0, 1);
+    View<T> t = resolve<T>(d, VRef{VK_BT, 0}, 0, 0, DIM);
+    const int R = d->R, bs = d->b;
+    int c[3];
+    real_coords(tid, d->nn, DIM, c);
+    int64_t pn = padded(c, d->np1, R, DIM);
+    const T* J = (const T*)d->J;
+    const int64_t Nn = d->Nnode;
+    double acc[DIM];
+    for (int a = 0; a < DIM; ++a) acc[a] = (double)y.at(pn, a);
+    for (int s = 0; s < d->S; ++s) {
+        int64_t pk = pn + stencil_offset(s, R, DIM, d->np1);
+        double zp = (double)z.at(pk, 0);
+        for (int a = 0; a < DIM; ++a) acc[a] -= (double)J[((int64_t)(s * bs + a) * bs + DIM) * Nn + tid] * zp;
+    }
+    for (int a = 0; a < DIM; ++a) t.at(pn, a) = (T)acc[a];
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------
+static std::vector<int64_t> level_rows(const std::vector<const Dev*>& hc, int l) {
+    std::vector<int64_t> v;
+    for (auto* h : hc) v.push_back(l < h->nlev ? h->lev[l].nrow : 1);
+    return v;
+}
+
+static int max_levels(const std::vector<const Dev*>& hc) {
+    int L = 0;
+    for (auto* h : hc) L = std::max(L, h->nlev);
+    return L;
+}
+
+static int max_ltail(const std::vector<const Dev*>& hc) {
+    int L = 0;
+    for (auto* h : hc) L = std::max(L, h->ltail);
+    return L;
+}
+
+template <int DIM, typename T>
+static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, hipStream_t st) {
+    const int Lmax = max_levels(hc);
+    for (int l = 0; l < Lmax; ++l) {
+        // the coarse operator of level l is needed before its inverse diagonal
+        if (l > 0) {
+            Batch Bc = make_batch(g.ddev, level_rows(hc, l), TPB);
+            PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l - 1));
+            hipLaunchKernelGGL((k_mg_rap<1, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
+        }
+        Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
+        hipLaunchKernelGGL((k_mg_dinv<DIM, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 0, l);
+        hipLaunchKernelGGL((k_mg_dinv<1, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 1, l);
+    }
+    Batch B1 = make_batch_one_block(g.ddev);
+    hipLaunchKernelGGL((k_mg_coarse_setup<DIM, T>), dim3(B1.n), dim3(256), 0, st, B1, 0);
+    hipLaunchKernelGGL((k_mg_coarse_setup<1, T>), dim3(B1.n), dim3(256), 0, st, B1, 1);
+}
+
+void launch_precond_setup(const Group& g, const std::vector<const Dev*>& hc, hipStream_t st) {
+    if (g.dim == 2) {
+        if (g.mixed) precond_setup_t<2, float>(g, hc, st);
+        else precond_setup_t<2, double>(g, hc, st);
+    } else {
+        if (g.mixed) precond_setup_t<3, float>(g, hc, st);
+        else precond_setup_t<3, double>(g, hc, st);
+    }
+}
+
+// One batched V-cycle of family fam (block BB): rhs0 / out0 are the level-0 Krylov references.
+template <int BB, typename T>
+static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, VRef rhs0, VRef out0, int nsm,
+                   hipStream_t st) {
+    const int Lstd = max_ltail(hc);
+    const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0};
+    for (int l = 0; l < Lstd; ++l) {
+        const VRef rhs = l == 0 ? rhs0 : LB, x = l == 0 ? out0 : LX;
+        Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
+        const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
+        if (nsm == 1) {
+            PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
+                      hipLaunchKernelGGL((k_mg_pre<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR));
+        } else {
+            hipLaunchKernelGGL((k_mg_smooth0<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x);
+            for (int k = 1; k < nsm; ++k) {
+                hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR);
+                hipLaunchKernelGGL((k_mg_update<BB, T>), gl, tb, 0, st, Bl, fam, l, x, LR);
+            }
+            hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR);
+        }
+        Batch Bc = make_batch(g.ddev, level_rows(hc, l + 1), TPB);
+        hipLaunchKernelGGL((k_mg_restrict<BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l, LR, LB);
+    }
+    Batch B1 = make_batch_one_block(g.ddev);
+    hipLaunchKernelGGL((k_mg_tail<BB, T>), dim3(B1.n), dim3(1024), 0, st, B1, fam, rhs0, out0);
+    for (int l = Lstd - 1; l >= 0; --l) {
+        const VRef rhs = l == 0 ? rhs0 : LB, x = l == 0 ? out0 : LX;
+        Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
+        const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
+        hipLaunchKernelGGL((k_mg_prolong<BB, T>), gl, tb, 0, st, Bl, fam, l, LX, x);
+        for (int k = 0; k < nsm; ++k) {
+            PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
+                      hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR));
+            hipLaunchKernelGGL((k_mg_update<BB, T>), gl, tb, 0, st, Bl, fam, l, x, LR);
+        }
+    }
+}
+
+// z = P^-1 y on Krylov vectors iy -> iz: Schur block first, then A
+template <int DIM, typename T>
+static void precond_apply_t(const Group& g, const std::vector<const Dev*>& hc, int iy, int iz, hipStream_t st) {
+    const int nsm = hc[0]->mg_nsm;
+    vcycle<1, T>(g, hc, 1, VRef{iy, DIM}, VRef{iz, DIM}, nsm, st);
+    Batch Bn = make_batch(g.ddev, g.nnode, TPB);
+    hipLaunchKernelGGL((k_b1<DIM, T>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn, VRef{iy, 0}, VRef{iz, DIM});
+    vcycle<DIM, T>(g, hc, 0, VRef{VK_BT, 0}, VRef{iz, 0}, nsm, st);
+}
+
+void launch_precond_apply(const Group& g, const std::vector<const Dev*>& hc, int iy, int iz, hipStream_t st) {
+    if (g.dim == 2) {
+        if (g.mixed) precond_apply_t<2, float>(g, hc, iy, iz, st);
+        else precond_apply_t<2, double>(g, hc, iy, iz, st);
+    } else {
+        if (g.mixed) precond_apply_t<3, float>(g, hc, iy, iz, st);
+        else precond_apply_t<3, double>(g, hc, iy, iz, st);
+    }
+}
+
+}  // namespace ppm

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <initializer_list>
 #include <vector>
 
@@ -14,7 +15,7 @@ namespace ppm {
 struct Group {
     int dim = 2, shape = 0, mixed = 0, S = 9, b = 3;
     std::vector<const Dev*> ddev;   // device descriptors
-    std::vector<int64_t> np, nnode, ncell, ncell1, npadb, npad;
+    std::vector<int64_t> np, nnode, ncell, ncell1, npadb, npad, ntile;
 };
 
 // Per-kernel timing with HIP events recorded on the launching stream (off unless enabled).
@@ -50,6 +51,24 @@ inline Batch make_batch(const std::vector<const Dev*>& dd, const std::vector<int
     return B;
 }
 
+// Exactly blocks[q] blocks for problem q.
+inline Batch make_batch_blocks(const std::vector<const Dev*>& dd, const std::vector<int64_t>& blocks) {
+    Batch B{};
+    B.n = (int)dd.size();
+    B.pfx[0] = 0;
+    for (int q = 0; q < B.n; ++q) {
+        B.pfx[q + 1] = B.pfx[q] + (int)std::max<int64_t>(blocks[q], 1);
+        B.d[q] = dd[q];
+    }
+    return B;
+}
+
+// Node tiles of the gather kernels covering a grid of nn nodes per axis.
+inline int64_t node_tiles(int dim, const int* nn) {
+    if (dim == 2) return (int64_t)((nn[0] + TILE2X - 1) / TILE2X) * ((nn[1] + TILE2Y - 1) / TILE2Y);
+    return (int64_t)((nn[0] + TILE3X - 1) / TILE3X) * ((nn[1] + TILE3Y - 1) / TILE3Y) * ((nn[2] + TILE3Z - 1) / TILE3Z);
+}
+
 inline Batch make_batch_one_block(const std::vector<const Dev*>& dd) {
     Batch B{};
     B.n = (int)dd.size();
@@ -72,9 +91,10 @@ void launch_g2p(const Group& g, hipStream_t st);
 // kern_assemble.hip
 void launch_assemble(const Group& g, bool want_J, hipStream_t st);
 
-// kern_solver.hip
+// kern_assemble.hip
 void launch_jacobian(const Group& g, hipStream_t st);
 void launch_precond_setup(const Group& g, const std::vector<const Dev*>& host_copies, hipStream_t st);
+void launch_precond_apply(const Group& g, const std::vector<const Dev*>& host_copies, int iy, int iz, hipStream_t st);
 void launch_krylov_init(const Group& g, double rtol, int maxit, hipStream_t st);
 void launch_krylov_iters(const Group& g, const std::vector<const Dev*>& host_copies, int iters, double rtol,
                          int maxit, hipStream_t st);

@@ -10,7 +10,11 @@ namespace ppm {
 constexpr int MAXB = 64;      // problems per batched launch
 constexpr int TPB = 256;      // threads per block of the streaming kernels
 constexpr int MAXLEV = 12;    // multigrid levels
-constexpr int CMAX = 256;     // largest coarsest-level system solved by a dense inverse
+constexpr int CMAX = 81;      // largest coarsest-level system solved by a dense inverse (LDS)
+constexpr int TAILMAX = 600;  // levels with at most this many nodes run inside one fused kernel
+// node tiles of the gather kernels (one block of TPB threads per tile)
+constexpr int TILE2X = 16, TILE2Y = 16;
+constexpr int TILE3X = 8, TILE3Y = 8, TILE3Z = 4;
 
 // Particle state, structure of arrays: field f, component c of particle i lives at
 // base[(f + c) * stride + i].  Every variant uses the same slots (2D leaves some unused).
@@ -55,6 +59,7 @@ enum Scal : int {
 
 struct MgLevel {
     int n[3];            // nodes per axis
+    int cz[3];           // 1 if the axis is coarsened towards the next level
     int np[3];           // padded nodes per axis
     int64_t nrow;        // prod n
     int64_t npad;        // prod np
@@ -85,6 +90,7 @@ struct Dev {
     // per-step parameters
     double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
     int nlev;
+    int ltail;    // first level handled by the fused small-level kernel
     int mg_nsm;
     // particles
     double* pc;   // committed state
@@ -114,7 +120,7 @@ struct Dev {
     double* Rv;       // [Npad*b] residual
     double* cellpi;   // [Ncell * 2^dim] original-MPM projection Pi N
     // quadrature-point records
-    double* rec;      // [NREC][Np]
+    double* rec;      // [Np][NREC] (one record per point)
     int* rbase;       // [dim][Np] window base node per axis
     // Jacobian, fixed stencil block rows: J[((s*b + a)*b + c)*Nnode + row], precision T
     void* J;

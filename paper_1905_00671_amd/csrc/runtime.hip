@@ -166,7 +166,8 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
         h.Npad *= h.np1[a];
     }
     h.h = g->h;
-    // multigrid levels
+    // multigrid levels: halve every axis that still has more than three nodes, until the
+    // coarsest system is small enough for the dense inverse
     int nl = 0;
     int n[3] = {h.nn[0], h.nn[1], h.nn[2]};
     while (true) {
@@ -175,18 +176,29 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
         for (int a = 0; a < 3; ++a) {
             L.n[a] = n[a];
             L.np[a] = a < D ? n[a] + 2 * h.R : 1;
+            L.cz[a] = 0;
             rows *= L.n[a];
             pads *= L.np[a];
         }
         L.nrow = rows;
         L.npad = pads;
         ++nl;
-        int mn = 1 << 30;
-        for (int a = 0; a < D; ++a) mn = std::min(mn, n[a]);
-        if (rows * D <= CMAX || mn <= 3 || nl == MAXLEV) break;
-        for (int a = 0; a < D; ++a) n[a] = (n[a] - 1) / 2 + 1 + ((n[a] - 1) % 2);
+        bool any = false;
+        for (int a = 0; a < D; ++a)
+            if (n[a] > 3) any = true;
+        if (rows * D <= CMAX || !any || nl == MAXLEV) break;
+        for (int a = 0; a < D; ++a) {
+            L.cz[a] = n[a] > 3;
+            if (L.cz[a]) n[a] = (n[a] - 1) / 2 + 1 + ((n[a] - 1) % 2);
+        }
     }
     h.nlev = nl;
+    h.ltail = nl - 1;
+    for (int l = 0; l < nl; ++l)
+        if (h.lev[l].nrow <= TAILMAX) {
+            h.ltail = l;
+            break;
+        }
     // the coarsest level is solved by a dense inverse of at most CMAX unknowns
     if (h.lev[nl - 1].nrow * D > CMAX) return 0;
     const size_t TS = h.mixed ? sizeof(float) : sizeof(double);
@@ -247,7 +259,7 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
     h.cinvS = c.take<char>((size_t)std::min<int64_t>(nS * nS, CMAX * CMAX) * TS);
     h.cwork = c.take<double>((size_t)CMAX * CMAX);
     int64_t maxrows = std::max<int64_t>(h.Nnode, np);
-    h.maxblocks = (maxrows + TPB - 1) / TPB + 1;
+    h.maxblocks = std::max<int64_t>((maxrows + TPB - 1) / TPB + 1, node_tiles(D, h.nn));
     h.partial = c.take<double>((size_t)h.maxblocks * 4);
     h.scal = c.take<double>(NSCAL);
     h.flags = c.take<int>(NFLAG);
@@ -308,6 +320,7 @@ Group make_group(const std::vector<ppmpm_problem*>& ps) {
         g.ncell1.push_back(p->h.Ncell + 1);
         g.npad.push_back(p->h.Npad);
         g.npadb.push_back(p->h.Npad * p->h.b);
+        g.ntile.push_back(node_tiles(p->h.dim, p->h.nn));
     }
     return g;
 }

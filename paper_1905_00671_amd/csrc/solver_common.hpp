@@ -1,0 +1,128 @@
+// Device helpers shared by the Krylov and multigrid kernels: padded-grid indexing, stencil
+// offsets, deterministic block reductions, operator access and per-problem vector references.
+#pragma once
+#include "ppmpm_internal.hpp"
+
+namespace ppm {
+
+#define PROB_PROLOGUE                                   \
+    const int q = batch_find(B, blockIdx.x);            \
+    const Dev* __restrict__ d = B.d[q];                 \
+    const int64_t lb = blockIdx.x - B.pfx[q];           \
+    const int64_t tid = lb * blockDim.x + threadIdx.x;
+
+template <typename T>
+__device__ __forceinline__ T* vp(void* p) { return (T*)p; }
+
+__device__ __forceinline__ void real_coords(int64_t row, const int* n, int dim, int* c) {
+    c[0] = (int)(row % n[0]);
+    c[1] = (int)((row / n[0]) % n[1]);
+    c[2] = dim == 3 ? (int)(row / ((int64_t)n[0] * n[1])) : 0;
+}
+__device__ __forceinline__ int64_t padded(const int* c, const int* np, int R, int dim) {
+    if (dim == 2) return (int64_t)(c[0] + R) + (int64_t)np[0] * (c[1] + R);
+    return (int64_t)(c[0] + R) + (int64_t)np[0] * ((c[1] + R) + (int64_t)np[1] * (c[2] + R));
+}
+__device__ __forceinline__ int64_t stencil_offset(int s, int R, int dim, const int* np) {
+    int SW = 2 * R + 1;
+    int dx = s % SW - R, dy = (s / SW) % SW - R, dz = dim == 3 ? s / (SW * SW) - R : 0;
+    return (int64_t)dx + (int64_t)np[0] * (dy + (int64_t)np[1] * dz);
+}
+
+// block reduction of NV values into partial[lb*4 + k] (fixed tree order: deterministic)
+template <int NV>
+__device__ __forceinline__ void block_partials(const Dev* d, int64_t lb, const double* v) {
+    __shared__ double sh[NV][TPB];
+    for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NV; ++k) d->partial[lb * 4 + k] = sh[k][0];
+}
+
+__device__ __forceinline__ bool krylov_done(const Dev* d) { return d->scal[SC_DONE] != 0.0; }
+
+// Operator entry (row, stencil s, a, c) of family fam (0: A, block dim; 1: S, block 1) on level l.
+// Level 0 reads the Jacobian's stored blocks; coarser levels their Galerkin operators.
+template <typename T>
+struct Op {
+    const T* base;
+    int64_t nrow;
+    int BJ;   // block size of the storage
+    int a0;   // first storage row/col of the family
+    __device__ __forceinline__ double at(int s, int a, int c, int64_t row) const {
+        return (double)base[((int64_t)(s * BJ + a + a0) * BJ + c + a0) * nrow + row];
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ Op<T> op_of(const Dev* d, int fam, int l) {
+    Op<T> o;
+    if (l == 0) {
+        o.base = (const T*)d->J;
+        o.nrow = d->Nnode;
+        o.BJ = d->b;
+        o.a0 = fam == 0 ? 0 : d->dim;
+    } else {
+        o.base = (const T*)(fam == 0 ? d->lev[l].A : d->lev[l].Sm);
+        o.nrow = d->lev[l].nrow;
+        o.BJ = fam == 0 ? d->dim : 1;
+        o.a0 = 0;
+    }
+    return o;
+}
+
+// fixed-stress diagonal of the Schur approximation on level 0 (zero on non-free pressure dofs)
+__device__ __forceinline__ double fs_term(const Dev* d, int64_t pn) {
+    return d->dfree[pn * d->b + d->dim] ? d->ct / d->Kfs * d->Mp[pn] : 0.0;
+}
+
+__device__ __forceinline__ double mask0(const Dev* d, int fam, int64_t pn, int comp) {
+    return d->dfree[pn * d->b + (fam == 0 ? comp : d->dim)] ? 1.0 : 0.0;
+}
+
+// Symbolic vector reference resolved per problem inside the kernels, so that one launch serves
+// every problem of a batch: kinds 0..8 are the Krylov vectors (x r rhat p v s t ph sh, block b,
+// component offset `off`), 9 is the rhs of the A cycle on level 0 (block dim), 10/11/12 are the
+// level solution / residual / right-hand side of the family being cycled (block BB).
+struct VRef {
+    int kind;
+    int off;
+};
+enum { VK_BT = 9, VK_LX = 10, VK_LR = 11, VK_LB = 12 };
+
+template <typename T>
+struct View {
+    T* p;
+    int stride, off;
+    __device__ __forceinline__ T& at(int64_t pn, int c) const { return p[pn * stride + off + c]; }
+};
+
+template <typename T>
+__device__ __forceinline__ View<T> resolve(const Dev* d, VRef v, int fam, int l, int BB) {
+    View<T> o;
+    o.off = v.off;
+    if (v.kind < 9) {
+        void* const vecs[9] = {d->kx, d->kr, d->kh, d->kp, d->kv, d->ks, d->kt, d->kph, d->ksh};
+        o.p = (T*)vecs[v.kind];
+        o.stride = d->b;
+    } else if (v.kind == VK_BT) {
+        o.p = (T*)d->kbt;
+        o.stride = d->dim;
+    } else {
+        const MgLevel& L = d->lev[l];
+        void* p;
+        if (v.kind == VK_LX) p = fam == 0 ? L.xa : L.xs;
+        else if (v.kind == VK_LR) p = fam == 0 ? L.ra : L.rs;
+        else p = fam == 0 ? L.ba : L.bsv;
+        o.p = (T*)p;
+        o.stride = BB;
+    }
+    return o;
+}
+
+}  // namespace ppm
