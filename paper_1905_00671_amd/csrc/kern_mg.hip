@@ -49,98 +49,169 @@ __device__ __forceinline__ void invert_small(const double* A, double* Ai) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// row operations (one grid node of one level)
+// row operations (one grid node of one level).  The stencil shape (DIM, R) is a compile-time
+// constant so that the stencil loops unroll and every load of a row is issued at once; the
+// level's sizes and operator pointers are read once per thread into an Lv.
 // ---------------------------------------------------------------------------------------------
+template <typename T>
+struct Lv {
+    int n0, n1, n2, np0, np1;
+    int64_t nrow;
+    const T* op;   // operator storage (level 0: the Jacobian)
+    int BJ, a0;    // block size of the storage, first row/column of the family inside it
+    const T* Di;   // inverse diagonal blocks
+    __device__ __forceinline__ double opv(int s, int a, int c, int64_t row) const {
+        return (double)op[((int64_t)(s * BJ + a + a0) * BJ + c + a0) * nrow + row];
+    }
+};
+
 template <int BB, typename T>
-__device__ __forceinline__ void dinv_apply(const Dev* d, int fam, int l, int64_t row, const double* v, double* out) {
+__device__ __forceinline__ Lv<T> lv_of(const Dev* d, int fam, int l) {
     const MgLevel& L = d->lev[l];
-    const T* Di = (const T*)(fam == 0 ? L.Ad : L.Sd);
+    Lv<T> v;
+    v.n0 = L.n[0];
+    v.n1 = L.n[1];
+    v.n2 = L.n[2];
+    v.np0 = L.np[0];
+    v.np1 = L.np[1];
+    v.nrow = L.nrow;
+    if (l == 0) {
+        v.op = (const T*)d->J;
+        v.BJ = d->b;
+        v.a0 = fam == 0 ? 0 : d->dim;
+    } else {
+        v.op = (const T*)(fam == 0 ? L.A : L.Sm);
+        v.BJ = BB;
+        v.a0 = 0;
+    }
+    v.Di = (const T*)(fam == 0 ? L.Ad : L.Sd);
+    return v;
+}
+
+// real coordinates of row and its padded index
+template <int DIM, int R, typename T>
+__device__ __forceinline__ int64_t lv_pad(const Lv<T>& v, int64_t row, int* c) {
+    c[0] = (int)(row % v.n0);
+    c[1] = (int)((row / v.n0) % v.n1);
+    c[2] = DIM == 3 ? (int)(row / ((int64_t)v.n0 * v.n1)) : 0;
+    int64_t p = (int64_t)(c[1] + R);
+    if (DIM == 3) p += (int64_t)v.np1 * (c[2] + R);
+    return (int64_t)(c[0] + R) + (int64_t)v.np0 * p;
+}
+
+template <int DIM, int R>
+struct Sten {
+    static constexpr int SW = 2 * R + 1;
+    static constexpr int S = DIM == 2 ? SW * SW : SW * SW * SW;
+    static constexpr int C = (S - 1) / 2;
+    static constexpr int ox(int s) { return s % SW - R; }
+    static constexpr int oy(int s) { return (s / SW) % SW - R; }
+    static constexpr int oz(int s) { return DIM == 3 ? s / (SW * SW) - R : 0; }
+};
+
+template <int BB, typename T>
+__device__ __forceinline__ void dinv_apply(const Lv<T>& v, int64_t row, const double* x, double* out) {
+#pragma unroll
     for (int a = 0; a < BB; ++a) {
         double t = 0.0;
-        for (int c = 0; c < BB; ++c) t += (double)Di[(int64_t)(a * BB + c) * L.nrow + row] * v[c];
+#pragma unroll
+        for (int c = 0; c < BB; ++c) t += (double)v.Di[(int64_t)(a * BB + c) * v.nrow + row] * x[c];
         out[a] = t;
     }
 }
 
 // x = omega Dinv rhs
-template <int BB, typename T>
-__device__ __forceinline__ void row_smooth0(const Dev* d, int fam, int l, int64_t row, View<T> rhs, View<T> x) {
-    const MgLevel& L = d->lev[l];
+template <int DIM, int R, int BB, typename T>
+__device__ __forceinline__ void row_smooth0(const Dev* d, const Lv<T>& v, int64_t row, View<T> rhs, View<T> x) {
     int c[3];
-    real_coords(row, L.n, d->dim, c);
-    int64_t pn = padded(c, L.np, d->R, d->dim);
+    const int64_t pn = lv_pad<DIM, R>(v, row, c);
     double r[BB], y[BB];
+#pragma unroll
     for (int a = 0; a < BB; ++a) r[a] = (double)rhs.at(pn, a);
-    dinv_apply<BB, T>(d, fam, l, row, r, y);
+    dinv_apply<BB>(v, row, r, y);
+#pragma unroll
     for (int a = 0; a < BB; ++a) x.at(pn, a) = (T)(d->omega * y[a]);
 }
 
-// r = rhs - A x
-template <int BB, typename T>
-__device__ __forceinline__ void row_resid(const Dev* d, int fam, int l, int64_t row, View<T> rhs, View<T> x, View<T> r) {
-    const MgLevel& L = d->lev[l];
-    const int dim = d->dim, R = d->R;
+// r = rhs - A x (ghost entries of x are zero, as are the operator entries that leave the grid)
+template <int DIM, int R, int BB, typename T, bool FULL>
+__device__ __forceinline__ void row_resid(const Dev* d, const Lv<T>& v, bool fs0, int64_t row, View<T> rhs,
+                                          View<T> x, View<T> r) {
+    using St = Sten<DIM, R>;
+    constexpr int SW = St::SW, NROW = St::S / SW;
     int c[3];
-    real_coords(row, L.n, dim, c);
-    int64_t pn = padded(c, L.np, R, dim);
-    Op<T> o = op_of<T>(d, fam, l);
+    const int64_t pn = lv_pad<DIM, R>(v, row, c);
     double acc[BB];
+#pragma unroll
     for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
-    for (int s = 0; s < d->S; ++s) {
-        int64_t pk = pn + stencil_offset(s, R, dim, L.np);
-        for (int cc = 0; cc < BB; ++cc) {
-            double xv = (double)x.at(pk, cc);
-            for (int a = 0; a < BB; ++a) acc[a] -= o.at(s, a, cc, row) * xv;
+#pragma unroll(FULL ? (DIM == 3 ? 3 : NROW) : 1)
+    for (int t = 0; t < NROW; ++t) {
+        const int oy = t % SW - R, oz = DIM == 3 ? t / SW - R : 0;
+        const int64_t poff = (int64_t)v.np0 * (oy + (int64_t)v.np1 * oz);
+#pragma unroll
+        for (int i = 0; i < SW; ++i) {
+            const int64_t pk = pn + (i - R) + poff;
+            const int s = t * SW + i;
+#pragma unroll
+            for (int cc = 0; cc < BB; ++cc) {
+                const double xv = (double)x.at(pk, cc);
+#pragma unroll
+                for (int a = 0; a < BB; ++a) acc[a] -= v.opv(s, a, cc, row) * xv;
+            }
         }
     }
-    if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * (double)x.at(pn, 0);
+    if (fs0) acc[0] -= fs_term(d, pn) * (double)x.at(pn, 0);
+#pragma unroll
     for (int a = 0; a < BB; ++a) r.at(pn, a) = (T)acc[a];
 }
 
 // first sweep from a zero guess fused with the residual:
 //   x_i = omega Dinv_i rhs_i,   r_i = rhs_i - sum_k A_ik (omega Dinv_k rhs_k)
-template <int BB, typename T>
-__device__ __forceinline__ void row_pre(const Dev* d, int fam, int l, int64_t row, View<T> rhs, View<T> x, View<T> r) {
-    const MgLevel& L = d->lev[l];
-    const int dim = d->dim, R = d->R;
+// (neighbours off the grid have a zero rhs ghost; their inverse diagonal is read at row i).
+// The stencil is walked one x-row at a time, the SW loads of a row issued together (FULL: all
+// rows unrolled, for the small levels whose grids are too small to hide latency by occupancy).
+template <int DIM, int R, int BB, typename T, bool FULL>
+__device__ __forceinline__ void row_pre(const Dev* d, const Lv<T>& v, bool fs0, int64_t row, View<T> rhs, View<T> x,
+                                        View<T> r) {
+    using St = Sten<DIM, R>;
+    constexpr int SW = St::SW, NROW = St::S / SW;
     int c[3];
-    real_coords(row, L.n, dim, c);
-    int64_t pn = padded(c, L.np, R, dim);
-    Op<T> o = op_of<T>(d, fam, l);
-    const T* Di = (const T*)(fam == 0 ? L.Ad : L.Sd);
-    const int64_t stride_pad = 1;
-    (void)stride_pad;
+    const int64_t pn = lv_pad<DIM, R>(v, row, c);
+    const double om = d->omega;
     double acc[BB], xi[BB];
+#pragma unroll
     for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
-    for (int s = 0; s < d->S; ++s) {
-        int off[3] = {0, 0, 0};
-        const int SW = 2 * R + 1;
-        off[0] = s % SW - R;
-        off[1] = (s / SW) % SW - R;
-        off[2] = dim == 3 ? s / (SW * SW) - R : 0;
-        int ck[3];
-        bool inside = true;
-        for (int a = 0; a < dim; ++a) {
-            ck[a] = c[a] + off[a];
-            if (ck[a] < 0 || ck[a] >= L.n[a]) inside = false;
+#pragma unroll(FULL ? (DIM == 3 ? 3 : NROW) : 1)
+    for (int t = 0; t < NROW; ++t) {
+        const int oy = t % SW - R, oz = DIM == 3 ? t / SW - R : 0;
+        bool iny = (unsigned)(c[1] + oy) < (unsigned)v.n1;
+        if (DIM == 3) iny = iny && (unsigned)(c[2] + oz) < (unsigned)v.n2;
+        const int64_t roff = (int64_t)v.n0 * (oy + (int64_t)v.n1 * oz);
+        const int64_t poff = (int64_t)v.np0 * (oy + (int64_t)v.np1 * oz);
+#pragma unroll
+        for (int i = 0; i < SW; ++i) {
+            const int ox = i - R, s = t * SW + i;
+            const bool in = iny && (unsigned)(c[0] + ox) < (unsigned)v.n0;
+            const int64_t krow = in ? row + ox + roff : row;
+            const int64_t pk = pn + ox + poff;
+            double bk[BB], xk[BB];
+#pragma unroll
+            for (int a = 0; a < BB; ++a) bk[a] = (double)rhs.at(pk, a);
+            dinv_apply<BB>(v, krow, bk, xk);
+#pragma unroll
+            for (int a = 0; a < BB; ++a) xk[a] *= om;
+            if (s == St::C) {
+#pragma unroll
+                for (int a = 0; a < BB; ++a) xi[a] = xk[a];
+            }
+#pragma unroll
+            for (int cc = 0; cc < BB; ++cc)
+#pragma unroll
+                for (int a = 0; a < BB; ++a) acc[a] -= v.opv(s, a, cc, row) * xk[cc];
         }
-        if (!inside) continue;   // no coupling outside the grid
-        if (dim == 2) ck[2] = 0;
-        int64_t krow = ck[0] + (int64_t)L.n[0] * (ck[1] + (int64_t)L.n[1] * ck[2]);
-        int64_t pk = pn + stencil_offset(s, R, dim, L.np);
-        double bk[BB], xk[BB];
-        for (int a = 0; a < BB; ++a) bk[a] = (double)rhs.at(pk, a);
-        for (int a = 0; a < BB; ++a) {
-            double t = 0.0;
-            for (int cc = 0; cc < BB; ++cc) t += (double)Di[(int64_t)(a * BB + cc) * L.nrow + krow] * bk[cc];
-            xk[a] = d->omega * t;
-        }
-        if (s == (d->S - 1) / 2)
-            for (int a = 0; a < BB; ++a) xi[a] = xk[a];
-        for (int cc = 0; cc < BB; ++cc)
-            for (int a = 0; a < BB; ++a) acc[a] -= o.at(s, a, cc, row) * xk[cc];
     }
-    if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * xi[0];
+    if (fs0) acc[0] -= fs_term(d, pn) * xi[0];
+#pragma unroll
     for (int a = 0; a < BB; ++a) {
         x.at(pn, a) = (T)xi[a];
         r.at(pn, a) = (T)acc[a];
@@ -148,81 +219,102 @@ __device__ __forceinline__ void row_pre(const Dev* d, int fam, int l, int64_t ro
 }
 
 // x += omega Dinv r
-template <int BB, typename T>
-__device__ __forceinline__ void row_update(const Dev* d, int fam, int l, int64_t row, View<T> x, View<T> r) {
-    const MgLevel& L = d->lev[l];
+template <int DIM, int R, int BB, typename T>
+__device__ __forceinline__ void row_update(const Dev* d, const Lv<T>& v, int64_t row, View<T> x, View<T> r) {
     int c[3];
-    real_coords(row, L.n, d->dim, c);
-    int64_t pn = padded(c, L.np, d->R, d->dim);
+    const int64_t pn = lv_pad<DIM, R>(v, row, c);
     double rr[BB], y[BB];
+#pragma unroll
     for (int a = 0; a < BB; ++a) rr[a] = (double)r.at(pn, a);
-    dinv_apply<BB, T>(d, fam, l, row, rr, y);
+    dinv_apply<BB>(v, row, rr, y);
+#pragma unroll
     for (int a = 0; a < BB; ++a) x.at(pn, a) = (T)((double)x.at(pn, a) + d->omega * y[a]);
 }
 
 // coarse rhs of node I on level l+1 = (P^T r)_I (level-0 fine dofs masked by the free mask)
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T>
 __device__ __forceinline__ void row_restrict(const Dev* d, int fam, int l, int64_t Irow, View<T> r, View<T> bc) {
     const MgLevel& F = d->lev[l];
     const MgLevel& C = d->lev[l + 1];
-    const int dim = d->dim, R = d->R;
+    const int fn[3] = {F.n[0], F.n[1], F.n[2]}, fz[3] = {F.cz[0], F.cz[1], F.cz[2]};
+    const int fp0 = F.np[0], fp1 = F.np[1];
     int I[3];
-    real_coords(Irow, C.n, dim, I);
+    real_coords(Irow, C.n, DIM, I);
     double acc[BB];
+#pragma unroll
     for (int a = 0; a < BB; ++a) acc[a] = 0.0;
-    const int nI = dim == 3 ? 27 : 9;
+    constexpr int nI = DIM == 3 ? 27 : 9;
+#pragma unroll
     for (int ii = 0; ii < nI; ++ii) {
-        int kk[3] = {ii % 3, (ii / 3) % 3, ii / 9};
+        const int kk[3] = {ii % 3, (ii / 3) % 3, ii / 9};
         int fi[3] = {0, 0, 0};
         double w = 1.0;
-        for (int a = 0; a < dim; ++a) {
-            fi[a] = cand(I[a], kk[a], F.cz[a]);
-            if (fi[a] < 0 || fi[a] >= F.n[a]) { w = 0.0; break; }
-            w *= pwa(fi[a], I[a], F.n[a], F.cz[a]);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            fi[a] = cand(I[a], kk[a], fz[a]);
+            const bool ok = fi[a] >= 0 && fi[a] < fn[a];
+            w = ok ? w * pwa(fi[a], I[a], fn[a], fz[a]) : 0.0;
+            fi[a] = ok ? fi[a] : 0;
         }
-        if (w == 0.0) continue;
-        int64_t fpn = padded(fi, F.np, R, dim);
-        for (int a = 0; a < BB; ++a) {
-            double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
-            acc[a] += w * m * (double)r.at(fpn, a);
+        if (w != 0.0) {
+            int64_t fpn = (int64_t)(fi[1] + R);
+            if (DIM == 3) fpn += (int64_t)fp1 * (fi[2] + R);
+            fpn = (fi[0] + R) + (int64_t)fp0 * fpn;
+#pragma unroll
+            for (int a = 0; a < BB; ++a) {
+                const double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
+                acc[a] += w * m * (double)r.at(fpn, a);
+            }
         }
     }
-    int64_t cpn = padded(I, C.np, R, dim);
+    const int64_t cpn = padded(I, C.np, R, DIM);
+#pragma unroll
     for (int a = 0; a < BB; ++a) bc.at(cpn, a) = (T)acc[a];
 }
 
 // x(fine node) += (P xc) (level-0 fine dofs masked)
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T>
 __device__ __forceinline__ void row_prolong(const Dev* d, int fam, int l, int64_t frow, View<T> xc, View<T> x) {
     const MgLevel& F = d->lev[l];
     const MgLevel& C = d->lev[l + 1];
-    const int dim = d->dim, R = d->R;
+    const int fn[3] = {F.n[0], F.n[1], F.n[2]}, fz[3] = {F.cz[0], F.cz[1], F.cz[2]};
+    const int cn[3] = {C.n[0], C.n[1], C.n[2]};
+    const int cp0 = C.np[0], cp1 = C.np[1];
     int fi[3];
-    real_coords(frow, F.n, dim, fi);
-    int64_t fpn = padded(fi, F.np, R, dim);
+    real_coords(frow, fn, DIM, fi);
+    const int64_t fpn = padded(fi, F.np, R, DIM);
     double acc[BB];
+#pragma unroll
     for (int a = 0; a < BB; ++a) acc[a] = 0.0;
-    const int nI = dim == 3 ? 8 : 4;
+    constexpr int nI = DIM == 3 ? 8 : 4;
+#pragma unroll
     for (int jj = 0; jj < nI; ++jj) {
         int I[3] = {0, 0, 0};
         double w = 1.0;
-        for (int a = 0; a < dim; ++a) {
-            int bit = (jj >> a) & 1;
-            if (F.cz[a]) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int bit = (jj >> a) & 1;
+            if (fz[a]) {
                 I[a] = (fi[a] >> 1) + bit;
-                if (I[a] >= C.n[a]) { w = 0.0; break; }
-                w *= pw1(fi[a], I[a], F.n[a]);
+                const bool ok = I[a] < cn[a];
+                w = ok ? w * pw1(fi[a], I[a], fn[a]) : 0.0;
+                I[a] = ok ? I[a] : 0;
             } else {
-                if (bit) { w = 0.0; break; }
+                w = bit ? 0.0 : w;
                 I[a] = fi[a];
             }
         }
-        if (w == 0.0) continue;
-        int64_t cpn = padded(I, C.np, R, dim);
-        for (int a = 0; a < BB; ++a) acc[a] += w * (double)xc.at(cpn, a);
+        if (w != 0.0) {
+            int64_t cpn = (int64_t)(I[1] + R);
+            if (DIM == 3) cpn += (int64_t)cp1 * (I[2] + R);
+            cpn = (I[0] + R) + (int64_t)cp0 * cpn;
+#pragma unroll
+            for (int a = 0; a < BB; ++a) acc[a] += w * (double)xc.at(cpn, a);
+        }
     }
+#pragma unroll
     for (int a = 0; a < BB; ++a) {
-        double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
+        const double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
         x.at(fpn, a) = (T)((double)x.at(fpn, a) + m * acc[a]);
     }
 }
@@ -410,53 +502,58 @@ __global__ void __launch_bounds__(256) k_mg_coarse_setup(Batch B, int fam) {
 // ---------------------------------------------------------------------------------------------
 // cycle kernels of the large levels (one thread per row, batched)
 // ---------------------------------------------------------------------------------------------
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T, bool FULL>
 __global__ void __launch_bounds__(TPB) k_mg_pre(Batch B, int fam, int l, VRef rv, VRef xv, VRef resv) {
     PROB_PROLOGUE
     if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
-    row_pre<BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB),
-                   resolve<T>(d, resv, fam, l, BB));
+    const Lv<T> v = lv_of<BB, T>(d, fam, l);
+    row_pre<DIM, R, BB, T, FULL>(d, v, fam == 1 && l == 0, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB),
+                           resolve<T>(d, resv, fam, l, BB));
 }
 
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_smooth0(Batch B, int fam, int l, VRef rv, VRef xv) {
     PROB_PROLOGUE
     if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
-    row_smooth0<BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB));
+    const Lv<T> v = lv_of<BB, T>(d, fam, l);
+    row_smooth0<DIM, R, BB, T>(d, v, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB));
 }
 
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T, bool FULL>
 __global__ void __launch_bounds__(TPB) k_mg_resid(Batch B, int fam, int l, VRef rv, VRef xv, VRef resv) {
     PROB_PROLOGUE
     if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
-    row_resid<BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB),
-                     resolve<T>(d, resv, fam, l, BB));
+    const Lv<T> v = lv_of<BB, T>(d, fam, l);
+    row_resid<DIM, R, BB, T, FULL>(d, v, fam == 1 && l == 0, tid, resolve<T>(d, rv, fam, l, BB),
+                             resolve<T>(d, xv, fam, l, BB), resolve<T>(d, resv, fam, l, BB));
 }
 
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_update(Batch B, int fam, int l, VRef xv, VRef resv) {
     PROB_PROLOGUE
     if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
-    row_update<BB, T>(d, fam, l, tid, resolve<T>(d, xv, fam, l, BB), resolve<T>(d, resv, fam, l, BB));
+    const Lv<T> v = lv_of<BB, T>(d, fam, l);
+    row_update<DIM, R, BB, T>(d, v, tid, resolve<T>(d, xv, fam, l, BB), resolve<T>(d, resv, fam, l, BB));
 }
 
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_restrict(Batch B, int fam, int l, VRef rv, VRef bv) {
     PROB_PROLOGUE
     if (krylov_done(d) || l >= d->ltail || l + 1 >= d->nlev || tid >= d->lev[l + 1].nrow) return;
-    row_restrict<BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, bv, fam, l + 1, BB));
+    row_restrict<DIM, R, BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, bv, fam, l + 1, BB));
 }
 
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_prolong(Batch B, int fam, int l, VRef xcv, VRef xv) {
     PROB_PROLOGUE
     if (krylov_done(d) || l >= d->ltail || l + 1 >= d->nlev || tid >= d->lev[l].nrow) return;
-    row_prolong<BB, T>(d, fam, l, tid, resolve<T>(d, xcv, fam, l + 1, BB), resolve<T>(d, xv, fam, l, BB));
+    row_prolong<DIM, R, BB, T>(d, fam, l, tid, resolve<T>(d, xcv, fam, l + 1, BB), resolve<T>(d, xv, fam, l, BB));
 }
 
 // All levels from the problem's ltail down to the coarsest and back up, in one block.
-template <int BB, typename T>
-__global__ void __launch_bounds__(1024) k_mg_tail(Batch B, int fam, VRef rhs0, VRef out0) {
+constexpr int TAIL_TPB = 256;
+template <int DIM, int R, int BB, typename T>
+__global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs0, VRef out0) {
     const int q = blockIdx.x;
     const Dev* d = B.d[q];
     if (krylov_done(d)) return;
@@ -464,28 +561,30 @@ __global__ void __launch_bounds__(1024) k_mg_tail(Batch B, int fam, VRef rhs0, V
     const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0};
     const int nt = blockDim.x;
     for (int l = L0; l < L - 1; ++l) {
+        const Lv<T> v = lv_of<BB, T>(d, fam, l);
+        const bool fs0 = fam == 1 && l == 0;
         View<T> rhs = resolve<T>(d, l == 0 ? rhs0 : LB, fam, l, BB);
         View<T> x = resolve<T>(d, l == 0 ? out0 : LX, fam, l, BB);
         View<T> r = resolve<T>(d, LR, fam, l, BB);
-        const int64_t n = d->lev[l].nrow;
+        const int64_t n = v.nrow;
         if (nsm == 1) {
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_pre<BB, T>(d, fam, l, i, rhs, x, r);
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_pre<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
             __syncthreads();
         } else {
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_smooth0<BB, T>(d, fam, l, i, rhs, x);
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_smooth0<DIM, R, BB, T>(d, v, i, rhs, x);
             __syncthreads();
             for (int k = 1; k < nsm; ++k) {
-                for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<BB, T>(d, fam, l, i, rhs, x, r);
+                for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
                 __syncthreads();
-                for (int64_t i = threadIdx.x; i < n; i += nt) row_update<BB, T>(d, fam, l, i, x, r);
+                for (int64_t i = threadIdx.x; i < n; i += nt) row_update<DIM, R, BB, T>(d, v, i, x, r);
                 __syncthreads();
             }
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<BB, T>(d, fam, l, i, rhs, x, r);
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
             __syncthreads();
         }
         View<T> bc = resolve<T>(d, LB, fam, l + 1, BB);
         const int64_t nc = d->lev[l + 1].nrow;
-        for (int64_t i = threadIdx.x; i < nc; i += nt) row_restrict<BB, T>(d, fam, l, i, r, bc);
+        for (int64_t i = threadIdx.x; i < nc; i += nt) row_restrict<DIM, R, BB, T>(d, fam, l, i, r, bc);
         __syncthreads();
     }
     {
@@ -496,64 +595,70 @@ __global__ void __launch_bounds__(1024) k_mg_tail(Batch B, int fam, VRef rhs0, V
         const int n = (int)(C.nrow * BB);
         const T* Ci = (const T*)(fam == 0 ? d->cinvA : d->cinvS);
         __shared__ double bv[CMAX];
-        const int dim = d->dim, R = d->R;
         if (n <= CMAX) {
             for (int e = threadIdx.x; e < n; e += nt) {
                 int c[3];
-                real_coords(e / BB, C.n, dim, c);
-                bv[e] = (double)rhs.at(padded(c, C.np, R, dim), e % BB);
+                real_coords(e / BB, C.n, DIM, c);
+                bv[e] = (double)rhs.at(padded(c, C.np, R, DIM), e % BB);
             }
             __syncthreads();
             for (int e = threadIdx.x; e < n; e += nt) {
                 double t = 0.0;
                 for (int k = 0; k < n; ++k) t += (double)Ci[(int64_t)e * n + k] * bv[k];
                 int c[3];
-                real_coords(e / BB, C.n, dim, c);
-                x.at(padded(c, C.np, R, dim), e % BB) = (T)t;
+                real_coords(e / BB, C.n, DIM, c);
+                x.at(padded(c, C.np, R, DIM), e % BB) = (T)t;
             }
         }
         __syncthreads();
     }
     for (int l = L - 2; l >= L0; --l) {
+        const Lv<T> v = lv_of<BB, T>(d, fam, l);
+        const bool fs0 = fam == 1 && l == 0;
         View<T> rhs = resolve<T>(d, l == 0 ? rhs0 : LB, fam, l, BB);
         View<T> x = resolve<T>(d, l == 0 ? out0 : LX, fam, l, BB);
         View<T> r = resolve<T>(d, LR, fam, l, BB);
         View<T> xc = resolve<T>(d, LX, fam, l + 1, BB);
-        const int64_t n = d->lev[l].nrow;
-        for (int64_t i = threadIdx.x; i < n; i += nt) row_prolong<BB, T>(d, fam, l, i, xc, x);
+        const int64_t n = v.nrow;
+        for (int64_t i = threadIdx.x; i < n; i += nt) row_prolong<DIM, R, BB, T>(d, fam, l, i, xc, x);
         __syncthreads();
         for (int k = 0; k < nsm; ++k) {
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<BB, T>(d, fam, l, i, rhs, x, r);
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
             __syncthreads();
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_update<BB, T>(d, fam, l, i, x, r);
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_update<DIM, R, BB, T>(d, v, i, x, r);
             __syncthreads();
         }
     }
 }
 
 // t_u = y_u - B1 z_p on level 0 (B1 = displacement rows, pressure columns of J)
-template <int DIM, typename T>
+template <int DIM, int R, typename T>
 __global__ void __launch_bounds__(TPB) k_b1(Batch B, VRef yv, VRef zv) {
     PROB_PROLOGUE
     if (krylov_done(d) || tid >= d->Nnode) return;
+    using St = Sten<DIM, R>;
     View<T> y = resolve<T>(d, yv, 0, 0, DIM), z = resolve<T>(d, zv, 0, 0, 1);
     View<T> t = resolve<T>(d, VRef{VK_BT, 0}, 0, 0, DIM);
-    const int R = d->R, bs = d->b;
+    constexpr int bs = DIM + 1;
     int c[3];
     real_coords(tid, d->nn, DIM, c);
-    int64_t pn = padded(c, d->np1, R, DIM);
+    const int64_t pn = padded(c, d->np1, R, DIM);
+    const int np0 = d->np1[0], np1 = d->np1[1];
     const T* J = (const T*)d->J;
     const int64_t Nn = d->Nnode;
     double acc[DIM];
+#pragma unroll
     for (int a = 0; a < DIM; ++a) acc[a] = (double)y.at(pn, a);
-    for (int s = 0; s < d->S; ++s) {
-        int64_t pk = pn + stencil_offset(s, R, DIM, d->np1);
-        double zp = (double)z.at(pk, 0);
+#pragma unroll
+    for (int s = 0; s < St::S; ++s) {
+        const int64_t pk = pn + St::ox(s) + (int64_t)np0 * (St::oy(s) + (int64_t)np1 * St::oz(s));
+        const double zp = (double)z.at(pk, 0);
+#pragma unroll
         for (int a = 0; a < DIM; ++a) acc[a] -= (double)J[((int64_t)(s * bs + a) * bs + DIM) * Nn + tid] * zp;
     }
+#pragma unroll
     for (int a = 0; a < DIM; ++a) t.at(pn, a) = (T)acc[a];
 }
-
 // ---------------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------------
@@ -605,61 +710,81 @@ void launch_precond_setup(const Group& g, const std::vector<const Dev*>& hc, hip
 }
 
 // One batched V-cycle of family fam (block BB): rhs0 / out0 are the level-0 Krylov references.
-template <int BB, typename T>
+template <int DIM, int R, int BB, typename T, bool FULL>
+static void vcycle_down(const Group& g, const std::vector<const Dev*>& hc, int fam, int l, VRef rhs, VRef x, int nsm,
+                        hipStream_t st) {
+    const VRef LR{VK_LR, 0}, LB{VK_LB, 0};
+    Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
+    const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
+    if (nsm == 1) {
+        PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
+                  hipLaunchKernelGGL((k_mg_pre<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR));
+    } else {
+        hipLaunchKernelGGL((k_mg_smooth0<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x);
+        for (int k = 1; k < nsm; ++k) {
+            hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR);
+            hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, x, LR);
+        }
+        hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR);
+    }
+    Batch Bc = make_batch(g.ddev, level_rows(hc, l + 1), TPB);
+    hipLaunchKernelGGL((k_mg_restrict<DIM, R, BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l, LR, LB);
+}
+
+template <int DIM, int R, int BB, typename T, bool FULL>
+static void vcycle_up(const Group& g, const std::vector<const Dev*>& hc, int fam, int l, VRef rhs, VRef x, int nsm,
+                      hipStream_t st) {
+    const VRef LX{VK_LX, 0}, LR{VK_LR, 0};
+    Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
+    const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
+    hipLaunchKernelGGL((k_mg_prolong<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, LX, x);
+    for (int k = 0; k < nsm; ++k) {
+        PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
+                  hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR));
+        hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, x, LR);
+    }
+}
+
+// One batched V-cycle of family fam (block BB): rhs0 / out0 are the level-0 Krylov references.
+// Level 0 walks its stencil row by row (occupancy hides latency there); the coarser levels,
+// whose grids cover a few CUs only, use fully unrolled rows.
+template <int DIM, int R, int BB, typename T>
 static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, VRef rhs0, VRef out0, int nsm,
                    hipStream_t st) {
     const int Lstd = max_ltail(hc);
-    const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0};
+    const VRef LX{VK_LX, 0}, LB{VK_LB, 0};
     for (int l = 0; l < Lstd; ++l) {
-        const VRef rhs = l == 0 ? rhs0 : LB, x = l == 0 ? out0 : LX;
-        Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
-        const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
-        if (nsm == 1) {
-            PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
-                      hipLaunchKernelGGL((k_mg_pre<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR));
-        } else {
-            hipLaunchKernelGGL((k_mg_smooth0<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x);
-            for (int k = 1; k < nsm; ++k) {
-                hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR);
-                hipLaunchKernelGGL((k_mg_update<BB, T>), gl, tb, 0, st, Bl, fam, l, x, LR);
-            }
-            hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR);
-        }
-        Batch Bc = make_batch(g.ddev, level_rows(hc, l + 1), TPB);
-        hipLaunchKernelGGL((k_mg_restrict<BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l, LR, LB);
+        if (l == 0) vcycle_down<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, out0, nsm, st);
+        else vcycle_down<DIM, R, BB, T, true>(g, hc, fam, l, LB, LX, nsm, st);
     }
     Batch B1 = make_batch_one_block(g.ddev);
-    hipLaunchKernelGGL((k_mg_tail<BB, T>), dim3(B1.n), dim3(1024), 0, st, B1, fam, rhs0, out0);
+    hipLaunchKernelGGL((k_mg_tail<DIM, R, BB, T>), dim3(B1.n), dim3(TAIL_TPB), 0, st, B1, fam, rhs0, out0);
     for (int l = Lstd - 1; l >= 0; --l) {
-        const VRef rhs = l == 0 ? rhs0 : LB, x = l == 0 ? out0 : LX;
-        Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
-        const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
-        hipLaunchKernelGGL((k_mg_prolong<BB, T>), gl, tb, 0, st, Bl, fam, l, LX, x);
-        for (int k = 0; k < nsm; ++k) {
-            PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
-                      hipLaunchKernelGGL((k_mg_resid<BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR));
-            hipLaunchKernelGGL((k_mg_update<BB, T>), gl, tb, 0, st, Bl, fam, l, x, LR);
-        }
+        if (l == 0) vcycle_up<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, out0, nsm, st);
+        else vcycle_up<DIM, R, BB, T, true>(g, hc, fam, l, LB, LX, nsm, st);
     }
 }
 
 // z = P^-1 y on Krylov vectors iy -> iz: Schur block first, then A
-template <int DIM, typename T>
+template <int DIM, int R, typename T>
 static void precond_apply_t(const Group& g, const std::vector<const Dev*>& hc, int iy, int iz, hipStream_t st) {
     const int nsm = hc[0]->mg_nsm;
-    vcycle<1, T>(g, hc, 1, VRef{iy, DIM}, VRef{iz, DIM}, nsm, st);
+    vcycle<DIM, R, 1, T>(g, hc, 1, VRef{iy, DIM}, VRef{iz, DIM}, nsm, st);
     Batch Bn = make_batch(g.ddev, g.nnode, TPB);
-    hipLaunchKernelGGL((k_b1<DIM, T>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn, VRef{iy, 0}, VRef{iz, DIM});
-    vcycle<DIM, T>(g, hc, 0, VRef{VK_BT, 0}, VRef{iz, 0}, nsm, st);
+    hipLaunchKernelGGL((k_b1<DIM, R, T>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn, VRef{iy, 0}, VRef{iz, DIM});
+    vcycle<DIM, R, DIM, T>(g, hc, 0, VRef{VK_BT, 0}, VRef{iz, 0}, nsm, st);
 }
 
 void launch_precond_apply(const Group& g, const std::vector<const Dev*>& hc, int iy, int iz, hipStream_t st) {
-    if (g.dim == 2) {
-        if (g.mixed) precond_apply_t<2, float>(g, hc, iy, iz, st);
-        else precond_apply_t<2, double>(g, hc, iy, iz, st);
+    if (g.dim == 2 && g.shape == 0) {
+        if (g.mixed) precond_apply_t<2, 1, float>(g, hc, iy, iz, st);
+        else precond_apply_t<2, 1, double>(g, hc, iy, iz, st);
+    } else if (g.dim == 2) {
+        if (g.mixed) precond_apply_t<2, 2, float>(g, hc, iy, iz, st);
+        else precond_apply_t<2, 2, double>(g, hc, iy, iz, st);
     } else {
-        if (g.mixed) precond_apply_t<3, float>(g, hc, iy, iz, st);
-        else precond_apply_t<3, double>(g, hc, iy, iz, st);
+        if (g.mixed) precond_apply_t<3, 1, float>(g, hc, iy, iz, st);
+        else precond_apply_t<3, 1, double>(g, hc, iy, iz, st);
     }
 }
 
