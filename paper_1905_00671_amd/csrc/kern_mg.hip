@@ -133,8 +133,9 @@ __device__ __forceinline__ void row_smooth0(const Dev* d, const Lv<T>& v, int64_
     for (int a = 0; a < BB; ++a) x.at(pn, a) = (T)(d->omega * y[a]);
 }
 
-// r = rhs - A x (ghost entries of x are zero, as are the operator entries that leave the grid)
-template <int DIM, int R, int BB, typename T, bool FULL>
+// r = rhs - A x (ghost entries of x are zero, as are the operator entries that leave the grid);
+// POST: the last post-smoothing sweep instead, r <- x + omega Dinv (rhs - A x) (r must not alias x)
+template <int DIM, int R, int BB, typename T, bool FULL, bool POST = false>
 __device__ __forceinline__ void row_resid(const Dev* d, const Lv<T>& v, bool fs0, int64_t row, View<T> rhs,
                                           View<T> x, View<T> r) {
     using St = Sten<DIM, R>;
@@ -161,8 +162,15 @@ __device__ __forceinline__ void row_resid(const Dev* d, const Lv<T>& v, bool fs0
         }
     }
     if (fs0) acc[0] -= fs_term(d, pn) * (double)x.at(pn, 0);
+    if (POST) {
+        double y[BB];
+        dinv_apply<BB>(v, row, acc, y);
 #pragma unroll
-    for (int a = 0; a < BB; ++a) r.at(pn, a) = (T)acc[a];
+        for (int a = 0; a < BB; ++a) r.at(pn, a) = (T)((double)x.at(pn, a) + d->omega * y[a]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < BB; ++a) r.at(pn, a) = (T)acc[a];
+    }
 }
 
 // first sweep from a zero guess fused with the residual:
@@ -528,6 +536,15 @@ __global__ void __launch_bounds__(TPB) k_mg_resid(Batch B, int fam, int l, VRef 
                              resolve<T>(d, xv, fam, l, BB), resolve<T>(d, resv, fam, l, BB));
 }
 
+template <int DIM, int R, int BB, typename T, bool FULL>
+__global__ void __launch_bounds__(TPB) k_mg_post(Batch B, int fam, int l, VRef rv, VRef xv, VRef outv) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
+    const Lv<T> v = lv_of<BB, T>(d, fam, l);
+    row_resid<DIM, R, BB, T, FULL, true>(d, v, fam == 1 && l == 0, tid, resolve<T>(d, rv, fam, l, BB),
+                                         resolve<T>(d, xv, fam, l, BB), resolve<T>(d, outv, fam, l, BB));
+}
+
 template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_update(Batch B, int fam, int l, VRef xv, VRef resv) {
     PROB_PROLOGUE
@@ -551,6 +568,9 @@ __global__ void __launch_bounds__(TPB) k_mg_prolong(Batch B, int fam, int l, VRe
 }
 
 // All levels from the problem's ltail down to the coarsest and back up, in one block.
+// Same conventions as the per-level kernels: on the way down a level's iterate is in LX and its
+// residual in LR; on the way up the prolongation adds the coarser correction (VK_SOL) into LX
+// and the last smoothing sweep writes the level's correction to LR (level 0: to out0).
 constexpr int TAIL_TPB = 256;
 template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs0, VRef out0) {
@@ -558,13 +578,13 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
     const Dev* d = B.d[q];
     if (krylov_done(d)) return;
     const int L0 = d->ltail, L = d->nlev, nsm = d->mg_nsm;
-    const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0};
+    const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0}, SOL{VK_SOL, 0};
     const int nt = blockDim.x;
     for (int l = L0; l < L - 1; ++l) {
         const Lv<T> v = lv_of<BB, T>(d, fam, l);
         const bool fs0 = fam == 1 && l == 0;
         View<T> rhs = resolve<T>(d, l == 0 ? rhs0 : LB, fam, l, BB);
-        View<T> x = resolve<T>(d, l == 0 ? out0 : LX, fam, l, BB);
+        View<T> x = resolve<T>(d, LX, fam, l, BB);
         View<T> r = resolve<T>(d, LR, fam, l, BB);
         const int64_t n = v.nrow;
         if (nsm == 1) {
@@ -616,18 +636,22 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
         const Lv<T> v = lv_of<BB, T>(d, fam, l);
         const bool fs0 = fam == 1 && l == 0;
         View<T> rhs = resolve<T>(d, l == 0 ? rhs0 : LB, fam, l, BB);
-        View<T> x = resolve<T>(d, l == 0 ? out0 : LX, fam, l, BB);
+        View<T> x = resolve<T>(d, LX, fam, l, BB);
         View<T> r = resolve<T>(d, LR, fam, l, BB);
-        View<T> xc = resolve<T>(d, LX, fam, l + 1, BB);
+        View<T> out = resolve<T>(d, l == 0 ? out0 : LR, fam, l, BB);
+        View<T> xc = resolve<T>(d, SOL, fam, l + 1, BB);
         const int64_t n = v.nrow;
         for (int64_t i = threadIdx.x; i < n; i += nt) row_prolong<DIM, R, BB, T>(d, fam, l, i, xc, x);
         __syncthreads();
-        for (int k = 0; k < nsm; ++k) {
+        for (int k = 1; k < nsm; ++k) {
             for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
             __syncthreads();
             for (int64_t i = threadIdx.x; i < n; i += nt) row_update<DIM, R, BB, T>(d, v, i, x, r);
             __syncthreads();
         }
+        for (int64_t i = threadIdx.x; i < n; i += nt)
+            row_resid<DIM, R, BB, T, true, true>(d, v, fs0, i, rhs, x, out);
+        __syncthreads();
     }
 }
 
@@ -710,39 +734,44 @@ void launch_precond_setup(const Group& g, const std::vector<const Dev*>& hc, hip
 }
 
 // One batched V-cycle of family fam (block BB): rhs0 / out0 are the level-0 Krylov references.
+// Down-sweep of one level: pre-smoothing from a zero guess (iterate -> LX, residual -> LR) and
+// restriction of the residual to the next level's right-hand side.
 template <int DIM, int R, int BB, typename T, bool FULL>
-static void vcycle_down(const Group& g, const std::vector<const Dev*>& hc, int fam, int l, VRef rhs, VRef x, int nsm,
+static void vcycle_down(const Group& g, const std::vector<const Dev*>& hc, int fam, int l, VRef rhs, int nsm,
                         hipStream_t st) {
-    const VRef LR{VK_LR, 0}, LB{VK_LB, 0};
+    const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0};
     Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
     const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
     if (nsm == 1) {
         PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
-                  hipLaunchKernelGGL((k_mg_pre<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR));
+                  hipLaunchKernelGGL((k_mg_pre<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR));
     } else {
-        hipLaunchKernelGGL((k_mg_smooth0<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, x);
+        hipLaunchKernelGGL((k_mg_smooth0<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, LX);
         for (int k = 1; k < nsm; ++k) {
-            hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR);
-            hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, x, LR);
+            hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR);
+            hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, LX, LR);
         }
-        hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR);
+        hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR);
     }
     Batch Bc = make_batch(g.ddev, level_rows(hc, l + 1), TPB);
     hipLaunchKernelGGL((k_mg_restrict<DIM, R, BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l, LR, LB);
 }
 
+// Up-sweep of one level: LX += P (coarser correction), post-smoothing, the last sweep fused with
+// the residual and written to `out` (LR, or the Krylov output on level 0).
 template <int DIM, int R, int BB, typename T, bool FULL>
-static void vcycle_up(const Group& g, const std::vector<const Dev*>& hc, int fam, int l, VRef rhs, VRef x, int nsm,
+static void vcycle_up(const Group& g, const std::vector<const Dev*>& hc, int fam, int l, VRef rhs, VRef out, int nsm,
                       hipStream_t st) {
-    const VRef LX{VK_LX, 0}, LR{VK_LR, 0};
+    const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, SOL{VK_SOL, 0};
     Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
     const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
-    hipLaunchKernelGGL((k_mg_prolong<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, LX, x);
-    for (int k = 0; k < nsm; ++k) {
-        PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
-                  hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, x, LR));
-        hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, x, LR);
+    hipLaunchKernelGGL((k_mg_prolong<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, SOL, LX);
+    for (int k = 1; k < nsm; ++k) {
+        hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR);
+        hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, LX, LR);
     }
+    PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
+              hipLaunchKernelGGL((k_mg_post<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, out));
 }
 
 // One batched V-cycle of family fam (block BB): rhs0 / out0 are the level-0 Krylov references.
@@ -752,16 +781,16 @@ template <int DIM, int R, int BB, typename T>
 static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, VRef rhs0, VRef out0, int nsm,
                    hipStream_t st) {
     const int Lstd = max_ltail(hc);
-    const VRef LX{VK_LX, 0}, LB{VK_LB, 0};
+    const VRef LR{VK_LR, 0}, LB{VK_LB, 0};
     for (int l = 0; l < Lstd; ++l) {
-        if (l == 0) vcycle_down<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, out0, nsm, st);
-        else vcycle_down<DIM, R, BB, T, true>(g, hc, fam, l, LB, LX, nsm, st);
+        if (l == 0) vcycle_down<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, nsm, st);
+        else vcycle_down<DIM, R, BB, T, true>(g, hc, fam, l, LB, nsm, st);
     }
     Batch B1 = make_batch_one_block(g.ddev);
     hipLaunchKernelGGL((k_mg_tail<DIM, R, BB, T>), dim3(B1.n), dim3(TAIL_TPB), 0, st, B1, fam, rhs0, out0);
     for (int l = Lstd - 1; l >= 0; --l) {
         if (l == 0) vcycle_up<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, out0, nsm, st);
-        else vcycle_up<DIM, R, BB, T, true>(g, hc, fam, l, LB, LX, nsm, st);
+        else vcycle_up<DIM, R, BB, T, true>(g, hc, fam, l, LB, LR, nsm, st);
     }
 }
 

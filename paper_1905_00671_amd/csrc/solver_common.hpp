@@ -88,12 +88,14 @@ __device__ __forceinline__ double mask0(const Dev* d, int fam, int64_t pn, int c
 // Symbolic vector reference resolved per problem inside the kernels, so that one launch serves
 // every problem of a batch: kinds 0..8 are the Krylov vectors (x r rhat p v s t ph sh, block b,
 // component offset `off`), 9 is the rhs of the A cycle on level 0 (block dim), 10/11/12 are the
-// level solution / residual / right-hand side of the family being cycled (block BB).
+// level iterate / residual / right-hand side of the family being cycled (block BB), 13 is where
+// the up-sweep leaves the level's correction: the iterate buffer on the coarsest level (written
+// by the dense solve), the residual buffer on the others (the fused post-smoother writes there).
 struct VRef {
     int kind;
     int off;
 };
-enum { VK_BT = 9, VK_LX = 10, VK_LR = 11, VK_LB = 12 };
+enum { VK_BT = 9, VK_LX = 10, VK_LR = 11, VK_LB = 12, VK_SOL = 13 };
 
 template <typename T>
 struct View {
@@ -115,9 +117,11 @@ __device__ __forceinline__ View<T> resolve(const Dev* d, VRef v, int fam, int l,
         o.stride = d->dim;
     } else {
         const MgLevel& L = d->lev[l];
+        int kind = v.kind;
+        if (kind == VK_SOL) kind = l == d->nlev - 1 ? VK_LX : VK_LR;
         void* p;
-        if (v.kind == VK_LX) p = fam == 0 ? L.xa : L.xs;
-        else if (v.kind == VK_LR) p = fam == 0 ? L.ra : L.rs;
+        if (kind == VK_LX) p = fam == 0 ? L.xa : L.xs;
+        else if (kind == VK_LR) p = fam == 0 ? L.ra : L.rs;
         else p = fam == 0 ? L.ba : L.bsv;
         o.p = (T*)p;
         o.stride = BB;
