@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -112,19 +113,32 @@ def spmv_roofline(w, kt, precision):
                 avg_launch_us=avg_s * 1e6, launches=k["launches"])
 
 
+def spmv_source_digest():
+    """sha256 of the SpMV kernel's source text (template line to closing brace)."""
+    src = open(os.path.join(ROOT, "paper_1905_00671_amd", "csrc", "kern_solver.hip")).read()
+    a = src.index("template <int DIM, int R, typename T>\n__global__ void __launch_bounds__(TPB) k_spmv(")
+    b = src.index("\n}\n", a) + 3
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def pmc_traffic(roof, precision):
-    """HBM bytes per SpMV launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "spmv_footing2d_large_pmc.json")
+    """HBM bytes per SpMV launch from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy-kernel calibration), if it was taken on the current kernel
+    source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "spmv_footing2d_large_pmc.txt")
     if roof is None or not os.path.exists(path):
         return None
     try:
-        d = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_1905_00671_amd", "csrc", "kern_solver.hip"), "rb").read()
-        if d.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        digest, per = None, {}
+        for line in open(path):
+            if line.startswith("kernel_source_sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            m = re.match(r"^(fp64|mixed):.*hbm_bytes_per_launch=([0-9.eE+]+)", line)
+            if m:
+                per[m.group(1)] = float(m.group(2))
+        if digest != spmv_source_digest():
             return None
-        key = "fp64" if precision == 0 else "mixed"
-        return d[key]["hbm_bytes_per_launch"]
+        return per.get("fp64" if precision == 0 else "mixed")
     except Exception:
         return None
 
