@@ -80,6 +80,10 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1905_00671_amd/build.py")
+        # torch ships its own HIP and HSA runtimes under the same sonames as /opt/rocm's; loading
+        # torch first makes the library bind to those instead of starting a second runtime in the
+        # process (which would find no device)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
         L.ppmpm_workspace_bytes.restype = ctypes.c_size_t
@@ -258,6 +262,7 @@ class Problem:
         if getattr(self, "h", None) is not None and self.h.value:
             self.L.ppmpm_destroy(self.h)
             self.h = ctypes.c_void_p()
+        self._ws = None      # the workspace goes back to torch's allocator
 
     def __del__(self):
         try:
