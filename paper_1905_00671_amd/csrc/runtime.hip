@@ -232,7 +232,6 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
     h.Rv = c.take<double>(P * bs);
     h.cellpi = c.take<double>(h.Ncell * (1 << D));
     h.rec = c.take<double>((size_t)nrec * np);
-    h.rbase = c.take<int>((size_t)D * np);
     h.J = c.take<char>((size_t)h.S * bs * bs * h.Nnode * TS);
     void** kv[9] = {&h.kx, &h.kr, &h.kh, &h.kp, &h.kv, &h.ks, &h.kt, &h.kph, &h.ksh};
     for (auto* p : kv) *p = c.take<char>((size_t)P * bs * TS);
@@ -361,7 +360,9 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
         h.hc2 = o->dynamic ? (1.0 - 0.5 * o->gamma / o->beta) * t : 0.0;
         h.tau = stab_tau(o, h.lam, h.G, h.kappa, h.h, t);
         h.Kfs = h.lam + 2.0 * h.G / h.dim;
-        h.omega = 0.7;
+        // damping of the block-Jacobi smoother, about 4 / (3 lambda_max(D^-1 A)): lambda_max is near
+        // 2 for the 2D stencils and near 3.2 for the 27-point trilinear one
+        h.omega = h.dim == 3 ? 0.5 : 0.7;
         h.mg_nsm = std::max(1, o->mg_smooth);
         ppmpm_status s = upload_desc(p);
         if (s) return s;
@@ -452,13 +453,16 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     h.dt = 1.0;
     h.beta = opt->beta;
     h.gamma = opt->gamma;
-    h.omega = 0.7;
+    h.omega = h.dim == 3 ? 0.5 : 0.7;
     h.mg_nsm = std::max(1, opt->mg_smooth);
-    if (hipHostMalloc((void**)&p->hpin, sizeof(Dev)) != hipSuccess ||
-        hipHostMalloc((void**)&p->spin, sizeof(double) * NSCAL) != hipSuccess ||
-        hipHostMalloc((void**)&p->fpin, sizeof(int) * NFLAG) != hipSuccess) {
-        ppmpm_destroy(p);
-        return fail(PPMPM_E_DEVICE, "pinned host allocation failed");
+    {
+        hipError_t e = hipHostMalloc((void**)&p->hpin, sizeof(Dev));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&p->spin, sizeof(double) * NSCAL);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&p->fpin, sizeof(int) * NFLAG);
+        if (e != hipSuccess) {
+            ppmpm_destroy(p);
+            return fail(PPMPM_E_DEVICE, std::string("pinned host allocation failed: ") + hipGetErrorString(e));
+        }
     }
     if (hipMemsetAsync(p->ws, 0, used, p->st) != hipSuccess) {
         ppmpm_destroy(p);
