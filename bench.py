@@ -31,8 +31,22 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particle-updates/s per Newton step, p50/p99 latency; FP32-mixed vs FP64 at 1e-8 resid"
 
 
+WORKLOAD = "footing2d_large"
+DESCR = {
+    "footing2d_large": "footing2d_large: 2D GIMP quasi-static rigid-footing half-model, 512x256 cells (h=0.0625 m) "
+                       "+16 empty rows, 524,288 points, neo-Hookean E=10 MPa nu=0.3, k from seed 0, "
+                       "dt=0.1 s, 5 mm/step, Newton 1e-8 per residual block",
+    "footing3d": "footing3d: 3D trilinear quasi-static rigid square-footing quarter-model, 96^3 cells (h=0.125 m) "
+                 "+2 empty layers, 7,077,888 points, neo-Hookean E=10 MPa nu=0.3, k=1e-12, dt=0.1 s, "
+                 "5 mm/step, Newton 1e-8 per residual block",
+}
+
+
 def workload(scale: int = 1):
     from paper_1905_00671_amd import workloads as W
+    if WORKLOAD == "footing3d":
+        n = 96 // scale
+        return W.footing3d(n=n, size=12.0 * n / 96, half_b=max(0.25, 1.0 * n / 96))
     return W.config(3, nx=512 // scale, ny=256 // scale, width=32.0 / scale, empty_rows=max(2, 16 // scale))
 
 
@@ -52,7 +66,11 @@ def run_path(w, precision, warmup, steps, bcs):
     p = B.Problem.from_workload(w, precision=precision)
     try:
         for n in range(1, warmup + 1):
-            p.step(w.dt, bcs[n])
+            ts = time.perf_counter()
+            st = p.step(w.dt, bcs[n])
+            torch.cuda.synchronize()
+            print(f"[bench] precision={precision} warm-up step {n}: {(time.perf_counter() - ts) * 1e3:.1f} ms "
+                  f"newton={st['newton_iters']} krylov={st['krylov_iters']}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         B.timing_reset()
         B.timing_enable(True)
@@ -191,14 +209,49 @@ def parity_check():
                 worst[prec][1] = max(worst[prec][1], ep)
         for prec, name in ((0, "fp64"), (1, "mixed")):
             out[name] = dict(rel_err_u=worst[prec][0], rel_err_p=worst[prec][1])
-        out["case"] = f"64x32-cell replica ({w.particles.n} points), 2 steps, Newton 1e-8, vs FP64 oracle"
+        out["case"] = f"1/8-scale replica of the workload ({w.particles.n} points), 2 steps, Newton 1e-8, vs FP64 oracle"
     finally:
         for p in probs.values():
             p.close()
     return out
 
 
+def serve_bench(nreq, realtime):
+    """The serving stream (Poisson arrivals of 2D consolidation / footing problems) through the
+    continuous-batching loop, FP64 then mixed, on the same trace."""
+    import torch
+    from paper_1905_00671_amd import serving as S
+    from paper_1905_00671_amd import workloads as W
+    trace = W.serving_trace(nreq=nreq)
+    out = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(0.8 * free)
+        rep = S.serve(trace, budget, realtime=realtime, **S.gpu_backend(prec))
+        torch.cuda.synchronize()
+        out[name] = rep.summary()
+        out[name]["budget_bytes"] = budget
+        print(f"[serve] {name}: {out[name]}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "serving: particle-steps/s with continuous batching; p50/p99 step and request latency",
+        "value": out["fp64"]["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream: {nreq} requests, Poisson arrivals at 20/s, 2D n=16..256 "
+                               f"(log-uniform), k=1e-16..1e-10, 20-50 steps, 50/50 consolidation (linear) / "
+                               f"footing (GIMP), dt=0.1 s, {'real-time arrivals' if realtime else 'idle gaps skipped'}"},
+        "fp64": out["fp64"],
+        "mixed": out["mixed"],
+        "mixed_vs_fp64": out["mixed"]["particle_steps_per_s"] / max(out["fp64"]["particle_steps_per_s"], 1e-300),
+    }
+    print(json.dumps(line))
+
+
 def main():
+    global WORKLOAD
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
@@ -206,10 +259,16 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--workload", choices=sorted(DESCR), default=WORKLOAD)
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving stream (continuous batching) instead of the footing step benchmark")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-no-wait", action="store_true", help="skip idle gaps between arrivals")
     ap.add_argument("--calibrate-mb", type=int, default=0,
                     help="before the run, stream a float32 tensor of this many MiB through one elementwise "
                          "kernel (read once, write once): the reference for hardware byte counters")
     args = ap.parse_args()
+    WORKLOAD = args.workload
     if args.gpus != 1:
         print(f"bench.py measures one MI355X: --gpus {args.gpus} is not supported (this build runs the hot path "
               f"on a single GPU; the multi-GPU decomposition is a design only).", file=sys.stderr)
@@ -218,6 +277,9 @@ def main():
     assert torch.cuda.is_available(), "a GPU is required"
     from paper_1905_00671_amd import binding as B
     B.lib()
+    if args.serve:
+        serve_bench(args.serve_requests, not args.serve_no_wait)
+        return
     if args.calibrate_mb > 0:
         a = torch.ones(args.calibrate_mb * 262144, dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
@@ -252,12 +314,10 @@ def main():
         "dtype": "f64" if head_prec == 0 else "mixed-f32/f64",
         "data": "synthetic",
         "config": {
-            "workload": "footing2d_large: 2D GIMP quasi-static rigid-footing half-model, 512x256 cells (h=0.0625 m) "
-                        "+16 empty rows, 524,288 points, neo-Hookean E=10 MPa nu=0.3, k from seed 0, "
-                        "dt=0.1 s, 5 mm/step, Newton 1e-8 per residual block",
+            "workload": DESCR[WORKLOAD],
             "points": w.particles.n,
             "grid_nodes": w.grid.nnode,
-            "dofs": w.grid.nnode * 3,
+            "dofs": w.grid.nnode * (w.grid.dim + 1),
             "k_m2": w.meta["k"],
         },
         "latency_ms": head["latency_ms"],
@@ -283,7 +343,7 @@ def main():
         line["mixed"]["roofline"] = roof32
     if not args.no_parity:
         line["parity"] = parity_check()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and WORKLOAD == "footing2d_large":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))
 

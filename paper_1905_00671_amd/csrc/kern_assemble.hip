@@ -11,6 +11,9 @@
 //               pair uniform per block: for each point reaching node i, the entries of all its
 //               column blocks J_ik come from one set of record loads; the node's fixed-stencil
 //               block row is accumulated in registers and written once (no atomics).
+// Points are bucketed by the first cell of their basis window, so the points that see node i at
+// window position l are exactly those of bucket i - l: both gathers loop over l at compile time
+// and every lane of a wavefront runs the same specialized code.
 // Residual terms (current configuration, dv = det(dF) V_n, grad S = dF^{-T} grad_n S):
 //   R_mom_i  = -(V_n/J_n) tau' grad S_i + dv p^h grad S_i + m S_i (g - a^h)       eq. residual-momentum
 //   R_mass_i = dv S_i theta + dv kappa grad S_i.(grad p^h - rho_f (g - a^h))       eq. residual-mass
@@ -38,7 +41,7 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     using L = RecLayout<DIM, WB>;
     const int bs = DIM + 1;
     const double* P = d->pw;
-    const int64_t s = d->ps, Np = d->Np;
+    const int64_t s = d->ps;
     const int64_t i = tid;
     double* rec = d->rec + i * L::N;
     double w[DIM][3], dw[DIM][3], s0v[DIM][3];
@@ -46,7 +49,6 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     for (int a = 0; a < DIM; ++a) {
         base[a] = basis_1d<SHAPE>(P[(PX + a) * s + i], P[(PLP + a) * s + i], d->x0[a], d->h, d->nc[a], w[a],
                                   dw[a], s0v[a]);
-        d->rbase[a * Np + i] = base[a];
         for (int k = 0; k < WB; ++k) {
             rec[L::W_ + a * WB + k] = w[a][k];
             rec[L::DW_ + a * WB + k] = dw[a][k];
@@ -190,13 +192,80 @@ __device__ __forceinline__ bool tile_node(const Dev* d, int64_t tile, int t, int
     return true;
 }
 
+// Points of the bucket (cell) n - l, l the window-local index LI of node n: exactly the points
+// whose basis window places node n at LI.  Returns false when that bucket is off the grid.
+template <int DIM, int WB, int LI>
+__device__ __forceinline__ bool bucket_of(const Dev* d, const int* n, int64_t* cid, int* p0, int* p1) {
+    constexpr int l0 = LI % WB, l1 = (LI / WB) % WB, l2 = DIM == 3 ? LI / (WB * WB) : 0;
+    const int c0 = n[0] - l0, c1 = n[1] - l1, c2 = DIM == 3 ? n[2] - l2 : 0;
+    if (c0 < 0 || c0 >= d->nc[0] || c1 < 0 || c1 >= d->nc[1]) return false;
+    if (DIM == 3 && (c2 < 0 || c2 >= d->nc[2])) return false;
+    *cid = c0 + (int64_t)d->nc[0] * (c1 + (int64_t)d->nc[1] * c2);
+    *p0 = d->cstart[*cid];
+    *p1 = d->cstart[*cid + 1];
+    return true;
+}
+
+// Residual contributions to node n of the points of bucket n - l (LI = window index of n).
+template <int DIM, int SHAPE, int LI>
+__device__ __forceinline__ void res_bucket(const Dev* __restrict__ d, const int* n, double* r) {
+    constexpr int WB = SHAPE ? 3 : 2;
+    constexpr int NN = DIM == 2 ? WB * WB : WB * WB * WB;
+    if constexpr (LI < NN) {
+        constexpr int li[3] = {LI % WB, (LI / WB) % WB, DIM == 3 ? LI / (WB * WB) : 0};
+        using L = RecLayout<DIM, WB>;
+        int64_t cid;
+        int p0, p1;
+        if (!bucket_of<DIM, WB, LI>(d, n, &cid, &p0, &p1)) p0 = p1 = 0, cid = 0;
+        // original MPM: Pi S_n of the cell, the same for every point of the bucket
+        const double pic = (SHAPE || p1 <= p0) ? 0.0 : d->cellpi[cid * NN + LI];
+        for (int p = p0; p < p1; ++p) {
+            const double* __restrict__ rc = d->rec + (int64_t)p * L::N;
+            double w[DIM], dw[DIM], Sv = 1.0, s0 = 1.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                w[a] = rc[L::W_ + a * WB + li[a]];
+                dw[a] = rc[L::DW_ + a * WB + li[a]];
+                if (SHAPE) s0 *= rc[L::S0_ + a * WB + li[a]];
+                Sv *= w[a];
+            }
+            double G[DIM], gS[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                double g = 1.0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) g *= (c == a) ? dw[c] : w[c];
+                G[a] = g;
+            }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                double t = 0.0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) t += rc[L::FI_ + c * DIM + a] * G[c];
+                gS[a] = t;
+            }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                double t = rc[L::BF_ + a] * Sv;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) t += rc[L::SG_ + a * DIM + c] * gS[c];
+                r[a] += t;
+            }
+            const double Pi = SHAPE ? s0 : pic;
+            double gw = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) gw += gS[a] * rc[L::QW_ + a];
+            r[DIM] += Sv * rc[L::DT_] + rc[L::DK_] * gw + rc[L::ST_] * (Sv - Pi);
+        }
+        res_bucket<DIM, SHAPE, LI + 1>(d, n, r);
+    }
+}
+
 template <int DIM, int SHAPE>
 __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
     const int q = batch_find(B, blockIdx.x);
     const Dev* __restrict__ d = B.d[q];
     const int64_t lb = blockIdx.x - B.pfx[q];
-    constexpr int WB = SHAPE ? 3 : 2;
-    using L = RecLayout<DIM, WB>;
     const int bs = DIM + 1;
     double ru2 = 0.0, rp2 = 0.0;
     bool bad = false;
@@ -204,70 +273,9 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
     int64_t row;
     if (tile_node<DIM>(d, lb, threadIdx.x, n, &row)) {
         const int64_t pn = pad_index(d, n[0], n[1], n[2]);
-        const int64_t Np = d->Np;
-        // cells holding points whose window reaches node n (a GIMP window starts at the point's
-        // cell or the one left of it)
-        int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
-        for (int a = 0; a < DIM; ++a) {
-            clo[a] = max(n[a] - (SHAPE ? 2 : 1), 0);
-            chi[a] = min(n[a] + (SHAPE ? 1 : 0), d->nc[a] - 1);
-        }
         double r[DIM + 1];
         for (int c = 0; c <= DIM; ++c) r[c] = 0.0;
-        for (int cz = clo[2]; cz <= chi[2]; ++cz)
-            for (int cy = clo[1]; cy <= chi[1]; ++cy) {
-                const int64_t rowc = (int64_t)d->nc[0] * (cy + (int64_t)d->nc[1] * cz);
-                const int p0 = d->cstart[rowc + clo[0]], p1 = d->cstart[rowc + chi[0] + 1];
-                for (int p = p0; p < p1; ++p) {
-                    int li[3] = {0, 0, 0}, bse[3] = {0, 0, 0};
-                    bool in = true;
-                    for (int a = 0; a < DIM; ++a) {
-                        bse[a] = d->rbase[a * Np + p];
-                        li[a] = n[a] - bse[a];
-                        if (li[a] < 0 || li[a] >= WB) in = false;
-                    }
-                    if (!in) continue;
-                    const double* __restrict__ rc = d->rec + (int64_t)p * L::N;
-                    double w[DIM], dw[DIM], Sv = 1.0, s0 = 1.0;
-                    for (int a = 0; a < DIM; ++a) {
-                        w[a] = rc[L::W_ + a * WB + li[a]];
-                        dw[a] = rc[L::DW_ + a * WB + li[a]];
-                        if (SHAPE) s0 *= rc[L::S0_ + a * WB + li[a]];
-                        Sv *= w[a];
-                    }
-                    double G[DIM], gS[DIM];
-                    for (int a = 0; a < DIM; ++a) {
-                        double g = 1.0;
-                        for (int c = 0; c < DIM; ++c) g *= (c == a) ? dw[c] : w[c];
-                        G[a] = g;
-                    }
-                    for (int a = 0; a < DIM; ++a) {
-                        double t = 0.0;
-                        for (int c = 0; c < DIM; ++c) t += rc[L::FI_ + c * DIM + a] * G[c];
-                        gS[a] = t;
-                    }
-                    for (int a = 0; a < DIM; ++a) {
-                        double t = rc[L::BF_ + a] * Sv;
-                        for (int c = 0; c < DIM; ++c) t += rc[L::SG_ + a * DIM + c] * gS[c];
-                        r[a] += t;
-                    }
-                    double Pi;
-                    if (SHAPE) {
-                        Pi = s0;
-                    } else {
-                        int64_t cid = 0, mul = 1, lin = 0;
-                        for (int a = 0; a < DIM; ++a) {
-                            cid += bse[a] * mul;
-                            mul *= d->nc[a];
-                            lin += (int64_t)li[a] << a;
-                        }
-                        Pi = d->cellpi[cid * (1 << DIM) + lin];
-                    }
-                    double gw = 0.0;
-                    for (int a = 0; a < DIM; ++a) gw += gS[a] * rc[L::QW_ + a];
-                    r[DIM] += Sv * rc[L::DT_] + rc[L::DK_] * gw + rc[L::ST_] * (Sv - Pi);
-                }
-            }
+        res_bucket<DIM, SHAPE, 0>(d, n, r);
         for (int c = 0; c <= DIM; ++c) {
             double v = r[c] + d->fext[pn * bs + c];
             if (!d->dfree[pn * bs + c]) v = 0.0;
@@ -306,9 +314,10 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
 //                   + dv kappa rho_f/(beta dt^2) gi_cc S_k
 //   ca = cc = dim : dv kappa gi.gk + tau c_t V_n (S_i - Pi_i)(S_k - Pi_k)
 // each written as u . gk + alpha S_k - gamma Pi_k = (f u) . grad_n S_k + alpha S_k - gamma Pi_k.
+// pic: the cell's Pi S_k (original MPM, PPP class only).
 template <int DIM, int SHAPE, int LI>
-__device__ __forceinline__ void jac_point(const Dev* __restrict__ d, const double* __restrict__ rc, int64_t cid,
-                                          int ca, int cc, double* acc) {
+__device__ __forceinline__ void jac_point(const double* __restrict__ rc, const double* pic, int ca, int cc,
+                                          double* acc) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int RR = SHAPE ? 2 : 1;
     constexpr int SW = 2 * RR + 1;
@@ -359,7 +368,10 @@ __device__ __forceinline__ void jac_point(const Dev* __restrict__ d, const doubl
     } else if (ca < DIM) {
 #pragma unroll
         for (int e = 0; e < DIM; ++e) u[e] = 0.0;
-        alpha = rc[L::DV_] * gi[ca];
+        double gia = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) gia += (e == ca) ? gi[e] : 0.0;
+        alpha = rc[L::DV_] * gia;
     } else if (cc < DIM) {
         const double bv = rc[L::BV_], dk = rc[L::DK_];
         double qw[DIM], giq = 0.0;
@@ -397,10 +409,8 @@ __device__ __forceinline__ void jac_point(const Dev* __restrict__ d, const doubl
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < NN; ++k) pik[k] = d->cellpi[cid * NN + k];
+            for (int k = 0; k < NN; ++k) pik[k] = pic[k];
         }
-        // Pi of the row node: the window index LI in the basis order of S0 / the cell's corner
-        // order (x fastest, two nodes per axis), which coincide for WB = 2
         gamma = rc[L::TC_] * (Si - pik[LI]);
         alpha = gamma;
     }
@@ -433,71 +443,60 @@ __device__ __forceinline__ void jac_point(const Dev* __restrict__ d, const doubl
             }
 }
 
+// All points of bucket n - l (LI = window index of n), then the next window index.
 template <int DIM, int SHAPE, int LI>
-__device__ __forceinline__ void jac_case(const Dev* d, const double* rc, int64_t cid, int ca, int cc, double* acc) {
+__device__ __forceinline__ void jac_bucket(const Dev* __restrict__ d, const int* n, int ca, int cc, double* acc) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int NN = DIM == 2 ? WB * WB : WB * WB * WB;
-    if constexpr (LI < NN) jac_point<DIM, SHAPE, LI>(d, rc, cid, ca, cc, acc);
+    if constexpr (LI < NN) {
+        using L = RecLayout<DIM, WB>;
+        int64_t cid;
+        int p0, p1;
+        if (bucket_of<DIM, WB, LI>(d, n, &cid, &p0, &p1)) {
+            double pic[NN];
+#pragma unroll
+            for (int k = 0; k < NN; ++k) pic[k] = 0.0;
+            if (!SHAPE && ca == DIM && cc == DIM && p1 > p0) {
+#pragma unroll
+                for (int k = 0; k < NN; ++k) pic[k] = d->cellpi[cid * NN + k];
+            }
+            for (int p = p0; p < p1; ++p) jac_point<DIM, SHAPE, LI>(d->rec + (int64_t)p * L::N, pic, ca, cc, acc);
+        }
+        jac_bucket<DIM, SHAPE, LI + 1>(d, n, ca, cc, acc);
+    }
 }
 
-// Jacobian, one thread per (row node, ca, cc): grid = (node tiles, b*b), blockIdx.y = ca*b + cc.
-// The node's block row over the fixed stencil is accumulated in registers and written once,
-// with the rows and columns of constrained dofs replaced by identity rows.
+// Block ids of the Jacobian: groups of XCDS tiles x b^2 component pairs; inside a group the b^2
+// blocks of one tile have ids that agree modulo XCDS, so with the round-robin placement of
+// workgroups on the XCDs they run on one XCD, close together in time, and read that tile's point
+// records through one L2 instead of once per component pair.
+constexpr int XCDS = 8;
+inline int64_t jacobian_blocks(int64_t ntile, int b) { return (ntile + XCDS - 1) / XCDS * XCDS * b * b; }
+
+// Jacobian, one thread per (row node, ca, cc), the component pair uniform per block.  The node's
+// block row over the fixed stencil is accumulated in registers and written once, with the rows
+// and columns of constrained dofs replaced by identity rows.
 template <int DIM, int SHAPE, typename T>
 __global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
     const int q = batch_find(B, blockIdx.x);
     const Dev* __restrict__ d = B.d[q];
     const int64_t lb = blockIdx.x - B.pfx[q];
-    constexpr int WB = SHAPE ? 3 : 2;
     constexpr int RR = SHAPE ? 2 : 1;
     constexpr int SW = 2 * RR + 1;
     constexpr int S = DIM == 2 ? SW * SW : SW * SW * SW;
     constexpr int BS = DIM + 1;
-    using L = RecLayout<DIM, WB>;
-    const int ca = blockIdx.y / BS, cc = blockIdx.y % BS;
+    constexpr int NP = BS * BS;
+    const int64_t grp = lb / (XCDS * NP), rem = lb % (XCDS * NP);
+    const int64_t tile = grp * XCDS + rem % XCDS;
+    const int pair = (int)(rem / XCDS);
+    const int ca = pair / BS, cc = pair % BS;
     int n[3];
     int64_t row;
-    if (!tile_node<DIM>(d, lb, threadIdx.x, n, &row)) return;
+    if (!tile_node<DIM>(d, tile, threadIdx.x, n, &row)) return;
     double acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0;
-    const int64_t Np = d->Np;
-    int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
-    for (int a = 0; a < DIM; ++a) {
-        clo[a] = max(n[a] - (SHAPE ? 2 : 1), 0);
-        chi[a] = min(n[a] + (SHAPE ? 1 : 0), d->nc[a] - 1);
-    }
-    for (int cz = clo[2]; cz <= chi[2]; ++cz)
-        for (int cy = clo[1]; cy <= chi[1]; ++cy) {
-            const int64_t rowc = (int64_t)d->nc[0] * (cy + (int64_t)d->nc[1] * cz);
-            const int p0 = d->cstart[rowc + clo[0]], p1 = d->cstart[rowc + chi[0] + 1];
-            for (int p = p0; p < p1; ++p) {
-                int li[3] = {0, 0, 0};
-                int64_t cid = 0, mul = 1;
-                bool in = true;
-                for (int a = 0; a < DIM; ++a) {
-                    const int bse = d->rbase[a * Np + p];
-                    li[a] = n[a] - bse;
-                    if (li[a] < 0 || li[a] >= WB) in = false;
-                    cid += bse * mul;
-                    mul *= d->nc[a];
-                }
-                if (!in) continue;
-                const double* rc = d->rec + (int64_t)p * L::N;
-                switch (li[0] + WB * (li[1] + WB * li[2])) {
-                    case 0: jac_case<DIM, SHAPE, 0>(d, rc, cid, ca, cc, acc); break;
-                    case 1: jac_case<DIM, SHAPE, 1>(d, rc, cid, ca, cc, acc); break;
-                    case 2: jac_case<DIM, SHAPE, 2>(d, rc, cid, ca, cc, acc); break;
-                    case 3: jac_case<DIM, SHAPE, 3>(d, rc, cid, ca, cc, acc); break;
-                    case 4: jac_case<DIM, SHAPE, 4>(d, rc, cid, ca, cc, acc); break;
-                    case 5: jac_case<DIM, SHAPE, 5>(d, rc, cid, ca, cc, acc); break;
-                    case 6: jac_case<DIM, SHAPE, 6>(d, rc, cid, ca, cc, acc); break;
-                    case 7: jac_case<DIM, SHAPE, 7>(d, rc, cid, ca, cc, acc); break;
-                    case 8: jac_case<DIM, SHAPE, 8>(d, rc, cid, ca, cc, acc); break;
-                    default: break;
-                }
-            }
-        }
+    jac_bucket<DIM, SHAPE, 0>(d, n, ca, cc, acc);
     const int64_t pni = pad_index(d, n[0], n[1], n[2]);
     const bool fr = d->dfree[pni * BS + ca] != 0;
     T* J = (T*)d->J;
@@ -568,8 +567,10 @@ void launch_assemble(const Group& g, bool want_J, hipStream_t st) {
 }
 
 void launch_jacobian(const Group& g, hipStream_t st) {
-    Batch Bn = make_batch_blocks(g.ddev, g.ntile);
-    const dim3 gr(Bn.pfx[Bn.n], g.b * g.b), tb(TPB);
+    std::vector<int64_t> nb;
+    for (auto t : g.ntile) nb.push_back(jacobian_blocks(t, g.b));
+    Batch Bn = make_batch_blocks(g.ddev, nb);
+    const dim3 gr(Bn.pfx[Bn.n]), tb(TPB);
     if (g.dim == 2 && g.shape == 0) {
         if (g.mixed) PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 0, float>), gr, tb, 0, st, Bn));
         else PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 0, double>), gr, tb, 0, st, Bn));

@@ -1,6 +1,7 @@
 // Particle-side kernels of one MPM step (Sec. 3.1, Stages 1, 3 and 4):
-//   counting sort of the material points into background cells (ties ordered by point id, so
-//   the order and every later sum are deterministic), the per-cell segmented reduction of the
+//   counting sort of the material points into buckets by the first cell of their basis window
+//   (the containing cell for original MPM; ties ordered by point id, so the order and every
+//   later sum are deterministic), the per-cell segmented reduction of the
 //   projection operator for original MPM (eq. projection-operator), lumped P2G as a per-node
 //   gather (eq. map-from-particles-to-nodes), and the G2P update with FLIP velocities and the
 //   GIMP domain update (Sec. 3.5).
@@ -84,7 +85,7 @@ __global__ void k_get_field(Batch B, int field, int ncomp, double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------------------------
-// counting sort into cells
+// counting sort into window-base buckets
 // ---------------------------------------------------------------------------------------------
 __global__ void k_zero_counts(Batch B) {
     PROB_PROLOGUE
@@ -101,8 +102,9 @@ __global__ void k_sort_keys(Batch B) {
     for (int a = 0; a < d->dim; ++a) {
         double xa = P[(PX + a) * s + tid];
         if (!(xa >= d->x0[a] && xa <= d->hi[a])) out = true;
-        int c = (int)floor((xa - d->x0[a]) / d->h);
-        c = c < 0 ? 0 : (c > d->nc[a] - 1 ? d->nc[a] - 1 : c);
+        // bucket = basis window base (the containing cell for original MPM)
+        int c = d->shape ? window_base<1>(xa, P[(PLP + a) * s + tid], d->x0[a], d->h, d->nc[a])
+                         : window_base<0>(xa, 0.0, d->x0[a], d->h, d->nc[a]);
         cid += c * mul;
         mul *= d->nc[a];
     }

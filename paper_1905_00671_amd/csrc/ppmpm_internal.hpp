@@ -121,7 +121,6 @@ struct Dev {
     double* cellpi;   // [Ncell * 2^dim] original-MPM projection Pi N
     // quadrature-point records
     double* rec;      // [Np][NREC] (one record per point)
-    int* rbase;       // [dim][Np] window base node per axis
     // Jacobian, fixed stencil block rows: J[((s*b + a)*b + c)*Nnode + row], precision T
     void* J;
     // Krylov vectors [Npad*b], precision T
@@ -190,6 +189,17 @@ __device__ __forceinline__ double hat_prim(double r, double h) {
 }
 __device__ __forceinline__ double hat_val(double r, double h) { return fmax(0.0, 1.0 - fabs(r) / h); }
 
+// First node of a particle's basis window along one axis (its sort bucket, too): original MPM
+// the cell containing x; GIMP the node at or left of the lower end of the domain [x-lp, x+lp]
+// clipped to the grid; clamped to the cells.  Sort keys and the basis use this one function, so
+// the bucket of a particle is exactly its window base.
+template <int SHAPE>
+__device__ __forceinline__ int window_base(double x, double lp, double x0, double h, int nc) {
+    const double a = SHAPE == 0 ? x : fmax(x - lp, x0);
+    int c = (int)floor((a - x0) / h);
+    return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+}
+
 // 1D basis of one particle along one axis.  Original MPM: the two nodes of the containing cell
 // (clamped), hat weights.  GIMP: the domain [x-lp, x+lp] clipped to the grid, three nodes from
 // the one at or left of its lower end; weight = domain average of the hat, gradient = domain
@@ -198,22 +208,18 @@ __device__ __forceinline__ double hat_val(double r, double h) { return fmax(0.0,
 template <int SHAPE>
 __device__ __forceinline__ int basis_1d(double x, double lp, double x0, double h, int nc, double* w,
                                         double* dw, double* s0) {
+    const int base = window_base<SHAPE>(x, lp, x0, h, nc);
     if (SHAPE == 0) {
-        int c = (int)floor((x - x0) / h);
-        c = c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
-        double xi = (x - (x0 + h * c)) / h;
+        double xi = (x - (x0 + h * base)) / h;
         w[0] = 1.0 - xi;
         w[1] = xi;
         dw[0] = -1.0 / h;
         dw[1] = 1.0 / h;
         s0[0] = s0[1] = 0.5;
-        return c;
     } else {
         double lo = x0, hi = x0 + h * nc;
         double a = fmax(x - lp, lo), bb = fmin(x + lp, hi);
         double len = bb - a;
-        int base = (int)floor((a - x0) / h);
-        base = base < 0 ? 0 : (base > nc - 1 ? nc - 1 : base);
         for (int k = 0; k < 3; ++k) {
             double xn = x0 + h * (base + k);
             w[k] = (hat_prim(bb - xn, h) - hat_prim(a - xn, h)) / len;
@@ -221,8 +227,8 @@ __device__ __forceinline__ int basis_1d(double x, double lp, double x0, double h
             double ov = fmin(bb, xn + h) - fmax(a, xn - h);
             s0[k] = ov > 0.0 ? 0.5 * ov / len : 0.0;
         }
-        return base;
     }
+    return base;
 }
 
 // ------------------------------------------------------------------------------------------------
