@@ -203,7 +203,9 @@ ppmpm_status ppmpm_eval_residual(ppmpm_problem* p, double dt, const ppmpm_bc* bc
 ppmpm_status ppmpm_apply_jacobian(ppmpm_problem* p, const double* v, double* y, int where);
 
 /* Nodal fields of the last Stage 1 (natural order): 0 lumped mass M, 1 P_n, 2 free-dof mask as
- * doubles [nnode*(dim+1)]. */
+ * doubles [nnode*(dim+1)]; 3 the Newton iterate [U, P] (node-interleaved, [nnode*(dim+1)]) that the
+ * last ppmpm_step / ppmpm_eval_residual used: after a successful step, the converged increments
+ * of Sec. 3.4 that the G2P update of Sec. 3.5 consumed. */
 ppmpm_status ppmpm_get_nodal(const ppmpm_problem* p, int field, double* out, int where);
 
 ppmpm_status ppmpm_destroy(ppmpm_problem* p);

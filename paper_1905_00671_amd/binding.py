@@ -254,7 +254,7 @@ class Problem:
 
     def get_nodal(self, field: int) -> np.ndarray:
         nn = int(np.prod([n + 1 for n in self.grid.ncell[: self.dim]]))
-        out = np.zeros(nn * (self.dim + 1) if field == 2 else nn)
+        out = np.zeros(nn * (self.dim + 1) if field >= 2 else nn)
         _check(self.L.ppmpm_get_nodal(self.h, field, _ptr(out), HOST))
         return out
 

@@ -311,6 +311,7 @@ __global__ void k_pad_to_nat(Batch B, double* __restrict__ out, int which) {
         if (which == 0) v = (double)vp<T>(d->kv)[k];
         else if (which == 1) v = d->Rv[k];
         else if (which == 2) v = (double)d->dfree[k];
+        else if (which == 3) v = d->X[k];
         else v = 0.0;
         out[tid * bs + a] = v;
     }
@@ -357,7 +358,9 @@ void launch_apply_jacobian(const Dev* dd, const Dev* hd, const double* v_nat, do
 
 void launch_nodal_out(const Dev* dd, const Dev* hd, int field, double* out, hipStream_t st) {
     Batch Bn = make_batch({dd}, {hd->Nnode}, TPB);
-    if (field == 2) {
+    if (field == 3) {
+        hipLaunchKernelGGL(k_pad_to_nat<double>, dim3(Bn.pfx[1]), dim3(TPB), 0, st, Bn, out, 3);
+    } else if (field == 2) {
         if (hd->mixed) hipLaunchKernelGGL(k_pad_to_nat<float>, dim3(Bn.pfx[1]), dim3(TPB), 0, st, Bn, out, 2);
         else hipLaunchKernelGGL(k_pad_to_nat<double>, dim3(Bn.pfx[1]), dim3(TPB), 0, st, Bn, out, 2);
     } else {

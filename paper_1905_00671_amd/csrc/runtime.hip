@@ -781,8 +781,8 @@ ppmpm_status ppmpm_apply_jacobian(ppmpm_problem* p, const double* v, double* y, 
 
 ppmpm_status ppmpm_get_nodal(const ppmpm_problem* pc, int field, double* out, int where) {
     ppmpm_problem* p = const_cast<ppmpm_problem*>(pc);
-    if (!p || !out || field < 0 || field > 2) return fail(PPMPM_E_INVALID, "bad get_nodal arguments");
-    const int64_t n = field == 2 ? p->h.Nnode * p->h.b : p->h.Nnode;
+    if (!p || !out || field < 0 || field > 3) return fail(PPMPM_E_INVALID, "bad get_nodal arguments");
+    const int64_t n = field >= 2 ? p->h.Nnode * p->h.b : p->h.Nnode;
     double* dst = where == PPMPM_DEVICE ? out : (double*)p->io;
     launch_nodal_out(p->d, &p->h, field, dst, p->st);
     HIPCHK(hipGetLastError());

@@ -1,0 +1,108 @@
+"""Parity at the full benchmark sizes, with the kernels and launch shapes bench.py times.
+
+Element-wise: the masked residual and J v at a random nodal state of the 512x256 GIMP footing
+(524,288 points) and of the 96^3 trilinear footing (7,077,888 points), against the oracle's
+material-point loops (matrix-free J v, so no sparse matrix is formed at these sizes).
+Whole step: one full time step of the 512x256 footing; the oracle evaluates its own residual at
+the GPU's converged Newton iterate (it must satisfy the Newton tolerance there) and applies its
+own G2P to that iterate, which must reproduce the GPU's particle state."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1905_00671_amd import workloads as W
+from tests.gpu_common import block_err, dyn_oracle_nodal, free_mask
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "footing2d_large": lambda: W.config(3),
+    "footing3d": lambda: W.footing3d(),
+}
+
+
+def _loads(bc, nn, d):
+    f = np.zeros((nn, d + 1))
+    f[:, :d] = bc["f_ext"].reshape(nn, d)
+    f[:, d] = -bc["q_ext"]
+    return f.reshape(-1)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fullsize_residual_and_jv(name):
+    from paper_1905_00671_amd import binding as B
+    w = CASES[name]()
+    g, d = w.grid, w.grid.dim
+    rng = np.random.default_rng(7)
+    print(f"[fullsize] {name}: {w.particles.n} points, {g.nnode} nodes", flush=True)
+    pr = O.from_workload(w)
+    bc = w.bc(1)
+    nodal = dyn_oracle_nodal(pr, bc)
+    act = nodal["active"]
+    free = free_mask(nodal, bc, d)
+    U = 2e-3 * g.h * (rng.random((g.nnode, d)) - 0.5) * act[:, None]
+    P = (nodal["Pn"] + 3e3 * (rng.random(g.nnode) - 0.5)) * act
+    v = rng.random(g.nnode * (d + 1)) - 0.5
+    v.reshape(-1, d + 1)[:, d] *= 1e6
+    R_or, _, Jv_or = pr.assemble(U, P, nodal, w.dt, want_J=False, vin=v * free)
+    R_or = (R_or + _loads(bc, g.nnode, d)) * free
+    Jv_or = np.where(free, Jv_or, v)
+    print("  oracle done", flush=True)
+    for precision in (0, 1):
+        gp = B.Problem.from_workload(w, precision=precision)
+        try:
+            R_gpu = gp.eval_residual(w.dt, bc, U, P)
+            assert np.array_equal(gp.get_nodal(2).astype(bool), free)
+            eu, ep = block_err(R_gpu, R_or, d)
+            print(f"  precision={precision} residual err u={eu:.2e} p={ep:.2e}", flush=True)
+            assert eu < 1e-11 and ep < 1e-11
+            y = gp.apply_jacobian(v)
+            eu, ep = block_err(y, Jv_or, d)
+            print(f"  precision={precision} J v err u={eu:.2e} p={ep:.2e}", flush=True)
+            tol = 1e-11 if precision == 0 else 2e-6
+            assert eu < tol and ep < tol
+        finally:
+            gp.close()
+
+
+def test_fullsize_step_footing2d():
+    from paper_1905_00671_amd import binding as B
+    w = W.config(3)
+    g, d = w.grid, w.grid.dim
+    nn = g.nnode
+    bc = w.bc(1)
+    gp = B.Problem.from_workload(w, precision=0)
+    try:
+        st = gp.step(w.dt, bc)
+        X = gp.get_nodal(3).reshape(nn, d + 1)
+        got = {k: gp.get(k) for k in ("u", "p", "x", "F")}
+    finally:
+        gp.close()
+    print(f"[fullsize step] newton={st['newton_iters']} krylov={st['krylov_iters']}", flush=True)
+    assert st["status"] == 0 and st["converged"]
+    U, P = X[:, :d].copy(), X[:, d].copy()
+    pr = O.from_workload(w)
+    nodal = dyn_oracle_nodal(pr, bc)
+    free = free_mask(nodal, bc, d)
+    loads = _loads(bc, nn, d)
+    # the Newton start of the step: Dirichlet increments, P_n elsewhere (p-hat on drained nodes)
+    act = nodal["active"]
+    ufix = bc["u_fixed"].astype(bool).reshape(nn, d)
+    pfix = bc["p_fixed"].astype(bool)
+    U0 = np.where(ufix, bc["u_inc"].reshape(nn, d), 0.0) * act[:, None]
+    P0 = np.where(pfix, bc["p_val"], nodal["Pn"]) * act
+    R0, _, _ = pr.assemble(U0, P0, nodal, w.dt, want_J=False)
+    R1, _, _ = pr.assemble(U, P, nodal, w.dt, want_J=False)
+    R0 = ((R0 + loads) * free).reshape(nn, d + 1)
+    R1 = ((R1 + loads) * free).reshape(nn, d + 1)
+    ru0, rp0 = np.linalg.norm(R0[:, :d]), np.linalg.norm(R0[:, d])
+    ru1, rp1 = np.linalg.norm(R1[:, :d]), np.linalg.norm(R1[:, d])
+    print(f"  oracle residual at the GPU iterate: u {ru1 / ru0:.2e}, p {rp1 / rp0:.2e} of the start", flush=True)
+    atol_u = 1e-12 * w.material.E * g.h ** (d - 1)
+    atol_p = 1e-12 * g.h ** d / w.dt
+    assert ru1 <= max(2e-8 * ru0, 2 * atol_u) and rp1 <= max(2e-8 * rp0, 2 * atol_p)
+    pr.g2p(U, P, nodal, w.dt)
+    for k, ref in (("u", pr.u), ("p", pr.p), ("x", pr.x), ("F", pr.F)):
+        err = np.abs(got[k] - ref).max() / max(np.abs(ref).max(), 1e-300)
+        print(f"  G2P {k}: max rel err {err:.2e}", flush=True)
+        assert err < 1e-10, k
