@@ -226,3 +226,53 @@ def test_failure_parity_overconstrained():
         assert np.array_equal(p.get("x"), x0)
     finally:
         p.close()
+
+
+def test_batch_larger_than_one_launch():
+    """More problems than one batched launch holds (64): the library splits the batch, and every
+    problem still matches its alone run bit for bit."""
+    B = _binding()
+    ks = [10.0 ** (-16 + 6 * i / 69) for i in range(70)]
+    ws = [W.consolidation2d(4 + (i % 3), ks[i], nsteps=1) for i in range(70)]
+    ps = [B.Problem.from_workload(w) for w in ws]
+    try:
+        st = B.step_batched(ps, [w.dt for w in ws], [w.bc(1) for w in ws])
+        assert all(s["status"] == 0 for s in st), [s["status"] for s in st]
+        got = [(p.get("u"), p.get("p")) for p in ps]
+    finally:
+        for p in ps:
+            p.close()
+    for i in (0, 33, 63, 64, 69):
+        w = ws[i]
+        p = B.Problem.from_workload(w)
+        try:
+            p.step(w.dt, w.bc(1))
+            assert np.array_equal(p.get("u"), got[i][0]) and np.array_equal(p.get("p"), got[i][1]), i
+        finally:
+            p.close()
+
+
+@pytest.mark.parametrize("case", ["undrained_k0", "no_stabilization", "one_point_per_cell"])
+def test_degenerate_cases_parity(case):
+    """Limits of the method: zero permeability (the pressure block is the stabilization term
+    alone), no PPP term (tau = 0, well-posed here because the column drains), and one point per
+    cell (the original-MPM projection equals the point value, so the PPP term vanishes)."""
+    if case == "undrained_k0":
+        w = W.terzaghi(k=0.0, nsteps=3)
+    elif case == "no_stabilization":
+        w = W.terzaghi(tau_kind=W.TAU_OFF, nsteps=3)
+    else:
+        w = W.consolidation2d(8, 1e-12, nsteps=2)
+        g = w.grid
+        xs = (np.arange(8) + 0.37) * g.h
+        X, Y = np.meshgrid(xs, xs, indexing="xy")
+        w.particles.x = np.stack([X.reshape(-1), Y.reshape(-1)], axis=1)
+        w.particles.vol = np.full(64, g.h * g.h)
+        w.particles.mass = w.material.rho0 * w.particles.vol
+        w.particles.lp = np.full((64, 2), 0.25 * g.h)
+    w.options.newton_rtol = 1e-10
+    w.options.krylov_rtol = 1e-12
+    print(f"[degenerate] {case}", flush=True)
+    errs = _run_steps(w, w.nsteps, 0)
+    for eu, ep, no, ng, kt in errs:
+        assert eu < 1e-10 and ep < 1e-10, errs
