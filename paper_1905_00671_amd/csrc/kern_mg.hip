@@ -239,16 +239,12 @@ __device__ __forceinline__ void row_update(const Dev* d, const Lv<T>& v, int64_t
     for (int a = 0; a < BB; ++a) x.at(pn, a) = (T)((double)x.at(pn, a) + d->omega * y[a]);
 }
 
-// coarse rhs of node I on level l+1 = (P^T r)_I (level-0 fine dofs masked by the free mask)
+// (P^T r)_I for coarse node I[] of level l+1 (level-0 fine dofs masked by the free mask)
 template <int DIM, int R, int BB, typename T>
-__device__ __forceinline__ void row_restrict(const Dev* d, int fam, int l, int64_t Irow, View<T> r, View<T> bc) {
+__device__ __forceinline__ void restrict_node(const Dev* d, int fam, int l, const int* I, View<T> r, double* acc) {
     const MgLevel& F = d->lev[l];
-    const MgLevel& C = d->lev[l + 1];
     const int fn[3] = {F.n[0], F.n[1], F.n[2]}, fz[3] = {F.cz[0], F.cz[1], F.cz[2]};
     const int fp0 = F.np[0], fp1 = F.np[1];
-    int I[3];
-    real_coords(Irow, C.n, DIM, I);
-    double acc[BB];
 #pragma unroll
     for (int a = 0; a < BB; ++a) acc[a] = 0.0;
     constexpr int nI = DIM == 3 ? 27 : 9;
@@ -275,23 +271,30 @@ __device__ __forceinline__ void row_restrict(const Dev* d, int fam, int l, int64
             }
         }
     }
+}
+
+// coarse rhs of node Irow on level l+1 = (P^T r)_I
+template <int DIM, int R, int BB, typename T>
+__device__ __forceinline__ void row_restrict(const Dev* d, int fam, int l, int64_t Irow, View<T> r, View<T> bc) {
+    const MgLevel& C = d->lev[l + 1];
+    int I[3];
+    real_coords(Irow, C.n, DIM, I);
+    double acc[BB];
+    restrict_node<DIM, R, BB, T>(d, fam, l, I, r, acc);
     const int64_t cpn = padded(I, C.np, R, DIM);
 #pragma unroll
     for (int a = 0; a < BB; ++a) bc.at(cpn, a) = (T)acc[a];
 }
 
-// x(fine node) += (P xc) (level-0 fine dofs masked)
+// (P xc) at fine node fi[] of level l, masked on level 0 (free dofs only)
 template <int DIM, int R, int BB, typename T>
-__device__ __forceinline__ void row_prolong(const Dev* d, int fam, int l, int64_t frow, View<T> xc, View<T> x) {
+__device__ __forceinline__ void prolong_node(const Dev* d, int fam, int l, const int* fi, int64_t fpn, View<T> xc,
+                                             double* acc) {
     const MgLevel& F = d->lev[l];
     const MgLevel& C = d->lev[l + 1];
     const int fn[3] = {F.n[0], F.n[1], F.n[2]}, fz[3] = {F.cz[0], F.cz[1], F.cz[2]};
     const int cn[3] = {C.n[0], C.n[1], C.n[2]};
     const int cp0 = C.np[0], cp1 = C.np[1];
-    int fi[3];
-    real_coords(frow, fn, DIM, fi);
-    const int64_t fpn = padded(fi, F.np, R, DIM);
-    double acc[BB];
 #pragma unroll
     for (int a = 0; a < BB; ++a) acc[a] = 0.0;
     constexpr int nI = DIM == 3 ? 8 : 4;
@@ -320,11 +323,23 @@ __device__ __forceinline__ void row_prolong(const Dev* d, int fam, int l, int64_
             for (int a = 0; a < BB; ++a) acc[a] += w * (double)xc.at(cpn, a);
         }
     }
+    if (l == 0) {
 #pragma unroll
-    for (int a = 0; a < BB; ++a) {
-        const double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
-        x.at(fpn, a) = (T)((double)x.at(fpn, a) + m * acc[a]);
+        for (int a = 0; a < BB; ++a) acc[a] *= mask0(d, fam, fpn, a);
     }
+}
+
+// x(fine node) += (P xc)
+template <int DIM, int R, int BB, typename T>
+__device__ __forceinline__ void row_prolong(const Dev* d, int fam, int l, int64_t frow, View<T> xc, View<T> x) {
+    const MgLevel& F = d->lev[l];
+    int fi[3];
+    real_coords(frow, F.n, DIM, fi);
+    const int64_t fpn = padded(fi, F.np, R, DIM);
+    double acc[BB];
+    prolong_node<DIM, R, BB, T>(d, fam, l, fi, fpn, xc, acc);
+#pragma unroll
+    for (int a = 0; a < BB; ++a) x.at(fpn, a) = (T)((double)x.at(fpn, a) + acc[a]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -556,7 +571,8 @@ __global__ void __launch_bounds__(TPB) k_mg_update(Batch B, int fam, int l, VRef
 template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_restrict(Batch B, int fam, int l, VRef rv, VRef bv) {
     PROB_PROLOGUE
-    if (krylov_done(d) || l >= d->ltail || l + 1 >= d->nlev || tid >= d->lev[l + 1].nrow) return;
+    // the transfer into the first tail level is done by the tail kernel
+    if (krylov_done(d) || l + 1 >= d->ltail || l + 1 >= d->nlev || tid >= d->lev[l + 1].nrow) return;
     row_restrict<DIM, R, BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, bv, fam, l + 1, BB));
 }
 
@@ -567,10 +583,212 @@ __global__ void __launch_bounds__(TPB) k_mg_prolong(Batch B, int fam, int l, VRe
     row_prolong<DIM, R, BB, T>(d, fam, l, tid, resolve<T>(d, xcv, fam, l + 1, BB), resolve<T>(d, xv, fam, l, BB));
 }
 
-// All levels from the problem's ltail down to the coarsest and back up, in one block.
-// Same conventions as the per-level kernels: on the way down a level's iterate is in LX and its
-// residual in LR; on the way up the prolongation adds the coarser correction (VK_SOL) into LX
-// and the last smoothing sweep writes the level's correction to LR (level 0: to out0).
+// ---------------------------------------------------------------------------------------------
+// Halo-tiled sweeps for V(1,1): one kernel per level on the way down and one on the way up.
+// A block owns a tile of the level (64 x 4 or 32 x 4 x 2 nodes, long in x so that a wavefront
+// reads each operator stream in contiguous runs) and first fills LDS for the tile plus a halo of
+// R nodes (component-major, conflict-free), then each thread finishes its node from LDS:
+//   down:  b = P^T r_fine (levels >= 1; the level's rhs on level 0), x0 = omega Dinv b in LDS,
+//          then r = b - A x0 for the tile (x0 and r written; b written on levels >= 1);
+//   up:    x' = x0 + P x_coarse in LDS, then out = x' + omega Dinv (b - A x') for the tile.
+// Halo nodes are computed by both neighbouring blocks (same inputs, same values); only the
+// owning block writes them.
+// ---------------------------------------------------------------------------------------------
+template <int DIM, int R>
+struct Tile {
+    static constexpr int TX = DIM == 2 ? MGT2X : MGT3X;
+    static constexpr int TY = DIM == 2 ? MGT2Y : MGT3Y;
+    static constexpr int TZ = DIM == 2 ? 1 : MGT3Z;
+    static constexpr int HX = TX + 2 * R, HY = TY + 2 * R, HZ = DIM == 2 ? 1 : TZ + 2 * R;
+    static constexpr int NS = HX * HY * HZ;
+    static_assert(TX * TY * TZ == TPB, "one thread per tile node");
+};
+
+template <int DIM>
+__device__ __forceinline__ void tile_origin(int64_t tile, int n0, int n1, int* o) {
+    constexpr int TX = DIM == 2 ? MGT2X : MGT3X, TY = DIM == 2 ? MGT2Y : MGT3Y, TZ = DIM == 2 ? 1 : MGT3Z;
+    const int ntx = (n0 + TX - 1) / TX, nty = (n1 + TY - 1) / TY;
+    o[0] = (int)(tile % ntx) * TX;
+    o[1] = (int)((tile / ntx) % nty) * TY;
+    o[2] = DIM == 3 ? (int)(tile / ((int64_t)ntx * nty)) * TZ : 0;
+}
+
+// level node of LDS slot j (tile origin o); false when it lies off the level grid
+template <int DIM, int R, typename T>
+__device__ __forceinline__ bool slot_node(const Lv<T>& v, const int* o, int j, int* c) {
+    using Tl = Tile<DIM, R>;
+    c[0] = o[0] + j % Tl::HX - R;
+    c[1] = o[1] + (j / Tl::HX) % Tl::HY - R;
+    c[2] = DIM == 3 ? o[2] + j / (Tl::HX * Tl::HY) - R : 0;
+    bool in = (unsigned)c[0] < (unsigned)v.n0 && (unsigned)c[1] < (unsigned)v.n1;
+    if (DIM == 3) in = in && (unsigned)c[2] < (unsigned)v.n2;
+    return in;
+}
+
+template <int DIM, int R, typename T>
+__device__ __forceinline__ int64_t level_pad(const Lv<T>& v, const int* c) {
+    int64_t p = (int64_t)(c[1] + R);
+    if (DIM == 3) p += (int64_t)v.np1 * (c[2] + R);
+    return (int64_t)(c[0] + R) + (int64_t)v.np0 * p;
+}
+
+// thread's own node: LDS slot, level coordinates; false when off the grid
+template <int DIM, int R, typename T>
+__device__ __forceinline__ bool own_node(const Lv<T>& v, const int* o, int* c, int* slot) {
+    using Tl = Tile<DIM, R>;
+    const int t = threadIdx.x;
+    const int tx = t % Tl::TX, ty = (t / Tl::TX) % Tl::TY, tz = DIM == 3 ? t / (Tl::TX * Tl::TY) : 0;
+    c[0] = o[0] + tx;
+    c[1] = o[1] + ty;
+    c[2] = o[2] + tz;
+    *slot = (tx + R) + Tl::HX * ((ty + R) + (DIM == 3 ? Tl::HY * (tz + R) : 0));
+    bool in = c[0] < v.n0 && c[1] < v.n1;
+    if (DIM == 3) in = in && c[2] < v.n2;
+    return in;
+}
+
+// acc -= sum_s A(s) xs[slot + offset(s)], the stencil walked per x-row (FULL: all rows unrolled)
+template <int DIM, int R, int BB, typename T, bool FULL>
+__device__ __forceinline__ void lds_stencil(const Lv<T>& v, int64_t row, const double* xs, int slot, double* acc) {
+    using Tl = Tile<DIM, R>;
+    using St = Sten<DIM, R>;
+    constexpr int SW = St::SW, NROW = St::S / SW;
+#pragma unroll(FULL ? (DIM == 3 ? 3 : NROW) : 1)
+    for (int t = 0; t < NROW; ++t) {
+        const int oy = t % SW - R, oz = DIM == 3 ? t / SW - R : 0;
+        const int srow = slot + Tl::HX * (oy + Tl::HY * oz);
+#pragma unroll
+        for (int i = 0; i < SW; ++i) {
+            const int s = t * SW + i;
+            const int sk = srow + i - R;
+#pragma unroll
+            for (int cc = 0; cc < BB; ++cc) {
+                const double xv = xs[cc * Tl::NS + sk];
+#pragma unroll
+                for (int a = 0; a < BB; ++a) acc[a] -= v.opv(s, a, cc, row) * xv;
+            }
+        }
+    }
+}
+
+template <int DIM, int R, int BB, typename T, bool FULL, bool RESTRICT>
+__global__ void __launch_bounds__(TPB) k_mg_down(Batch B, int fam, int l, VRef rhsv) {
+    using Tl = Tile<DIM, R>;
+    const int q = batch_find(B, blockIdx.x);
+    const Dev* __restrict__ d = B.d[q];
+    const int64_t tile = blockIdx.x - B.pfx[q];
+    if (krylov_done(d) || l >= d->ltail) return;
+    __shared__ double sx[Tl::NS * BB], sb[Tl::NS * BB];
+    const Lv<T> v = lv_of<BB, T>(d, fam, l);
+    View<T> rhs = resolve<T>(d, rhsv, fam, l, BB);
+    View<T> x = resolve<T>(d, VRef{VK_LX, 0}, fam, l, BB);
+    View<T> r = resolve<T>(d, VRef{VK_LR, 0}, fam, l, BB);
+    View<T> rf = resolve<T>(d, VRef{VK_LR, 0}, fam, RESTRICT ? l - 1 : l, BB);
+    int o[3];
+    tile_origin<DIM>(tile, v.n0, v.n1, o);
+    const double om = d->omega;
+    for (int j = threadIdx.x; j < Tl::NS; j += TPB) {
+        int c[3];
+        double bk[BB], xk[BB];
+#pragma unroll
+        for (int a = 0; a < BB; ++a) bk[a] = xk[a] = 0.0;
+        if (slot_node<DIM, R>(v, o, j, c)) {
+            const int64_t pn = level_pad<DIM, R>(v, c);
+            if (RESTRICT) {
+                restrict_node<DIM, R, BB, T>(d, fam, l - 1, c, rf, bk);
+                // round to the storage precision, as the stored rhs is what the up-sweep reads
+#pragma unroll
+                for (int a = 0; a < BB; ++a) bk[a] = (double)(T)bk[a];
+                const int hx = j % Tl::HX - R, hy = (j / Tl::HX) % Tl::HY - R,
+                          hz = DIM == 3 ? j / (Tl::HX * Tl::HY) - R : 0;
+                const bool owned = hx >= 0 && hx < Tl::TX && hy >= 0 && hy < Tl::TY && hz >= 0 && hz < Tl::TZ;
+                if (owned) {
+#pragma unroll
+                    for (int a = 0; a < BB; ++a) rhs.at(pn, a) = (T)bk[a];
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < BB; ++a) bk[a] = (double)rhs.at(pn, a);
+            }
+            const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
+            dinv_apply<BB>(v, row, bk, xk);
+#pragma unroll
+            for (int a = 0; a < BB; ++a) xk[a] = (double)(T)(om * xk[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < BB; ++a) {
+            sb[a * Tl::NS + j] = bk[a];
+            sx[a * Tl::NS + j] = xk[a];
+        }
+    }
+    __syncthreads();
+    int c[3], slot;
+    if (!own_node<DIM, R>(v, o, c, &slot)) return;
+    const int64_t pn = level_pad<DIM, R>(v, c);
+    const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
+    double acc[BB];
+#pragma unroll
+    for (int a = 0; a < BB; ++a) acc[a] = sb[a * Tl::NS + slot];
+    lds_stencil<DIM, R, BB, T, FULL>(v, row, sx, slot, acc);
+    if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * sx[slot];
+#pragma unroll
+    for (int a = 0; a < BB; ++a) {
+        x.at(pn, a) = (T)sx[a * Tl::NS + slot];
+        r.at(pn, a) = (T)acc[a];
+    }
+}
+
+template <int DIM, int R, int BB, typename T, bool FULL>
+__global__ void __launch_bounds__(TPB) k_mg_up(Batch B, int fam, int l, VRef rhsv, VRef outv) {
+    using Tl = Tile<DIM, R>;
+    const int q = batch_find(B, blockIdx.x);
+    const Dev* __restrict__ d = B.d[q];
+    const int64_t tile = blockIdx.x - B.pfx[q];
+    if (krylov_done(d) || l >= d->ltail) return;
+    __shared__ double sx[Tl::NS * BB];
+    const Lv<T> v = lv_of<BB, T>(d, fam, l);
+    View<T> rhs = resolve<T>(d, rhsv, fam, l, BB);
+    View<T> x = resolve<T>(d, VRef{VK_LX, 0}, fam, l, BB);
+    View<T> xc = resolve<T>(d, VRef{VK_SOL, 0}, fam, l + 1, BB);
+    View<T> out = resolve<T>(d, outv, fam, l, BB);
+    int o[3];
+    tile_origin<DIM>(tile, v.n0, v.n1, o);
+    for (int j = threadIdx.x; j < Tl::NS; j += TPB) {
+        int c[3];
+        double xk[BB];
+#pragma unroll
+        for (int a = 0; a < BB; ++a) xk[a] = 0.0;
+        if (slot_node<DIM, R>(v, o, j, c)) {
+            const int64_t pn = level_pad<DIM, R>(v, c);
+            double pc[BB];
+            prolong_node<DIM, R, BB, T>(d, fam, l, c, pn, xc, pc);
+            // the iterate is stored in precision T after the prolongation
+#pragma unroll
+            for (int a = 0; a < BB; ++a) xk[a] = (double)(T)((double)x.at(pn, a) + pc[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < BB; ++a) sx[a * Tl::NS + j] = xk[a];
+    }
+    __syncthreads();
+    int c[3], slot;
+    if (!own_node<DIM, R>(v, o, c, &slot)) return;
+    const int64_t pn = level_pad<DIM, R>(v, c);
+    const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
+    double acc[BB], y[BB];
+#pragma unroll
+    for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
+    lds_stencil<DIM, R, BB, T, FULL>(v, row, sx, slot, acc);
+    if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * sx[slot];
+    dinv_apply<BB>(v, row, acc, y);
+#pragma unroll
+    for (int a = 0; a < BB; ++a) out.at(pn, a) = (T)(sx[a * Tl::NS + slot] + d->omega * y[a]);
+}
+
+// All levels from the problem's ltail down to the coarsest and back up, in one block, starting
+// with the restriction of the residual of level ltail-1.  Same conventions as the per-level
+// kernels: on the way down a level's iterate is in LX and its residual in LR; on the way up the
+// prolongation adds the coarser correction (VK_SOL) into LX and the last smoothing sweep writes
+// the level's correction to LR (level 0: to out0).
 constexpr int TAIL_TPB = 256;
 template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs0, VRef out0) {
@@ -580,6 +798,14 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
     const int L0 = d->ltail, L = d->nlev, nsm = d->mg_nsm;
     const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0}, SOL{VK_SOL, 0};
     const int nt = blockDim.x;
+    if (L0 > 0) {
+        // right-hand side of the first tail level from the residual of the level above it
+        View<T> rf = resolve<T>(d, LR, fam, L0 - 1, BB);
+        View<T> bc = resolve<T>(d, LB, fam, L0, BB);
+        const int64_t nc = d->lev[L0].nrow;
+        for (int64_t i = threadIdx.x; i < nc; i += nt) row_restrict<DIM, R, BB, T>(d, fam, L0 - 1, i, rf, bc);
+        __syncthreads();
+    }
     for (int l = L0; l < L - 1; ++l) {
         const Lv<T> v = lv_of<BB, T>(d, fam, l);
         const bool fs0 = fam == 1 && l == 0;
@@ -733,7 +959,6 @@ void launch_precond_setup(const Group& g, const std::vector<const Dev*>& hc, hip
     }
 }
 
-// One batched V-cycle of family fam (block BB): rhs0 / out0 are the level-0 Krylov references.
 // Down-sweep of one level: pre-smoothing from a zero guess (iterate -> LX, residual -> LR) and
 // restriction of the residual to the next level's right-hand side.
 template <int DIM, int R, int BB, typename T, bool FULL>
@@ -774,24 +999,58 @@ static void vcycle_up(const Group& g, const std::vector<const Dev*>& hc, int fam
               hipLaunchKernelGGL((k_mg_post<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, out));
 }
 
+
+static std::vector<int64_t> level_tiles(const std::vector<const Dev*>& hc, int l) {
+    std::vector<int64_t> v;
+    for (auto* h : hc) v.push_back(l < h->nlev ? mg_tiles(h->dim, h->lev[l].n) : 1);
+    return v;
+}
+
 // One batched V-cycle of family fam (block BB): rhs0 / out0 are the level-0 Krylov references.
-// Level 0 walks its stencil row by row (occupancy hides latency there); the coarser levels,
-// whose grids cover a few CUs only, use fully unrolled rows.
+// V(1,1): one halo-tiled kernel per level and direction; the fine level walks its stencil row by
+// row (occupancy hides latency there), the coarser levels unroll it (their grids cover a few CUs
+// only).  More smoothing sweeps use the per-operation kernels.
 template <int DIM, int R, int BB, typename T>
 static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, VRef rhs0, VRef out0, int nsm,
                    hipStream_t st) {
     const int Lstd = max_ltail(hc);
-    const VRef LR{VK_LR, 0}, LB{VK_LB, 0};
-    for (int l = 0; l < Lstd; ++l) {
-        if (l == 0) vcycle_down<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, nsm, st);
-        else vcycle_down<DIM, R, BB, T, true>(g, hc, fam, l, LB, nsm, st);
+    const VRef LR{VK_LR, 0}, LB{VK_LB, 0}, LX{VK_LX, 0};
+    const dim3 tb(TPB);
+    if (nsm == 1) {
+        for (int l = 0; l < Lstd; ++l) {
+            Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
+            const dim3 gt(Bt.pfx[Bt.n]);
+            if (l == 0)
+                PPM_TIMED(KT_MG0_RESID, st,
+                          hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, false, false>), gt, tb, 0, st, Bt, fam, 0, rhs0));
+            else
+                hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, true, true>), gt, tb, 0, st, Bt, fam, l, LB);
+        }
+    } else {
+        for (int l = 0; l < Lstd; ++l) {
+            if (l == 0) vcycle_down<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, nsm, st);
+            else vcycle_down<DIM, R, BB, T, true>(g, hc, fam, l, LB, nsm, st);
+        }
     }
     Batch B1 = make_batch_one_block(g.ddev);
     hipLaunchKernelGGL((k_mg_tail<DIM, R, BB, T>), dim3(B1.n), dim3(TAIL_TPB), 0, st, B1, fam, rhs0, out0);
-    for (int l = Lstd - 1; l >= 0; --l) {
-        if (l == 0) vcycle_up<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, out0, nsm, st);
-        else vcycle_up<DIM, R, BB, T, true>(g, hc, fam, l, LB, LR, nsm, st);
+    if (nsm == 1) {
+        for (int l = Lstd - 1; l >= 0; --l) {
+            Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
+            const dim3 gt(Bt.pfx[Bt.n]);
+            if (l == 0)
+                PPM_TIMED(KT_MG0_RESID, st,
+                          hipLaunchKernelGGL((k_mg_up<DIM, R, BB, T, false>), gt, tb, 0, st, Bt, fam, 0, rhs0, out0));
+            else
+                hipLaunchKernelGGL((k_mg_up<DIM, R, BB, T, true>), gt, tb, 0, st, Bt, fam, l, LB, LR);
+        }
+    } else {
+        for (int l = Lstd - 1; l >= 0; --l) {
+            if (l == 0) vcycle_up<DIM, R, BB, T, false>(g, hc, fam, l, rhs0, out0, nsm, st);
+            else vcycle_up<DIM, R, BB, T, true>(g, hc, fam, l, LB, LR, nsm, st);
+        }
     }
+    (void)LX;
 }
 
 // z = P^-1 y on Krylov vectors iy -> iz: Schur block first, then A

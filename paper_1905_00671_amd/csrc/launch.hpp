@@ -69,6 +69,12 @@ inline int64_t node_tiles(int dim, const int* nn) {
     return (int64_t)((nn[0] + TILE3X - 1) / TILE3X) * ((nn[1] + TILE3Y - 1) / TILE3Y) * ((nn[2] + TILE3Z - 1) / TILE3Z);
 }
 
+// Tiles of the multigrid sweeps covering a level of n nodes per axis.
+inline int64_t mg_tiles(int dim, const int* n) {
+    if (dim == 2) return (int64_t)((n[0] + MGT2X - 1) / MGT2X) * ((n[1] + MGT2Y - 1) / MGT2Y);
+    return (int64_t)((n[0] + MGT3X - 1) / MGT3X) * ((n[1] + MGT3Y - 1) / MGT3Y) * ((n[2] + MGT3Z - 1) / MGT3Z);
+}
+
 inline Batch make_batch_one_block(const std::vector<const Dev*>& dd) {
     Batch B{};
     B.n = (int)dd.size();
