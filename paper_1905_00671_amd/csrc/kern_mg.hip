@@ -348,7 +348,7 @@ __device__ __forceinline__ void row_prolong(const Dev* d, int fam, int l, int64_
 template <int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_dinv(Batch B, int fam, int l) {
     PROB_PROLOGUE
-    if (l >= d->nlev) return;
+    if (l >= d->nlev || (fam == 1 && l > d->ls_stop)) return;
     const MgLevel& L = d->lev[l];
     if (tid >= L.nrow) return;
     Op<T> o = op_of<T>(d, fam, l);
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(TPB) k_mg_dinv(Batch B, int fam, int l) {
 template <int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_rap(Batch B, int fam, int l) {
     PROB_PROLOGUE
-    if (l + 1 >= d->nlev) return;
+    if (l + 1 >= d->nlev || (fam == 1 && l + 1 > d->ls_stop)) return;
     const MgLevel& F = d->lev[l];
     const MgLevel& C = d->lev[l + 1];
     if (tid >= C.nrow) return;
@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(256) k_mg_coarse_setup(Batch B, int fam) {
     const MgLevel& L = d->lev[l];
     const int dim = d->dim, R = d->R;
     const int n = (int)(L.nrow * BB);
-    if (n > CMAX) return;
+    if (n > CMAX || (fam == 1 && d->ls_stop < d->ltail)) return;
     __shared__ double M[CMAX][CMAX + 1];
     __shared__ int perm[CMAX];
     __shared__ int piv;
@@ -677,7 +677,7 @@ __global__ void __launch_bounds__(TPB) k_mg_down(Batch B, int fam, int l, VRef r
     const int q = batch_find(B, blockIdx.x);
     const Dev* __restrict__ d = B.d[q];
     const int64_t tile = blockIdx.x - B.pfx[q];
-    if (krylov_done(d) || l >= d->ltail) return;
+    if (krylov_done(d) || l >= d->ltail || (fam == 1 && l > d->ls_stop)) return;
     __shared__ double sx[Tl::NS * BB], sb[Tl::NS * BB];
     const Lv<T> v = lv_of<BB, T>(d, fam, l);
     View<T> rhs = resolve<T>(d, rhsv, fam, l, BB);
@@ -744,7 +744,10 @@ __global__ void __launch_bounds__(TPB) k_mg_up(Batch B, int fam, int l, VRef rhs
     const int q = batch_find(B, blockIdx.x);
     const Dev* __restrict__ d = B.d[q];
     const int64_t tile = blockIdx.x - B.pfx[q];
-    if (krylov_done(d) || l >= d->ltail) return;
+    if (krylov_done(d) || l >= d->ltail || (fam == 1 && l > d->ls_stop)) return;
+    // last level of a truncated Schur hierarchy: no coarser correction, so that the down and up
+    // kernels of this level are two damped Jacobi sweeps
+    const bool coarse = !(fam == 1 && l == d->ls_stop);
     __shared__ double sx[Tl::NS * BB];
     const Lv<T> v = lv_of<BB, T>(d, fam, l);
     View<T> rhs = resolve<T>(d, rhsv, fam, l, BB);
@@ -761,7 +764,9 @@ __global__ void __launch_bounds__(TPB) k_mg_up(Batch B, int fam, int l, VRef rhs
         if (slot_node<DIM, R>(v, o, j, c)) {
             const int64_t pn = level_pad<DIM, R>(v, c);
             double pc[BB];
-            prolong_node<DIM, R, BB, T>(d, fam, l, c, pn, xc, pc);
+#pragma unroll
+            for (int a = 0; a < BB; ++a) pc[a] = 0.0;
+            if (coarse) prolong_node<DIM, R, BB, T>(d, fam, l, c, pn, xc, pc);
             // the iterate is stored in precision T after the prolongation
 #pragma unroll
             for (int a = 0; a < BB; ++a) xk[a] = (double)(T)((double)x.at(pn, a) + pc[a]);
@@ -794,7 +799,7 @@ template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs0, VRef out0) {
     const int q = blockIdx.x;
     const Dev* d = B.d[q];
-    if (krylov_done(d)) return;
+    if (krylov_done(d) || (fam == 1 && d->ls_stop < d->ltail)) return;
     const int L0 = d->ltail, L = d->nlev, nsm = d->mg_nsm;
     const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0}, SOL{VK_SOL, 0};
     const int nt = blockDim.x;
@@ -933,20 +938,30 @@ static int max_ltail(const std::vector<const Dev*>& hc) {
 template <int DIM, typename T>
 static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, hipStream_t st) {
     const int Lmax = max_levels(hc);
+    // deepest level of the Schur hierarchy over the batch (truncated hierarchies stop at ls_stop)
+    int LmaxS = 0;
+    bool full_s = false;
+    for (auto* h : hc) {
+        if (h->ls_stop < h->ltail) LmaxS = std::max(LmaxS, h->ls_stop + 1);
+        else {
+            LmaxS = std::max(LmaxS, h->nlev);
+            full_s = true;
+        }
+    }
     for (int l = 0; l < Lmax; ++l) {
         // the coarse operator of level l is needed before its inverse diagonal
         if (l > 0) {
             Batch Bc = make_batch(g.ddev, level_rows(hc, l), TPB);
             PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l - 1));
-            hipLaunchKernelGGL((k_mg_rap<1, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
+            if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap<1, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
         }
         Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
         hipLaunchKernelGGL((k_mg_dinv<DIM, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 0, l);
-        hipLaunchKernelGGL((k_mg_dinv<1, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 1, l);
+        if (l < LmaxS) hipLaunchKernelGGL((k_mg_dinv<1, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 1, l);
     }
     Batch B1 = make_batch_one_block(g.ddev);
     hipLaunchKernelGGL((k_mg_coarse_setup<DIM, T>), dim3(B1.n), dim3(256), 0, st, B1, 0);
-    hipLaunchKernelGGL((k_mg_coarse_setup<1, T>), dim3(B1.n), dim3(256), 0, st, B1, 1);
+    if (full_s) hipLaunchKernelGGL((k_mg_coarse_setup<1, T>), dim3(B1.n), dim3(256), 0, st, B1, 1);
 }
 
 void launch_precond_setup(const Group& g, const std::vector<const Dev*>& hc, hipStream_t st) {
@@ -1013,7 +1028,21 @@ static std::vector<int64_t> level_tiles(const std::vector<const Dev*>& hc, int l
 template <int DIM, int R, int BB, typename T>
 static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, VRef rhs0, VRef out0, int nsm,
                    hipStream_t st) {
-    const int Lstd = max_ltail(hc);
+    int Lstd = max_ltail(hc);
+    bool need_tail = true;
+    if (fam == 1) {
+        // truncated Schur hierarchies end at ls_stop (down and up there, no tail)
+        int L = 0;
+        need_tail = false;
+        for (auto* h : hc) {
+            if (h->ls_stop < h->ltail) L = std::max(L, h->ls_stop + 1);
+            else {
+                L = std::max(L, h->ltail);
+                need_tail = true;
+            }
+        }
+        Lstd = L;
+    }
     const VRef LR{VK_LR, 0}, LB{VK_LB, 0}, LX{VK_LX, 0};
     const dim3 tb(TPB);
     if (nsm == 1) {
@@ -1033,7 +1062,8 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
         }
     }
     Batch B1 = make_batch_one_block(g.ddev);
-    hipLaunchKernelGGL((k_mg_tail<DIM, R, BB, T>), dim3(B1.n), dim3(TAIL_TPB), 0, st, B1, fam, rhs0, out0);
+    if (need_tail)
+        hipLaunchKernelGGL((k_mg_tail<DIM, R, BB, T>), dim3(B1.n), dim3(TAIL_TPB), 0, st, B1, fam, rhs0, out0);
     if (nsm == 1) {
         for (int l = Lstd - 1; l >= 0; --l) {
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));

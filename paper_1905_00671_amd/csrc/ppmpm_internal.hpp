@@ -95,6 +95,7 @@ struct Dev {
     double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
     int nlev;
     int ltail;    // first level handled by the fused small-level kernel
+    int ls_stop;  // Schur-block hierarchy ends here with two Jacobi sweeps (>= ltail: not truncated)
     int mg_nsm;
     // particles
     double* pc;   // committed state

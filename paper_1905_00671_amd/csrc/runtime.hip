@@ -286,6 +286,25 @@ double stab_tau(const ppmpm_options* o, double lam, double G, double kappa, doub
     return o->tau_scale * std::max(t, 0.0);
 }
 
+// Depth of the Schur-block (S) multigrid.  S is a pressure mass term (c_t/K) M_p plus a Darcy
+// diffusion term; on level l their ratio is the diffusion number Fo_l = kappa K / (c_t h_l^2)
+// (h_l the smallest node spacing of the level).  Below the first level l >= 1 with Fo_l < 1/4
+// the operator is close to a scaled mass matrix, which two damped Jacobi sweeps invert well
+// enough, so the S cycle ends there (V(1,1) only; ltail or more means the full hierarchy).
+int schur_truncation(const Dev& h) {
+    if (h.mg_nsm != 1) return MAXLEV;
+    const double kK = h.kappa * h.Kfs / h.ct;
+    for (int l = 1; l < h.ltail; ++l) {
+        double hmin = 1e300;
+        for (int a = 0; a < h.dim; ++a) {
+            const double sp = h.h * (double)(h.nn[a] - 1) / (double)(h.lev[l].n[a] - 1);
+            hmin = std::min(hmin, sp);
+        }
+        if (kK / (hmin * hmin) < 0.25) return l;
+    }
+    return MAXLEV;
+}
+
 ppmpm_status upload_desc(ppmpm_problem* p) {
     *p->hpin = p->h;
     HIPCHK(hipMemcpyAsync(p->d, p->hpin, sizeof(Dev), hipMemcpyHostToDevice, p->st));
@@ -364,6 +383,7 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
         // 2 for the 2D stencils and near 3.2 for the 27-point trilinear one
         h.omega = h.dim == 3 ? 0.5 : 0.7;
         h.mg_nsm = std::max(1, o->mg_smooth);
+        h.ls_stop = schur_truncation(h);
         ppmpm_status s = upload_desc(p);
         if (s) return s;
         HIPCHK(hipMemsetAsync(h.flags, 0, sizeof(int) * NFLAG, st));
@@ -455,6 +475,7 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     h.gamma = opt->gamma;
     h.omega = h.dim == 3 ? 0.5 : 0.7;
     h.mg_nsm = std::max(1, opt->mg_smooth);
+    h.ls_stop = MAXLEV;
     {
         hipError_t e = hipHostMalloc((void**)&p->hpin, sizeof(Dev));
         if (e == hipSuccess) e = hipHostMalloc((void**)&p->spin, sizeof(double) * NSCAL);
