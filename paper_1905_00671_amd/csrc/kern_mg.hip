@@ -366,7 +366,8 @@ __global__ void __launch_bounds__(TPB) k_mg_dinv(Batch B, int fam, int l) {
     for (int k = 0; k < BB * BB; ++k) out[(int64_t)k * L.nrow + tid] = (T)Ai[k];
 }
 
-// Galerkin coarse operator of level l+1: thread per (coarse row, stencil entry)
+// Galerkin coarse operator of level l+1 (2D): thread per (coarse row, stencil entry), looping
+// over the candidate pairs of the two coarse nodes
 template <int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_rap(Batch B, int fam, int l) {
     PROB_PROLOGUE
@@ -437,6 +438,107 @@ __global__ void __launch_bounds__(TPB) k_mg_rap(Batch B, int fam, int l) {
     T* out = (T*)(fam == 0 ? C.A : C.Sm);
     for (int a = 0; a < BB; ++a)
         for (int c = 0; c < BB; ++c) out[((int64_t)(s * BB + a) * BB + c) * C.nrow + tid] = (T)blk[a * BB + c];
+}
+
+// Galerkin coarse operator of level l+1 (3D), one thread per (coarse row I, component pair (a, c)):
+// for every fine candidate i of I (weight P_iI) and every stencil entry delta of fine row i,
+// A_f(i, i + delta) goes to the coarse parents J of j = i + delta with weight P_iI P_jJ.  On a
+// coarsened axis i = 2I - 1 + k and j = 2I + m with m = k + delta - 1, so the parents of j sit
+// at J - I = m/2 (m even) or (m-1)/2 + {0, 1} (m odd); on other axes J = j.  Each thread owns a
+// column of stencil-slot accumulators in LDS (no sharing, fixed summation order).
+__device__ __forceinline__ int rap_parents(int cz, int k, int dl, int* off) {
+    if (!cz) {
+        off[0] = dl;
+        return k == 1 ? 1 : 0;
+    }
+    const int m = k + dl - 1;
+    if ((m & 1) == 0) {
+        off[0] = m / 2;
+        return 1;
+    }
+    off[0] = (m - 1) / 2;
+    off[1] = off[0] + 1;
+    return 2;
+}
+
+template <int DIM, int R, int BB, typename T>
+__global__ void __launch_bounds__(TPB) k_mg_rap2(Batch B, int fam, int l) {
+    constexpr int SW = 2 * R + 1;
+    constexpr int S = DIM == 2 ? SW * SW : SW * SW * SW;
+    __shared__ double sacc[S * TPB];
+    PROB_PROLOGUE
+    if (l + 1 >= d->nlev || (fam == 1 && l + 1 > d->ls_stop)) return;
+    const MgLevel& F = d->lev[l];
+    const MgLevel& C = d->lev[l + 1];
+    if (tid >= C.nrow) return;
+    const int a = blockIdx.y / BB, c = blockIdx.y % BB;
+    double* acc = sacc + threadIdx.x;   // slot s at acc[s * TPB]
+    for (int s = 0; s < S; ++s) acc[s * TPB] = 0.0;
+    const int fn[3] = {F.n[0], F.n[1], F.n[2]}, cn[3] = {C.n[0], C.n[1], C.n[2]};
+    const int cz[3] = {F.cz[0], F.cz[1], DIM == 3 ? F.cz[2] : 0};
+    Op<T> o = op_of<T>(d, fam, l);
+    int I[3];
+    real_coords(tid, C.n, DIM, I);
+    constexpr int NK = DIM == 2 ? 9 : 27;
+    for (int kk = 0; kk < NK; ++kk) {
+        const int k[3] = {kk % 3, (kk / 3) % 3, kk / 9};
+        int fi[3] = {0, 0, 0};
+        double wi = 1.0;
+        for (int ax = 0; ax < DIM; ++ax) {
+            if (!cz[ax] && k[ax] != 1) wi = 0.0;
+            fi[ax] = cz[ax] ? 2 * I[ax] - 1 + k[ax] : I[ax];
+            if (fi[ax] < 0 || fi[ax] >= fn[ax]) wi = 0.0;
+            if (wi != 0.0) wi *= pwa(fi[ax], I[ax], fn[ax], cz[ax]);
+        }
+        if (wi == 0.0) continue;
+        const int64_t frow = fi[0] + (int64_t)fn[0] * (fi[1] + (int64_t)fn[1] * fi[2]);
+        const int64_t fpn = padded(fi, F.np, d->R, DIM);
+        if (l == 0 && mask0(d, fam, fpn, a) == 0.0) continue;
+        for (int s = 0; s < S; ++s) {
+            const int dl[3] = {s % SW - R, (s / SW) % SW - R, DIM == 3 ? s / (SW * SW) - R : 0};
+            int fj[3] = {0, 0, 0};
+            bool jok = true;
+            for (int ax = 0; ax < DIM; ++ax) {
+                fj[ax] = fi[ax] + dl[ax];
+                if (fj[ax] < 0 || fj[ax] >= fn[ax]) jok = false;
+            }
+            if (!jok) continue;
+            double v = o.at(s, a, c, frow);
+            if (fam == 1 && l == 0 && s == (S - 1) / 2) v += fs_term(d, fpn);
+            if (l == 0) v *= mask0(d, fam, padded(fj, F.np, d->R, DIM), c);
+            if (v == 0.0) continue;
+            v *= wi;
+            int off[3][2], np[3] = {1, 1, 1};
+            for (int ax = 0; ax < DIM; ++ax) np[ax] = rap_parents(cz[ax], k[ax], dl[ax], off[ax]);
+            for (int bz = 0; bz < (DIM == 3 ? np[2] : 1); ++bz)
+                for (int by = 0; by < np[1]; ++by)
+                    for (int bx = 0; bx < np[0]; ++bx) {
+                        const int o3[3] = {off[0][bx], off[1][by], DIM == 3 ? off[2][bz] : 0};
+                        double wj = 1.0;
+                        for (int ax = 0; ax < DIM; ++ax) {
+                            const int J = I[ax] + o3[ax];
+                            if (J < 0 || J >= cn[ax]) wj = 0.0;
+                            else if (cz[ax]) wj *= pw1(fj[ax], J, fn[ax]);
+                        }
+                        if (wj == 0.0) continue;
+                        const int slot = (o3[0] + R) + SW * ((o3[1] + R) + (DIM == 3 ? SW * (o3[2] + R) : 0));
+                        acc[slot * TPB] += wj * v;
+                    }
+        }
+    }
+    // stencil slots that leave the coarse grid hold zero; an empty row gets a unit diagonal
+    T* out = (T*)(fam == 0 ? C.A : C.Sm);
+    for (int s = 0; s < S; ++s) {
+        const int off3[3] = {s % SW - R, (s / SW) % SW - R, DIM == 3 ? s / (SW * SW) - R : 0};
+        bool valid = true;
+        for (int ax = 0; ax < DIM; ++ax) {
+            const int J = I[ax] + off3[ax];
+            if (J < 0 || J >= cn[ax]) valid = false;
+        }
+        double v = valid ? acc[s * TPB] : 0.0;
+        if (s == (S - 1) / 2 && a == c && v == 0.0) v = 1.0;
+        out[((int64_t)(s * BB + a) * BB + c) * C.nrow + tid] = (T)v;
+    }
 }
 
 // Dense inverse of the coarsest operator, Gauss-Jordan with partial pivoting in FP64 in LDS,
@@ -525,15 +627,6 @@ __global__ void __launch_bounds__(256) k_mg_coarse_setup(Batch B, int fam) {
 // ---------------------------------------------------------------------------------------------
 // cycle kernels of the large levels (one thread per row, batched)
 // ---------------------------------------------------------------------------------------------
-template <int DIM, int R, int BB, typename T, bool FULL>
-__global__ void __launch_bounds__(TPB) k_mg_pre(Batch B, int fam, int l, VRef rv, VRef xv, VRef resv) {
-    PROB_PROLOGUE
-    if (krylov_done(d) || l >= d->ltail || tid >= d->lev[l].nrow) return;
-    const Lv<T> v = lv_of<BB, T>(d, fam, l);
-    row_pre<DIM, R, BB, T, FULL>(d, v, fam == 1 && l == 0, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, xv, fam, l, BB),
-                           resolve<T>(d, resv, fam, l, BB));
-}
-
 template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_smooth0(Batch B, int fam, int l, VRef rv, VRef xv) {
     PROB_PROLOGUE
@@ -687,7 +780,11 @@ __global__ void __launch_bounds__(TPB) k_mg_down(Batch B, int fam, int l, VRef r
     int o[3];
     tile_origin<DIM>(tile, v.n0, v.n1, o);
     const double om = d->omega;
-    for (int j = threadIdx.x; j < Tl::NS; j += TPB) {
+    // all slots of a thread unrolled, so that their loads are in flight together
+#pragma unroll
+    for (int jj = 0; jj < (Tl::NS + TPB - 1) / TPB; ++jj) {
+        const int j = threadIdx.x + jj * TPB;
+        if (j >= Tl::NS) break;
         int c[3];
         double bk[BB], xk[BB];
 #pragma unroll
@@ -756,7 +853,10 @@ __global__ void __launch_bounds__(TPB) k_mg_up(Batch B, int fam, int l, VRef rhs
     View<T> out = resolve<T>(d, outv, fam, l, BB);
     int o[3];
     tile_origin<DIM>(tile, v.n0, v.n1, o);
-    for (int j = threadIdx.x; j < Tl::NS; j += TPB) {
+#pragma unroll
+    for (int jj = 0; jj < (Tl::NS + TPB - 1) / TPB; ++jj) {
+        const int j = threadIdx.x + jj * TPB;
+        if (j >= Tl::NS) break;
         int c[3];
         double xk[BB];
 #pragma unroll
@@ -935,7 +1035,7 @@ static int max_ltail(const std::vector<const Dev*>& hc) {
     return L;
 }
 
-template <int DIM, typename T>
+template <int DIM, int R, typename T>
 static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, hipStream_t st) {
     const int Lmax = max_levels(hc);
     // deepest level of the Schur hierarchy over the batch (truncated hierarchies stop at ls_stop)
@@ -952,8 +1052,13 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, h
         // the coarse operator of level l is needed before its inverse diagonal
         if (l > 0) {
             Batch Bc = make_batch(g.ddev, level_rows(hc, l), TPB);
-            PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l - 1));
-            if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap<1, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
+            if constexpr (DIM == 2) {
+                PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l - 1));
+                if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap<1, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
+            } else {
+                PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap2<DIM, R, DIM, T>), dim3(Bc.pfx[Bc.n], DIM * DIM), dim3(TPB), 0, st, Bc, 0, l - 1));
+                if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap2<DIM, R, 1, T>), dim3(Bc.pfx[Bc.n], 1), dim3(TPB), 0, st, Bc, 1, l - 1);
+            }
         }
         Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
         hipLaunchKernelGGL((k_mg_dinv<DIM, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 0, l);
@@ -965,34 +1070,34 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, h
 }
 
 void launch_precond_setup(const Group& g, const std::vector<const Dev*>& hc, hipStream_t st) {
-    if (g.dim == 2) {
-        if (g.mixed) precond_setup_t<2, float>(g, hc, st);
-        else precond_setup_t<2, double>(g, hc, st);
+    if (g.dim == 2 && g.shape == 0) {
+        if (g.mixed) precond_setup_t<2, 1, float>(g, hc, st);
+        else precond_setup_t<2, 1, double>(g, hc, st);
+    } else if (g.dim == 2) {
+        if (g.mixed) precond_setup_t<2, 2, float>(g, hc, st);
+        else precond_setup_t<2, 2, double>(g, hc, st);
     } else {
-        if (g.mixed) precond_setup_t<3, float>(g, hc, st);
-        else precond_setup_t<3, double>(g, hc, st);
+        if (g.mixed) precond_setup_t<3, 1, float>(g, hc, st);
+        else precond_setup_t<3, 1, double>(g, hc, st);
     }
 }
 
-// Down-sweep of one level: pre-smoothing from a zero guess (iterate -> LX, residual -> LR) and
-// restriction of the residual to the next level's right-hand side.
+// Down-sweep of one level with nsm >= 2 sweeps (per-operation kernels): pre-smoothing from a
+// zero guess (iterate -> LX, residual -> LR) and restriction of the residual to the next level's
+// right-hand side.
 template <int DIM, int R, int BB, typename T, bool FULL>
 static void vcycle_down(const Group& g, const std::vector<const Dev*>& hc, int fam, int l, VRef rhs, int nsm,
                         hipStream_t st) {
     const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0};
     Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
     const dim3 gl(Bl.pfx[Bl.n]), tb(TPB);
-    if (nsm == 1) {
-        PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
-                  hipLaunchKernelGGL((k_mg_pre<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR));
-    } else {
-        hipLaunchKernelGGL((k_mg_smooth0<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, LX);
-        for (int k = 1; k < nsm; ++k) {
-            hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR);
-            hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, LX, LR);
-        }
+    hipLaunchKernelGGL((k_mg_smooth0<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, rhs, LX);
+    for (int k = 1; k < nsm; ++k) {
         hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR);
+        hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, LX, LR);
     }
+    PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
+              hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR));
     Batch Bc = make_batch(g.ddev, level_rows(hc, l + 1), TPB);
     hipLaunchKernelGGL((k_mg_restrict<DIM, R, BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l, LR, LB);
 }

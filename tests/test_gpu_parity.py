@@ -276,3 +276,15 @@ def test_degenerate_cases_parity(case):
     errs = _run_steps(w, w.nsteps, 0)
     for eu, ep, no, ng, kt in errs:
         assert eu < 1e-10 and ep < 1e-10, errs
+
+
+def test_step_parity_two_smoothing_sweeps():
+    """V(2,2) cycles (the per-operation multigrid kernels) reach the same states as the oracle."""
+    make, nsteps = STEP_CASES["footing2d_qs_gimp"]
+    w = make()
+    w.options.newton_rtol = 1e-10
+    w.options.krylov_rtol = 1e-12
+    print("[steps fp64, mg_smooth=2]", flush=True)
+    errs = _run_steps(w, nsteps, 0, mg_smooth=2)
+    for eu, ep, no, ng, kt in errs:
+        assert eu < 1e-10 and ep < 1e-10, errs
