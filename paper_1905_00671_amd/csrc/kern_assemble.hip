@@ -466,16 +466,12 @@ __device__ __forceinline__ void jac_bucket(const Dev* __restrict__ d, const int*
     }
 }
 
-// Block ids of the Jacobian: groups of XCDS tiles x b^2 component pairs; inside a group the b^2
-// blocks of one tile have ids that agree modulo XCDS, so with the round-robin placement of
-// workgroups on the XCDs they run on one XCD, close together in time, and read that tile's point
-// records through one L2 instead of once per component pair.
-constexpr int XCDS = 8;
-inline int64_t jacobian_blocks(int64_t ntile, int b) { return (ntile + XCDS - 1) / XCDS * XCDS * b * b; }
-
-// Jacobian, one thread per (row node, ca, cc), the component pair uniform per block.  The node's
-// block row over the fixed stencil is accumulated in registers and written once, with the rows
-// and columns of constrained dofs replaced by identity rows.
+// Jacobian, one thread per (row node, ca, cc).  The b^2 component pairs of a node are adjacent
+// lanes of one wavefront (64 / b^2 nodes per wavefront, consecutive in x), so that all lanes of a
+// node read the same point record at the same time and a wavefront's record loads touch a few
+// cache lines instead of one per lane.  The node's block row over the fixed stencil is
+// accumulated in registers and written once, with the rows and columns of constrained dofs
+// replaced by identity rows.
 template <int DIM, int SHAPE, typename T>
 __global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
     const int q = batch_find(B, blockIdx.x);
@@ -486,13 +482,19 @@ __global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
     constexpr int S = DIM == 2 ? SW * SW : SW * SW * SW;
     constexpr int BS = DIM + 1;
     constexpr int NP = BS * BS;
-    const int64_t grp = lb / (XCDS * NP), rem = lb % (XCDS * NP);
-    const int64_t tile = grp * XCDS + rem % XCDS;
-    const int pair = (int)(rem / XCDS);
+    constexpr int NPW = 64 / NP;                 // nodes per wavefront
+    constexpr int NODES = (TPB / 64) * NPW;      // nodes per block (an x-run)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane >= NP * NPW) return;
+    const int pair = lane % NP;
     const int ca = pair / BS, cc = pair % BS;
+    const int ntx = (d->nn[0] + NODES - 1) / NODES;
     int n[3];
-    int64_t row;
-    if (!tile_node<DIM>(d, tile, threadIdx.x, n, &row)) return;
+    n[0] = (int)(lb % ntx) * NODES + wave * NPW + lane / NP;
+    n[1] = (int)((lb / ntx) % d->nn[1]);
+    n[2] = DIM == 3 ? (int)(lb / ((int64_t)ntx * d->nn[1])) : 0;
+    if (n[0] >= d->nn[0]) return;
+    const int64_t row = n[0] + (int64_t)d->nn[0] * (n[1] + (int64_t)d->nn[1] * n[2]);
     double acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0;
@@ -567,9 +569,7 @@ void launch_assemble(const Group& g, bool want_J, hipStream_t st) {
 }
 
 void launch_jacobian(const Group& g, hipStream_t st) {
-    std::vector<int64_t> nb;
-    for (auto t : g.ntile) nb.push_back(jacobian_blocks(t, g.b));
-    Batch Bn = make_batch_blocks(g.ddev, nb);
+    Batch Bn = make_batch_blocks(g.ddev, g.jblk);
     const dim3 gr(Bn.pfx[Bn.n]), tb(TPB);
     if (g.dim == 2 && g.shape == 0) {
         if (g.mixed) PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 0, float>), gr, tb, 0, st, Bn));

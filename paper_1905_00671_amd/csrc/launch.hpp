@@ -15,7 +15,7 @@ namespace ppm {
 struct Group {
     int dim = 2, shape = 0, mixed = 0, S = 9, b = 3;
     std::vector<const Dev*> ddev;   // device descriptors
-    std::vector<int64_t> np, nnode, ncell, ncell1, npadb, npad, ntile;
+    std::vector<int64_t> np, nnode, ncell, ncell1, npadb, npad, ntile, jblk;
 };
 
 // Per-kernel timing with HIP events recorded on the launching stream (off unless enabled).
@@ -67,6 +67,13 @@ inline Batch make_batch_blocks(const std::vector<const Dev*>& dd, const std::vec
 inline int64_t node_tiles(int dim, const int* nn) {
     if (dim == 2) return (int64_t)((nn[0] + TILE2X - 1) / TILE2X) * ((nn[1] + TILE2Y - 1) / TILE2Y);
     return (int64_t)((nn[0] + TILE3X - 1) / TILE3X) * ((nn[1] + TILE3Y - 1) / TILE3Y) * ((nn[2] + TILE3Z - 1) / TILE3Z);
+}
+
+// Blocks of the Jacobian kernel: x-runs of (TPB / 64) * (64 / b^2) nodes, one per (y, z) row.
+inline int64_t jacobian_blocks(int dim, const int* nn) {
+    const int b = dim + 1, nodes = (TPB / 64) * (64 / (b * b));
+    const int64_t runs = (nn[0] + nodes - 1) / nodes;
+    return runs * nn[1] * (dim == 3 ? nn[2] : 1);
 }
 
 // Tiles of the multigrid sweeps covering a level of n nodes per axis.

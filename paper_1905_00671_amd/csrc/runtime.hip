@@ -339,6 +339,7 @@ Group make_group(const std::vector<ppmpm_problem*>& ps) {
         g.npad.push_back(p->h.Npad);
         g.npadb.push_back(p->h.Npad * p->h.b);
         g.ntile.push_back(node_tiles(p->h.dim, p->h.nn));
+        g.jblk.push_back(jacobian_blocks(p->h.dim, p->h.nn));
     }
     return g;
 }
