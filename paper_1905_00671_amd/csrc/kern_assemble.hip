@@ -502,7 +502,6 @@ __global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
     const int64_t pni = pad_index(d, n[0], n[1], n[2]);
     const bool fr = d->dfree[pni * BS + ca] != 0;
     T* J = (T*)d->J;
-    const int64_t Nn = d->Nnode;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int off[3] = {s % SW - RR, (s / SW) % SW - RR, DIM == 3 ? s / (SW * SW) - RR : 0};
@@ -519,7 +518,7 @@ __global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
             const bool fc = d->dfree[pnk * BS + cc] != 0;
             if (!(fr && fc)) v = (s == (S - 1) / 2 && ca == cc) ? 1.0 : 0.0;
         }
-        J[((int64_t)(s * BS + ca) * BS + cc) * Nn + row] = (T)v;
+        J[jidx<DIM>((s * BS + ca) * BS + cc, row, S * BS * BS, d->Nnode)] = (T)v;
     }
 }
 

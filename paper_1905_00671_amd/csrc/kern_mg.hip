@@ -57,11 +57,14 @@ template <typename T>
 struct Lv {
     int n0, n1, n2, np0, np1;
     int64_t nrow;
-    const T* op;   // operator storage (level 0: the Jacobian)
+    const T* op;   // operator storage (level 0: the Jacobian, row-blocked)
     int BJ, a0;    // block size of the storage, first row/column of the family inside it
+    int sh;        // index = (row >> sh) * bstride + e * estride + (row & mask)
+    int64_t mask, estride, bstride;
     const T* Di;   // inverse diagonal blocks
     __device__ __forceinline__ double opv(int s, int a, int c, int64_t row) const {
-        return (double)op[((int64_t)(s * BJ + a + a0) * BJ + c + a0) * nrow + row];
+        const int64_t e = (int64_t)(s * BJ + a + a0) * BJ + c + a0;
+        return (double)op[(row >> sh) * bstride + e * estride + (row & mask)];
     }
 };
 
@@ -79,10 +82,19 @@ __device__ __forceinline__ Lv<T> lv_of(const Dev* d, int fam, int l) {
         v.op = (const T*)d->J;
         v.BJ = d->b;
         v.a0 = fam == 0 ? 0 : d->dim;
+        const bool blk = d->dim == 3;   // layout of jidx
+        v.sh = blk ? 6 : 62;
+        v.mask = blk ? (int64_t)(JB - 1) : ~(int64_t)0;
+        v.estride = blk ? (int64_t)JB : d->Nnode;
+        v.bstride = blk ? (int64_t)d->S * d->b * d->b * JB : 0;
     } else {
         v.op = (const T*)(fam == 0 ? L.A : L.Sm);
         v.BJ = BB;
         v.a0 = 0;
+        v.sh = 62;
+        v.mask = ~(int64_t)0;
+        v.estride = L.nrow;
+        v.bstride = 0;
     }
     v.Di = (const T*)(fam == 0 ? L.Ad : L.Sd);
     return v;
@@ -1000,7 +1012,6 @@ __global__ void __launch_bounds__(TPB) k_b1(Batch B, VRef yv, VRef zv) {
     const int64_t pn = padded(c, d->np1, R, DIM);
     const int np0 = d->np1[0], np1 = d->np1[1];
     const T* J = (const T*)d->J;
-    const int64_t Nn = d->Nnode;
     double acc[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) acc[a] = (double)y.at(pn, a);
@@ -1009,7 +1020,7 @@ __global__ void __launch_bounds__(TPB) k_b1(Batch B, VRef yv, VRef zv) {
         const int64_t pk = pn + St::ox(s) + (int64_t)np0 * (St::oy(s) + (int64_t)np1 * St::oz(s));
         const double zp = (double)z.at(pk, 0);
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) acc[a] -= (double)J[((int64_t)(s * bs + a) * bs + DIM) * Nn + tid] * zp;
+        for (int a = 0; a < DIM; ++a) acc[a] -= (double)J[jidx<DIM>((s * bs + a) * bs + DIM, tid, St::S * bs * bs, d->Nnode)] * zp;
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) t.at(pn, a) = (T)acc[a];

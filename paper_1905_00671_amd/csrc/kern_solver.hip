@@ -33,7 +33,6 @@ __global__ void __launch_bounds__(TPB) k_spmv(Batch B, int ix, int iy, int ia, i
         const T* __restrict__ x = vp<T>(vecs[ix]);
         T* __restrict__ y = vp<T>(vecs[iy]);
         const T* __restrict__ J = vp<T>(d->J);
-        const int64_t Nn = d->Nnode;
         int c[3];
         real_coords(tid, d->nn, DIM, c);
         const int64_t pn = padded(c, d->np1, R, DIM);
@@ -49,7 +48,7 @@ __global__ void __launch_bounds__(TPB) k_spmv(Batch B, int ix, int iy, int ia, i
             for (int a = 0; a < BS; ++a) {
                 T t = 0;
 #pragma unroll
-                for (int cc = 0; cc < BS; ++cc) t += J[((int64_t)(s * BS + a) * BS + cc) * Nn + tid] * xv[cc];
+                for (int cc = 0; cc < BS; ++cc) t += J[jidx<DIM>((s * BS + a) * BS + cc, tid, S * BS * BS, d->Nnode)] * xv[cc];
                 acc[a] += (double)t;
             }
         }

@@ -126,7 +126,8 @@ struct Dev {
     double* cellpi;   // [Ncell * 2^dim] original-MPM projection Pi N
     // quadrature-point records
     double* rec;      // [Np][NREC] (one record per point)
-    // Jacobian, fixed stencil block rows: J[((s*b + a)*b + c)*Nnode + row], precision T
+    // Jacobian, fixed stencil block rows: entry e = (s*b + a)*b + c of row r at
+    // J[jidx<dim>(e, r, S*b*b, Nnode)], precision T (see jidx)
     void* J;
     // Krylov vectors [Npad*b], precision T
     void* kx; void* kr; void* kh; void* kp; void* kv; void* ks; void* kt; void* kph; void* ksh;
@@ -142,6 +143,19 @@ struct Dev {
     int* flags;       // [NFLAG]
     int64_t maxblocks;
 };
+
+// Jacobian storage.  3D: rows in blocks of JB, entry-major inside a block, so that a wavefront's
+// whole block row (432 words per row) is one contiguous run.  2D: entry-major over all rows,
+// J[e * Nnode + row] (the 2D Jacobian is small enough to stay largely in the 256 MB Infinity
+// Cache, and this order measured faster there).  Both give 64 consecutive words per entry for a
+// wavefront of 64 consecutive rows.
+constexpr int JB = 64;
+template <int DIM>
+__host__ __device__ __forceinline__ int64_t jidx(int e, int64_t row, int NE, int64_t nrow) {
+    if (DIM == 3) return (row >> 6) * ((int64_t)NE << 6) + ((int64_t)e << 6) + (row & 63);
+    return (int64_t)e * nrow + row;
+}
+__host__ __device__ __forceinline__ int64_t jrows_padded(int64_t nrow) { return (nrow + JB - 1) / JB * JB; }
 
 // Batch of problems of one kernel variant, passed by value to every kernel.
 struct Batch {

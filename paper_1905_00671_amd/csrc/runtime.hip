@@ -232,7 +232,7 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
     h.Rv = c.take<double>(P * bs);
     h.cellpi = c.take<double>(h.Ncell * (1 << D));
     h.rec = c.take<double>((size_t)nrec * np);
-    h.J = c.take<char>((size_t)h.S * bs * bs * h.Nnode * TS);
+    h.J = c.take<char>((size_t)h.S * bs * bs * jrows_padded(h.Nnode) * TS);
     void** kv[9] = {&h.kx, &h.kr, &h.kh, &h.kp, &h.kv, &h.ks, &h.kt, &h.kph, &h.ksh};
     for (auto* p : kv) *p = c.take<char>((size_t)P * bs * TS);
     h.kbt = c.take<char>((size_t)P * D * TS);

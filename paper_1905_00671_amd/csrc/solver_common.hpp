@@ -47,15 +47,20 @@ __device__ __forceinline__ void block_partials(const Dev* d, int64_t lb, const d
 __device__ __forceinline__ bool krylov_done(const Dev* d) { return d->scal[SC_DONE] != 0.0; }
 
 // Operator entry (row, stencil s, a, c) of family fam (0: A, block dim; 1: S, block 1) on level l.
-// Level 0 reads the Jacobian's stored blocks; coarser levels their Galerkin operators.
+// Level 0 reads the Jacobian's stored blocks (row-blocked layout, see jidx); coarser levels their
+// Galerkin operators [S][B][B][nrow].  One index formula covers both:
+//   (row >> sh) * bstride + e * estride + (row & mask).
 template <typename T>
 struct Op {
     const T* base;
     int64_t nrow;
     int BJ;   // block size of the storage
     int a0;   // first storage row/col of the family
+    int sh;
+    int64_t mask, estride, bstride;
     __device__ __forceinline__ double at(int s, int a, int c, int64_t row) const {
-        return (double)base[((int64_t)(s * BJ + a + a0) * BJ + c + a0) * nrow + row];
+        const int64_t e = (int64_t)(s * BJ + a + a0) * BJ + c + a0;
+        return (double)base[(row >> sh) * bstride + e * estride + (row & mask)];
     }
 };
 
@@ -67,11 +72,20 @@ __device__ __forceinline__ Op<T> op_of(const Dev* d, int fam, int l) {
         o.nrow = d->Nnode;
         o.BJ = d->b;
         o.a0 = fam == 0 ? 0 : d->dim;
+        const bool blk = d->dim == 3;   // layout of jidx
+        o.sh = blk ? 6 : 62;
+        o.mask = blk ? (int64_t)(JB - 1) : ~(int64_t)0;
+        o.estride = blk ? (int64_t)JB : d->Nnode;
+        o.bstride = blk ? (int64_t)d->S * d->b * d->b * JB : 0;
     } else {
         o.base = (const T*)(fam == 0 ? d->lev[l].A : d->lev[l].Sm);
         o.nrow = d->lev[l].nrow;
         o.BJ = fam == 0 ? d->dim : 1;
         o.a0 = 0;
+        o.sh = 62;
+        o.mask = ~(int64_t)0;
+        o.estride = o.nrow;
+        o.bstride = 0;
     }
     return o;
 }
