@@ -1047,7 +1047,15 @@ static int max_ltail(const std::vector<const Dev*>& hc) {
 }
 
 template <int DIM, int R, typename T>
-static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, hipStream_t st) {
+static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, bool coarse, hipStream_t st) {
+    if (!coarse) {
+        // later Newton iterations of a step: the fine level follows the new Jacobian (its operator
+        // is a view of J, its inverse diagonal is rebuilt here); the coarse levels are kept
+        Batch Bl = make_batch(g.ddev, level_rows(hc, 0), TPB);
+        hipLaunchKernelGGL((k_mg_dinv<DIM, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 0, 0);
+        hipLaunchKernelGGL((k_mg_dinv<1, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 1, 0);
+        return;
+    }
     const int Lmax = max_levels(hc);
     // deepest level of the Schur hierarchy over the batch (truncated hierarchies stop at ls_stop)
     int LmaxS = 0;
@@ -1080,16 +1088,16 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, h
     if (full_s) hipLaunchKernelGGL((k_mg_coarse_setup<1, T>), dim3(B1.n), dim3(256), 0, st, B1, 1);
 }
 
-void launch_precond_setup(const Group& g, const std::vector<const Dev*>& hc, hipStream_t st) {
+void launch_precond_setup(const Group& g, const std::vector<const Dev*>& hc, bool coarse, hipStream_t st) {
     if (g.dim == 2 && g.shape == 0) {
-        if (g.mixed) precond_setup_t<2, 1, float>(g, hc, st);
-        else precond_setup_t<2, 1, double>(g, hc, st);
+        if (g.mixed) precond_setup_t<2, 1, float>(g, hc, coarse, st);
+        else precond_setup_t<2, 1, double>(g, hc, coarse, st);
     } else if (g.dim == 2) {
-        if (g.mixed) precond_setup_t<2, 2, float>(g, hc, st);
-        else precond_setup_t<2, 2, double>(g, hc, st);
+        if (g.mixed) precond_setup_t<2, 2, float>(g, hc, coarse, st);
+        else precond_setup_t<2, 2, double>(g, hc, coarse, st);
     } else {
-        if (g.mixed) precond_setup_t<3, 1, float>(g, hc, st);
-        else precond_setup_t<3, 1, double>(g, hc, st);
+        if (g.mixed) precond_setup_t<3, 1, float>(g, hc, coarse, st);
+        else precond_setup_t<3, 1, double>(g, hc, coarse, st);
     }
 }
 

@@ -106,7 +106,9 @@ void launch_assemble(const Group& g, bool want_J, hipStream_t st);
 
 // kern_assemble.hip
 void launch_jacobian(const Group& g, hipStream_t st);
-void launch_precond_setup(const Group& g, const std::vector<const Dev*>& host_copies, hipStream_t st);
+// coarse: rebuild the Galerkin hierarchy (first Newton iteration of a step); otherwise only the
+// fine-level inverse diagonals follow the new Jacobian
+void launch_precond_setup(const Group& g, const std::vector<const Dev*>& host_copies, bool coarse, hipStream_t st);
 void launch_precond_apply(const Group& g, const std::vector<const Dev*>& host_copies, int iy, int iz, hipStream_t st);
 void launch_krylov_init(const Group& g, double rtol, int maxit, hipStream_t st);
 void launch_krylov_iters(const Group& g, const std::vector<const Dev*>& host_copies, int iters, double rtol,

@@ -640,7 +640,7 @@ ppmpm_status ppmpm_step_batched(ppmpm_problem* const* probs, int nprob, const do
             auto hcs = host_copies(cont);
             auto t3 = clk::now();
             launch_jacobian(gc, st);
-            launch_precond_setup(gc, hcs, st);
+            launch_precond_setup(gc, hcs, it == 0, st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(st));
             auto t4 = clk::now();
