@@ -11,7 +11,7 @@ constexpr int MAXB = 64;      // problems per batched launch
 constexpr int TPB = 256;      // threads per block of the streaming kernels
 constexpr int MAXLEV = 12;    // multigrid levels
 constexpr int CMAX = 81;      // largest coarsest-level system solved by a dense inverse (LDS)
-constexpr int TAILMAX = 160;  // levels with at most this many nodes run inside one fused kernel
+constexpr int TAILMAX = 200;  // levels with at most this many nodes run inside one fused kernel
 // node tiles of the gather kernels (one block of TPB threads per tile)
 constexpr int TILE2X = 16, TILE2Y = 16;
 constexpr int TILE3X = 8, TILE3Y = 8, TILE3Z = 4;
