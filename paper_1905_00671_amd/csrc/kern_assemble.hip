@@ -3,7 +3,7 @@
 // Two passes per Newton iteration:
 //   k_records   one thread per (sorted) material point: basis at x_n, relative deformation
 //               dF = 1 + sum U (x) grad_n S, stress, tangent and every per-point coefficient the
-//               residual and the Jacobian need (one contiguous "quadrature record" per point);
+//               residual and the Jacobian need (the point's "quadrature record", see RecRef);
 //   k_residual  one thread per grid node (blocks cover 16x16 / 8x8x4 node tiles): gathers R_i
 //               from the points whose basis reaches node i (no atomics, fixed summation order),
 //               applies the boundary conditions and writes per-block partial norms;
@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     const double* P = d->pw;
     const int64_t s = d->ps;
     const int64_t i = tid;
-    double* rec = d->rec + i * L::N;
+    const RecRef rec(d->rec, i, L::N);
     double w[DIM][3], dw[DIM][3], s0v[DIM][3];
     int base[3] = {0, 0, 0};
     for (int a = 0; a < DIM; ++a) {
@@ -62,36 +62,27 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     }
     const double dt = d->dt, be = d->beta, ga = d->gamma;
     const bool dyn = d->dyn;
-    double G[NN][DIM], Sv[NN], Pi[NN], U[NN][DIM], Pk[NN], acc[NN][DIM], vel[NN][DIM], pdot[NN];
+    // pass 1: relative deformation dF = 1 + sum_k U_k (x) grad_n S_k
     double dF[DIM * DIM];
+#pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) dF[k] = (k % (DIM + 1) == 0) ? 1.0 : 0.0;
+#pragma unroll
     for (int k = 0; k < NN; ++k) {
-        int li[3] = {k % WB, (k / WB) % WB, DIM == 3 ? k / (WB * WB) : 0};
-        double sv = 1.0, s0p = 1.0;
+        const int li[3] = {k % WB, (k / WB) % WB, DIM == 3 ? k / (WB * WB) : 0};
+        double G[DIM];
+#pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            sv *= w[a][li[a]];
-            s0p *= s0v[a][li[a]];
             double gr = 1.0;
+#pragma unroll
             for (int c = 0; c < DIM; ++c) gr *= (c == a) ? dw[c][li[c]] : w[c][li[c]];
-            G[k][a] = gr;
+            G[a] = gr;
         }
-        Sv[k] = sv;
-        Pi[k] = SHAPE ? s0p : d->cellpi[cid * (1 << DIM) + k];
-        int64_t pn = pad_index(d, base[0] + li[0], base[1] + li[1], DIM == 3 ? base[2] + li[2] : 0);
-        const double* Xn = d->X + pn * bs;
-        for (int a = 0; a < DIM; ++a) U[k][a] = Xn[a];
-        Pk[k] = Xn[DIM];
-        for (int a = 0; a < DIM; ++a)
-            for (int c = 0; c < DIM; ++c) dF[a * DIM + c] += U[k][a] * G[k][c];
-        double dP = Pk[k] - d->Pn[pn];
-        pdot[k] = d->ct * dP;
-        if (dyn) {
-            pdot[k] += d->hc1 * d->pdn[pn] + d->hc2 * d->pddn[pn];
-            for (int a = 0; a < DIM; ++a) {
-                double v0 = d->vn[pn * 3 + a], a0 = d->an[pn * 3 + a];
-                acc[k][a] = U[k][a] / (be * dt * dt) - v0 / (be * dt) + (1.0 - 0.5 / be) * a0;
-                vel[k][a] = ga / (be * dt) * U[k][a] + (1.0 - ga / be) * v0 + (1.0 - 0.5 * ga / be) * dt * a0;
-            }
+        const int64_t pn = pad_index(d, base[0] + li[0], base[1] + li[1], DIM == 3 ? base[2] + li[2] : 0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const double u = d->X[pn * bs + a];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) dF[a * DIM + c] += u * G[c];
         }
     }
     double dJ = det<DIM>(dF);
@@ -100,40 +91,72 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
         dJ = 1.0;
         for (int k = 0; k < DIM * DIM; ++k) dF[k] = (k % (DIM + 1) == 0) ? 1.0 : 0.0;
     }
-    double f[DIM * DIM], Fn[DIM * DIM], F[DIM * DIM];
+    double f[DIM * DIM], F[DIM * DIM], detFn;
     inverse<DIM>(dF, f);
-    for (int k = 0; k < DIM * DIM; ++k) Fn[k] = P[(PF + k) * s + i];
-    for (int a = 0; a < DIM; ++a)
-        for (int c = 0; c < DIM; ++c) {
-            double t = 0.0;
-            for (int k = 0; k < DIM; ++k) t += dF[a * DIM + k] * Fn[k * DIM + c];
-            F[a * DIM + c] = t;
-        }
-    double tau[DIM * DIM], tzz, T[DIM * DIM * DIM * DIM];
-    kirchhoff_tangent<DIM>(d->model, d->lam, d->G, F, tau, &tzz, T);
+    {
+        double Fn[DIM * DIM];
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) Fn[k] = P[(PF + k) * s + i];
+        detFn = det<DIM>(Fn);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) t += dF[a * DIM + k] * Fn[k * DIM + c];
+                F[a * DIM + c] = t;
+            }
+    }
     const double Vn = P[PV * s + i], m = P[PM * s + i];
-    const double V0 = Vn / det<DIM>(Fn);
+    const double V0 = Vn / detFn;
     const double dv = dJ * Vn;
-    double gS[NN][DIM];
-    double ph = 0.0, gp[DIM], ah[DIM], l[DIM * DIM];
+    // pass 2: pressure, its gradient, the stabilization term and (Newmark) a^h, grad v
+    double ph = 0.0, gp[DIM], ah[DIM], l[DIM * DIM], pst = 0.0;
+#pragma unroll
     for (int a = 0; a < DIM; ++a) gp[a] = ah[a] = 0.0;
+#pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) l[k] = 0.0;
-    double pst = 0.0;
+#pragma unroll
     for (int k = 0; k < NN; ++k) {
+        const int li[3] = {k % WB, (k / WB) % WB, DIM == 3 ? k / (WB * WB) : 0};
+        double sv = 1.0, s0p = 1.0, G[DIM], gS[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            sv *= w[a][li[a]];
+            s0p *= s0v[a][li[a]];
+            double gr = 1.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) gr *= (c == a) ? dw[c][li[c]] : w[c][li[c]];
+            G[a] = gr;
+        }
+#pragma unroll
         for (int a = 0; a < DIM; ++a) {
             double t = 0.0;
-            for (int c = 0; c < DIM; ++c) t += f[c * DIM + a] * G[k][c];
-            gS[k][a] = t;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) t += f[c * DIM + a] * G[c];
+            gS[a] = t;
         }
-        ph += Sv[k] * Pk[k];
-        for (int a = 0; a < DIM; ++a) gp[a] += Pk[k] * gS[k][a];
-        pst += (Sv[k] - Pi[k]) * pdot[k];
+        const double Pi = SHAPE ? s0p : d->cellpi[cid * (1 << DIM) + k];
+        const int64_t pn = pad_index(d, base[0] + li[0], base[1] + li[1], DIM == 3 ? base[2] + li[2] : 0);
+        const double Pk = d->X[pn * bs + DIM];
+        double pdot = d->ct * (Pk - d->Pn[pn]);
+        ph += sv * Pk;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) gp[a] += Pk * gS[a];
         if (dyn) {
+            pdot += d->hc1 * d->pdn[pn] + d->hc2 * d->pddn[pn];
+#pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                ah[a] += Sv[k] * acc[k][a];
-                for (int c = 0; c < DIM; ++c) l[a * DIM + c] += vel[k][a] * gS[k][c];
+                const double u = d->X[pn * bs + a], v0 = d->vn[pn * 3 + a], a0 = d->an[pn * 3 + a];
+                const double acc = u / (be * dt * dt) - v0 / (be * dt) + (1.0 - 0.5 / be) * a0;
+                const double vel = ga / (be * dt) * u + (1.0 - ga / be) * v0 + (1.0 - 0.5 * ga / be) * dt * a0;
+                ah[a] += sv * acc;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) l[a * DIM + c] += vel * gS[c];
             }
         }
+        pst += (sv - Pi) * pdot;
     }
     double theta;
     if (dyn) {
@@ -144,17 +167,45 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     }
     double wv[DIM];
     for (int a = 0; a < DIM; ++a) wv[a] = gp[a] - d->rho_f * (d->g[a] - ah[a]);
-    // tangent with the geometric term and the pressure term folded in
-    for (int a = 0; a < DIM; ++a)
-        for (int bb = 0; bb < DIM; ++bb)
-            for (int c = 0; c < DIM; ++c)
-                for (int e = 0; e < DIM; ++e) {
-                    double v = -V0 * T[((a * DIM + bb) * DIM + c) * DIM + e];
-                    if (bb == c) v += V0 * tau[a * DIM + e];
-                    if (a == bb && c == e) v += dv * ph;
-                    if (a == e && bb == c) v -= dv * ph;
-                    rec[L::AB_ + ((a * DIM + bb) * DIM + c) * DIM + e] = v;
-                }
+    // Kirchhoff stress and the tangent with the geometric and pressure terms folded in
+    double tau[DIM * DIM], tzz;
+    if constexpr (DIM == 2) {
+        double T[16];
+        kirchhoff_tangent<2>(d->model, d->lam, d->G, F, tau, &tzz, T);
+        for (int a = 0; a < DIM; ++a)
+            for (int bb = 0; bb < DIM; ++bb)
+                for (int c = 0; c < DIM; ++c)
+                    for (int e = 0; e < DIM; ++e) {
+                        double v = -V0 * T[((a * DIM + bb) * DIM + c) * DIM + e];
+                        if (bb == c) v += V0 * tau[a * DIM + e];
+                        if (a == bb && c == e) v += dv * ph;
+                        if (a == e && bb == c) v -= dv * ph;
+                        rec[L::AB_ + ((a * DIM + bb) * DIM + c) * DIM + e] = v;
+                    }
+    } else {
+        // neo-Hookean (the 3D model): T_{ab,ce} = G (d_ac b_eb + b_ae d_bc) + lambda d_ab d_ce
+        kirchhoff_tangent<3>(d->model, d->lam, d->G, F, tau, &tzz, nullptr);
+        double bm[9];
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) {
+                double t = 0.0;
+                for (int k = 0; k < 3; ++k) t += F[a * 3 + k] * F[c * 3 + k];
+                bm[a * 3 + c] = t;
+            }
+        const double Gm = d->G, lam = d->lam;
+        for (int a = 0; a < 3; ++a)
+            for (int bb = 0; bb < 3; ++bb)
+                for (int c = 0; c < 3; ++c)
+                    for (int e = 0; e < 3; ++e) {
+                        double Tv = (a == c ? Gm * bm[e * 3 + bb] : 0.0) + (bb == c ? Gm * bm[a * 3 + e] : 0.0) +
+                                    (a == bb && c == e ? lam : 0.0);
+                        double v = -V0 * Tv;
+                        if (bb == c) v += V0 * tau[a * 3 + e];
+                        if (a == bb && c == e) v += dv * ph;
+                        if (a == e && bb == c) v -= dv * ph;
+                        rec[L::AB_ + ((a * 3 + bb) * 3 + c) * 3 + e] = v;
+                    }
+    }
     for (int k = 0; k < DIM * DIM; ++k) {
         rec[L::FI_ + k] = f[k];
         rec[L::LV_ + k] = dyn ? dv * l[k] : 0.0;
@@ -220,7 +271,7 @@ __device__ __forceinline__ void res_bucket(const Dev* __restrict__ d, const int*
         // original MPM: Pi S_n of the cell, the same for every point of the bucket
         const double pic = (SHAPE || p1 <= p0) ? 0.0 : d->cellpi[cid * NN + LI];
         for (int p = p0; p < p1; ++p) {
-            const double* __restrict__ rc = d->rec + (int64_t)p * L::N;
+            const RecRef rc(d->rec, p, L::N);
             double w[DIM], dw[DIM], Sv = 1.0, s0 = 1.0;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -316,7 +367,7 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
 // each written as u . gk + alpha S_k - gamma Pi_k = (f u) . grad_n S_k + alpha S_k - gamma Pi_k.
 // pic: the cell's Pi S_k (original MPM, PPP class only).
 template <int DIM, int SHAPE, int LI>
-__device__ __forceinline__ void jac_point(const double* __restrict__ rc, const double* pic, int ca, int cc,
+__device__ __forceinline__ void jac_point(const RecRef rc, const double* pic, int ca, int cc,
                                           double* acc) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int RR = SHAPE ? 2 : 1;
@@ -460,7 +511,7 @@ __device__ __forceinline__ void jac_bucket(const Dev* __restrict__ d, const int*
 #pragma unroll
                 for (int k = 0; k < NN; ++k) pic[k] = d->cellpi[cid * NN + k];
             }
-            for (int p = p0; p < p1; ++p) jac_point<DIM, SHAPE, LI>(d->rec + (int64_t)p * L::N, pic, ca, cc, acc);
+            for (int p = p0; p < p1; ++p) jac_point<DIM, SHAPE, LI>(RecRef(d->rec, p, L::N), pic, ca, cc, acc);
         }
         jac_bucket<DIM, SHAPE, LI + 1>(d, n, ca, cc, acc);
     }

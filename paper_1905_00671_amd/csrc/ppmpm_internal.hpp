@@ -125,7 +125,7 @@ struct Dev {
     double* Rv;       // [Npad*b] residual
     double* cellpi;   // [Ncell * 2^dim] original-MPM projection Pi N
     // quadrature-point records
-    double* rec;      // [Np][NREC] (one record per point)
+    double* rec;      // point records, NREC contiguous words per point (RecRef)
     // Jacobian, fixed stencil block rows: entry e = (s*b + a)*b + c of row r at
     // J[jidx<dim>(e, r, S*b*b, Nnode)], precision T (see jidx)
     void* J;
@@ -196,6 +196,15 @@ struct RecLayout {
     static constexpr int ST_ = DT_ + 1;                // tau V_n (pdot - Pi pdot)
     static constexpr int N = ST_ + 1;
 };
+
+// Record of point p: NREC contiguous words (the gathers read ~30 fields of one point per visit,
+// which then share a few cache lines).  rec[f] is field f of the point.
+struct RecRef {
+    double* b;
+    __device__ __forceinline__ RecRef(double* base, int64_t p, int nrec) : b(base + p * nrec) {}
+    __device__ __forceinline__ double& operator[](int f) const { return b[f]; }
+};
+__host__ __device__ __forceinline__ int64_t rec_points_padded(int64_t np) { return np; }
 
 // ------------------------------------------------------------------------------------------------
 // basis functions (Sec. 3.1)

@@ -231,7 +231,7 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
     h.X = c.take<double>(P * bs);
     h.Rv = c.take<double>(P * bs);
     h.cellpi = c.take<double>(h.Ncell * (1 << D));
-    h.rec = c.take<double>((size_t)nrec * np);
+    h.rec = c.take<double>((size_t)nrec * rec_points_padded(np));
     h.J = c.take<char>((size_t)h.S * bs * bs * jrows_padded(h.Nnode) * TS);
     void** kv[9] = {&h.kx, &h.kr, &h.kh, &h.kp, &h.kv, &h.ks, &h.kt, &h.kph, &h.ksh};
     for (auto* p : kv) *p = c.take<char>((size_t)P * bs * TS);
