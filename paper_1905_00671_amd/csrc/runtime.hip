@@ -288,13 +288,14 @@ double stab_tau(const ppmpm_options* o, double lam, double G, double kappa, doub
 
 // Depth of the Schur-block (S) multigrid.  S is a pressure mass term (c_t/K) M_p plus a Darcy
 // diffusion term; on level l their ratio is the diffusion number Fo_l = kappa K / (c_t h_l^2)
-// (h_l the smallest node spacing of the level).  Below the first level l >= 1 with Fo_l < 1/4
-// the operator is close to a scaled mass matrix, which two damped Jacobi sweeps invert well
-// enough, so the S cycle ends there (V(1,1) only; ltail or more means the full hierarchy).
+// (h_l the smallest node spacing of the level).  From the first level with Fo_l < 1/4 on, the
+// operator is close to a scaled mass matrix, which two damped Jacobi sweeps invert well enough,
+// so the S cycle ends there (level 0: no coarse levels at all; V(1,1) only; ltail or more means
+// the full hierarchy).
 int schur_truncation(const Dev& h) {
     if (h.mg_nsm != 1) return MAXLEV;
     const double kK = h.kappa * h.Kfs / h.ct;
-    for (int l = 1; l < h.ltail; ++l) {
+    for (int l = 0; l < h.ltail; ++l) {
         double hmin = 1e300;
         for (int a = 0; a < h.dim; ++a) {
             const double sp = h.h * (double)(h.nn[a] - 1) / (double)(h.lev[l].n[a] - 1);
