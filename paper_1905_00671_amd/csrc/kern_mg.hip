@@ -272,15 +272,15 @@ __device__ __forceinline__ void restrict_node(const Dev* d, int fam, int l, cons
             w = ok ? w * pwa(fi[a], I[a], fn[a], fz[a]) : 0.0;
             fi[a] = ok ? fi[a] : 0;
         }
-        if (w != 0.0) {
-            int64_t fpn = (int64_t)(fi[1] + R);
-            if (DIM == 3) fpn += (int64_t)fp1 * (fi[2] + R);
-            fpn = (fi[0] + R) + (int64_t)fp0 * fpn;
+        // no branch around the loads: a candidate off the grid was moved onto node 0 with a zero
+        // weight, so all loads of the node are issued together instead of one round trip each
+        int64_t fpn = (int64_t)(fi[1] + R);
+        if (DIM == 3) fpn += (int64_t)fp1 * (fi[2] + R);
+        fpn = (fi[0] + R) + (int64_t)fp0 * fpn;
 #pragma unroll
-            for (int a = 0; a < BB; ++a) {
-                const double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
-                acc[a] += w * m * (double)r.at(fpn, a);
-            }
+        for (int a = 0; a < BB; ++a) {
+            const double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
+            acc[a] += w * m * (double)r.at(fpn, a);
         }
     }
 }
@@ -327,13 +327,12 @@ __device__ __forceinline__ void prolong_node(const Dev* d, int fam, int l, const
                 I[a] = fi[a];
             }
         }
-        if (w != 0.0) {
-            int64_t cpn = (int64_t)(I[1] + R);
-            if (DIM == 3) cpn += (int64_t)cp1 * (I[2] + R);
-            cpn = (I[0] + R) + (int64_t)cp0 * cpn;
+        // unconditional loads (see restrict_node); I[] is a valid coarse node when w is zero
+        int64_t cpn = (int64_t)(I[1] + R);
+        if (DIM == 3) cpn += (int64_t)cp1 * (I[2] + R);
+        cpn = (I[0] + R) + (int64_t)cp0 * cpn;
 #pragma unroll
-            for (int a = 0; a < BB; ++a) acc[a] += w * (double)xc.at(cpn, a);
-        }
+        for (int a = 0; a < BB; ++a) acc[a] += w * (double)xc.at(cpn, a);
     }
     if (l == 0) {
 #pragma unroll
@@ -677,7 +676,9 @@ template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TPB) k_mg_restrict(Batch B, int fam, int l, VRef rv, VRef bv) {
     PROB_PROLOGUE
     // the transfer into the first tail level is done by the tail kernel
-    if (krylov_done(d) || l + 1 >= d->ltail || l + 1 >= d->nlev || tid >= d->lev[l + 1].nrow) return;
+    if (krylov_done(d) || l + 1 >= d->ltail || l + 1 >= d->nlev || (fam == 1 && l + 1 > d->ls_stop) ||
+        tid >= d->lev[l + 1].nrow)
+        return;
     row_restrict<DIM, R, BB, T>(d, fam, l, tid, resolve<T>(d, rv, fam, l, BB), resolve<T>(d, bv, fam, l + 1, BB));
 }
 
@@ -693,8 +694,9 @@ __global__ void __launch_bounds__(TPB) k_mg_prolong(Batch B, int fam, int l, VRe
 // A block owns a tile of the level (64 x 4 or 32 x 4 x 2 nodes, long in x so that a wavefront
 // reads each operator stream in contiguous runs) and first fills LDS for the tile plus a halo of
 // R nodes (component-major, conflict-free), then each thread finishes its node from LDS:
-//   down:  b = P^T r_fine (levels >= 1; the level's rhs on level 0), x0 = omega Dinv b in LDS,
-//          then r = b - A x0 for the tile (x0 and r written; b written on levels >= 1);
+//   down:  b = the level's rhs (on levels >= 1, P^T r_fine written before by k_mg_restrict, one
+//          thread per coarse node), x0 = omega Dinv b in LDS, then r = b - A x0 for the tile
+//          (x0 and r written);
 //   up:    x' = x0 + P x_coarse in LDS, then out = x' + omega Dinv (b - A x') for the tile.
 // Halo nodes are computed by both neighbouring blocks (same inputs, same values); only the
 // owning block writes them.
@@ -776,7 +778,7 @@ __device__ __forceinline__ void lds_stencil(const Lv<T>& v, int64_t row, const d
     }
 }
 
-template <int DIM, int R, int BB, typename T, bool FULL, bool RESTRICT>
+template <int DIM, int R, int BB, typename T, bool FULL>
 __global__ void __launch_bounds__(TPB) k_mg_down(Batch B, int fam, int l, VRef rhsv) {
     using Tl = Tile<DIM, R>;
     const int q = batch_find(B, blockIdx.x);
@@ -788,7 +790,6 @@ __global__ void __launch_bounds__(TPB) k_mg_down(Batch B, int fam, int l, VRef r
     View<T> rhs = resolve<T>(d, rhsv, fam, l, BB);
     View<T> x = resolve<T>(d, VRef{VK_LX, 0}, fam, l, BB);
     View<T> r = resolve<T>(d, VRef{VK_LR, 0}, fam, l, BB);
-    View<T> rf = resolve<T>(d, VRef{VK_LR, 0}, fam, RESTRICT ? l - 1 : l, BB);
     int o[3];
     tile_origin<DIM>(tile, v.n0, v.n1, o);
     const double om = d->omega;
@@ -803,22 +804,8 @@ __global__ void __launch_bounds__(TPB) k_mg_down(Batch B, int fam, int l, VRef r
         for (int a = 0; a < BB; ++a) bk[a] = xk[a] = 0.0;
         if (slot_node<DIM, R>(v, o, j, c)) {
             const int64_t pn = level_pad<DIM, R>(v, c);
-            if (RESTRICT) {
-                restrict_node<DIM, R, BB, T>(d, fam, l - 1, c, rf, bk);
-                // round to the storage precision, as the stored rhs is what the up-sweep reads
 #pragma unroll
-                for (int a = 0; a < BB; ++a) bk[a] = (double)(T)bk[a];
-                const int hx = j % Tl::HX - R, hy = (j / Tl::HX) % Tl::HY - R,
-                          hz = DIM == 3 ? j / (Tl::HX * Tl::HY) - R : 0;
-                const bool owned = hx >= 0 && hx < Tl::TX && hy >= 0 && hy < Tl::TY && hz >= 0 && hz < Tl::TZ;
-                if (owned) {
-#pragma unroll
-                    for (int a = 0; a < BB; ++a) rhs.at(pn, a) = (T)bk[a];
-                }
-            } else {
-#pragma unroll
-                for (int a = 0; a < BB; ++a) bk[a] = (double)rhs.at(pn, a);
-            }
+            for (int a = 0; a < BB; ++a) bk[a] = (double)rhs.at(pn, a);
             const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
             dinv_apply<BB>(v, row, bk, xk);
 #pragma unroll
@@ -1175,9 +1162,13 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
             const dim3 gt(Bt.pfx[Bt.n]);
             if (l == 0)
                 PPM_TIMED(KT_MG0_RESID, st,
-                          hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, false, false>), gt, tb, 0, st, Bt, fam, 0, rhs0));
-            else
-                hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, true, true>), gt, tb, 0, st, Bt, fam, l, LB);
+                          hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, false>), gt, tb, 0, st, Bt, fam, 0, rhs0));
+            else {
+                // restriction of the finer residual once per coarse node, then the sweep reads it
+                Batch Bc = make_batch(g.ddev, level_rows(hc, l), TPB);
+                hipLaunchKernelGGL((k_mg_restrict<DIM, R, BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l - 1, LR, LB);
+                hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, true>), gt, tb, 0, st, Bt, fam, l, LB);
+            }
         }
     } else {
         for (int l = 0; l < Lstd; ++l) {
