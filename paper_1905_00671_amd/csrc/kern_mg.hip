@@ -185,59 +185,6 @@ __device__ __forceinline__ void row_resid(const Dev* d, const Lv<T>& v, bool fs0
     }
 }
 
-// first sweep from a zero guess fused with the residual:
-//   x_i = omega Dinv_i rhs_i,   r_i = rhs_i - sum_k A_ik (omega Dinv_k rhs_k)
-// (neighbours off the grid have a zero rhs ghost; their inverse diagonal is read at row i).
-// The stencil is walked one x-row at a time, the SW loads of a row issued together (FULL: all
-// rows unrolled, for the small levels whose grids are too small to hide latency by occupancy).
-template <int DIM, int R, int BB, typename T, bool FULL>
-__device__ __forceinline__ void row_pre(const Dev* d, const Lv<T>& v, bool fs0, int64_t row, View<T> rhs, View<T> x,
-                                        View<T> r) {
-    using St = Sten<DIM, R>;
-    constexpr int SW = St::SW, NROW = St::S / SW;
-    int c[3];
-    const int64_t pn = lv_pad<DIM, R>(v, row, c);
-    const double om = d->omega;
-    double acc[BB], xi[BB];
-#pragma unroll
-    for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
-#pragma unroll(FULL ? (DIM == 3 ? 3 : NROW) : 1)
-    for (int t = 0; t < NROW; ++t) {
-        const int oy = t % SW - R, oz = DIM == 3 ? t / SW - R : 0;
-        bool iny = (unsigned)(c[1] + oy) < (unsigned)v.n1;
-        if (DIM == 3) iny = iny && (unsigned)(c[2] + oz) < (unsigned)v.n2;
-        const int64_t roff = (int64_t)v.n0 * (oy + (int64_t)v.n1 * oz);
-        const int64_t poff = (int64_t)v.np0 * (oy + (int64_t)v.np1 * oz);
-#pragma unroll
-        for (int i = 0; i < SW; ++i) {
-            const int ox = i - R, s = t * SW + i;
-            const bool in = iny && (unsigned)(c[0] + ox) < (unsigned)v.n0;
-            const int64_t krow = in ? row + ox + roff : row;
-            const int64_t pk = pn + ox + poff;
-            double bk[BB], xk[BB];
-#pragma unroll
-            for (int a = 0; a < BB; ++a) bk[a] = (double)rhs.at(pk, a);
-            dinv_apply<BB>(v, krow, bk, xk);
-#pragma unroll
-            for (int a = 0; a < BB; ++a) xk[a] *= om;
-            if (s == St::C) {
-#pragma unroll
-                for (int a = 0; a < BB; ++a) xi[a] = xk[a];
-            }
-#pragma unroll
-            for (int cc = 0; cc < BB; ++cc)
-#pragma unroll
-                for (int a = 0; a < BB; ++a) acc[a] -= v.opv(s, a, cc, row) * xk[cc];
-        }
-    }
-    if (fs0) acc[0] -= fs_term(d, pn) * xi[0];
-#pragma unroll
-    for (int a = 0; a < BB; ++a) {
-        x.at(pn, a) = (T)xi[a];
-        r.at(pn, a) = (T)acc[a];
-    }
-}
-
 // x += omega Dinv r
 template <int DIM, int R, int BB, typename T>
 __device__ __forceinline__ void row_update(const Dev* d, const Lv<T>& v, int64_t row, View<T> x, View<T> r) {
@@ -251,9 +198,9 @@ __device__ __forceinline__ void row_update(const Dev* d, const Lv<T>& v, int64_t
     for (int a = 0; a < BB; ++a) x.at(pn, a) = (T)((double)x.at(pn, a) + d->omega * y[a]);
 }
 
-// (P^T r)_I for coarse node I[] of level l+1 (level-0 fine dofs masked by the free mask)
-template <int DIM, int R, int BB, typename T>
-__device__ __forceinline__ void restrict_node(const Dev* d, int fam, int l, const int* I, View<T> r, double* acc) {
+// (P^T r)_I for coarse node I[] of level l+1 (MASK: level-0 fine dofs masked by the free mask)
+template <int DIM, int R, int BB, typename T, bool MASK>
+__device__ __forceinline__ void restrict_gather(const Dev* d, int fam, int l, const int* I, View<T> r, double* acc) {
     const MgLevel& F = d->lev[l];
     const int fn[3] = {F.n[0], F.n[1], F.n[2]}, fz[3] = {F.cz[0], F.cz[1], F.cz[2]};
     const int fp0 = F.np[0], fp1 = F.np[1];
@@ -279,10 +226,18 @@ __device__ __forceinline__ void restrict_node(const Dev* d, int fam, int l, cons
         fpn = (fi[0] + R) + (int64_t)fp0 * fpn;
 #pragma unroll
         for (int a = 0; a < BB; ++a) {
-            const double m = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
+            const double m = MASK ? mask0(d, fam, fpn, a) : 1.0;
             acc[a] += w * m * (double)r.at(fpn, a);
         }
     }
+}
+
+// the level test taken once, outside the unrolled gather (a conditional load per candidate
+// would put a branch between the loads)
+template <int DIM, int R, int BB, typename T>
+__device__ __forceinline__ void restrict_node(const Dev* d, int fam, int l, const int* I, View<T> r, double* acc) {
+    if (l == 0) restrict_gather<DIM, R, BB, T, true>(d, fam, l, I, r, acc);
+    else restrict_gather<DIM, R, BB, T, false>(d, fam, l, I, r, acc);
 }
 
 // coarse rhs of node Irow on level l+1 = (P^T r)_I
@@ -754,13 +709,15 @@ __device__ __forceinline__ bool own_node(const Lv<T>& v, const int* o, int* c, i
     return in;
 }
 
-// acc -= sum_s A(s) xs[slot + offset(s)], the stencil walked per x-row (FULL: all rows unrolled)
+// acc -= sum_s A(s) xs[slot + offset(s)], the stencil walked per x-row (FULL, or scalar blocks,
+// whose rows hold few loads each: rows unrolled)
 template <int DIM, int R, int BB, typename T, bool FULL>
 __device__ __forceinline__ void lds_stencil(const Lv<T>& v, int64_t row, const double* xs, int slot, double* acc) {
     using Tl = Tile<DIM, R>;
     using St = Sten<DIM, R>;
     constexpr int SW = St::SW, NROW = St::S / SW;
-#pragma unroll(FULL ? (DIM == 3 ? 3 : NROW) : 1)
+    constexpr int UNR = BB == 1 ? NROW : (FULL ? (DIM == 3 ? 3 : NROW) : 1);
+#pragma unroll(UNR)
     for (int t = 0; t < NROW; ++t) {
         const int oy = t % SW - R, oz = DIM == 3 ? t / SW - R : 0;
         const int srow = slot + Tl::HX * (oy + Tl::HY * oz);
@@ -888,12 +845,24 @@ __global__ void __launch_bounds__(TPB) k_mg_up(Batch B, int fam, int l, VRef rhs
     for (int a = 0; a < BB; ++a) out.at(pn, a) = (T)(sx[a * Tl::NS + slot] + d->omega * y[a]);
 }
 
+constexpr int TAIL_TPB = 256;
+
+// Residual of the n rows of a tail level: r = rhs - A x (POST: out = x + omega Dinv (rhs - A x)),
+// one thread per row.  (Splitting a row's stencil over several threads when the level has fewer
+// rows than threads measured no faster.)
+template <int DIM, int R, int BB, typename T, bool POST>
+__device__ __forceinline__ void tail_resid(const Dev* d, const Lv<T>& v, bool fs0, View<T> rhs, View<T> x,
+                                           View<T> out) {
+    for (int64_t i = threadIdx.x; i < v.nrow; i += blockDim.x)
+        row_resid<DIM, R, BB, T, true, POST>(d, v, fs0, i, rhs, x, out);
+    __syncthreads();
+}
+
 // All levels from the problem's ltail down to the coarsest and back up, in one block, starting
 // with the restriction of the residual of level ltail-1.  Same conventions as the per-level
 // kernels: on the way down a level's iterate is in LX and its residual in LR; on the way up the
 // prolongation adds the coarser correction (VK_SOL) into LX and the last smoothing sweep writes
 // the level's correction to LR (level 0: to out0).
-constexpr int TAIL_TPB = 256;
 template <int DIM, int R, int BB, typename T>
 __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs0, VRef out0) {
     const int q = blockIdx.x;
@@ -917,21 +886,17 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
         View<T> x = resolve<T>(d, LX, fam, l, BB);
         View<T> r = resolve<T>(d, LR, fam, l, BB);
         const int64_t n = v.nrow;
-        if (nsm == 1) {
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_pre<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
-            __syncthreads();
-        } else {
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_smooth0<DIM, R, BB, T>(d, v, i, rhs, x);
-            __syncthreads();
-            for (int k = 1; k < nsm; ++k) {
-                for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
-                __syncthreads();
-                for (int64_t i = threadIdx.x; i < n; i += nt) row_update<DIM, R, BB, T>(d, v, i, x, r);
-                __syncthreads();
-            }
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
+        // smoothing from a zero guess, then the residual against the stored iterate (in one block
+        // the iterate is L2-resident; the fused form would rebuild omega Dinv b for every
+        // neighbour of a row)
+        for (int64_t i = threadIdx.x; i < n; i += nt) row_smooth0<DIM, R, BB, T>(d, v, i, rhs, x);
+        __syncthreads();
+        for (int k = 1; k < nsm; ++k) {
+            tail_resid<DIM, R, BB, T, false>(d, v, fs0, rhs, x, r);
+            for (int64_t i = threadIdx.x; i < n; i += nt) row_update<DIM, R, BB, T>(d, v, i, x, r);
             __syncthreads();
         }
+        tail_resid<DIM, R, BB, T, false>(d, v, fs0, rhs, x, r);
         View<T> bc = resolve<T>(d, LB, fam, l + 1, BB);
         const int64_t nc = d->lev[l + 1].nrow;
         for (int64_t i = threadIdx.x; i < nc; i += nt) row_restrict<DIM, R, BB, T>(d, fam, l, i, r, bc);
@@ -944,20 +909,41 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
         View<T> x = resolve<T>(d, l == 0 ? out0 : LX, fam, l, BB);
         const int n = (int)(C.nrow * BB);
         const T* Ci = (const T*)(fam == 0 ? d->cinvA : d->cinvS);
-        __shared__ double bv[CMAX];
+        // x = Ci b: NPART threads per row, each a fixed-length slice of the row with its loads
+        // unconditional (index clamped, weight zero past n), partial sums added in LDS
+        constexpr int NPART = TAIL_TPB / CMAX, SL = (CMAX + NPART - 1) / NPART;
+        __shared__ double bv[CMAX + SL * NPART];
+        __shared__ double part[NPART * CMAX];
         if (n <= CMAX) {
-            for (int e = threadIdx.x; e < n; e += nt) {
-                int c[3];
-                real_coords(e / BB, C.n, DIM, c);
-                bv[e] = (double)rhs.at(padded(c, C.np, R, DIM), e % BB);
+            for (int e = threadIdx.x; e < CMAX + SL * NPART; e += nt) {
+                double b = 0.0;
+                if (e < n) {
+                    int c[3];
+                    real_coords(e / BB, C.n, DIM, c);
+                    b = (double)rhs.at(padded(c, C.np, R, DIM), e % BB);
+                }
+                bv[e] = b;
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < n; e += nt) {
+            const int e = threadIdx.x % CMAX, pi = threadIdx.x / CMAX;
+            if (pi < NPART && e < n) {
+                const T* crow = Ci + (int64_t)e * n;
                 double t = 0.0;
-                for (int k = 0; k < n; ++k) t += (double)Ci[(int64_t)e * n + k] * bv[k];
+#pragma unroll
+                for (int j = 0; j < SL; ++j) {
+                    const int k = pi * SL + j;
+                    t += (double)crow[k < n ? k : n - 1] * bv[k];
+                }
+                part[pi * CMAX + e] = t;
+            }
+            __syncthreads();
+            for (int e2 = threadIdx.x; e2 < n; e2 += nt) {
+                double t = 0.0;
+#pragma unroll
+                for (int q2 = 0; q2 < NPART; ++q2) t += part[q2 * CMAX + e2];
                 int c[3];
-                real_coords(e / BB, C.n, DIM, c);
-                x.at(padded(c, C.np, R, DIM), e % BB) = (T)t;
+                real_coords(e2 / BB, C.n, DIM, c);
+                x.at(padded(c, C.np, R, DIM), e2 % BB) = (T)t;
             }
         }
         __syncthreads();
@@ -974,14 +960,11 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
         for (int64_t i = threadIdx.x; i < n; i += nt) row_prolong<DIM, R, BB, T>(d, fam, l, i, xc, x);
         __syncthreads();
         for (int k = 1; k < nsm; ++k) {
-            for (int64_t i = threadIdx.x; i < n; i += nt) row_resid<DIM, R, BB, T, true>(d, v, fs0, i, rhs, x, r);
-            __syncthreads();
+            tail_resid<DIM, R, BB, T, false>(d, v, fs0, rhs, x, r);
             for (int64_t i = threadIdx.x; i < n; i += nt) row_update<DIM, R, BB, T>(d, v, i, x, r);
             __syncthreads();
         }
-        for (int64_t i = threadIdx.x; i < n; i += nt)
-            row_resid<DIM, R, BB, T, true, true>(d, v, fs0, i, rhs, x, out);
-        __syncthreads();
+        tail_resid<DIM, R, BB, T, true>(d, v, fs0, rhs, x, out);
     }
 }
 

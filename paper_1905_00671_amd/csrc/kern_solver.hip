@@ -80,56 +80,81 @@ __device__ __forceinline__ int64_t node_pad(const Dev* d, int64_t tid) {
     return padded(c, d->np1, d->R, d->dim);
 }
 
+// The vector kernels take the block size at compile time and read every operand of a node
+// before writing, through restrict-qualified pointers, so the loads of all b components are in
+// flight together.
+
 // x = 0, r = rhat = -R, p = v = 0; partial (r, r)
-template <typename T>
+template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_init(Batch B) {
     PROB_PROLOGUE
     double v[1] = {0.0};
     if (tid < d->Nnode) {
-        const int64_t pn = node_pad<T>(d, tid);
-        const int bs = d->b;
-        for (int a = 0; a < bs; ++a) {
-            int64_t k = pn * bs + a;
-            T r = (T)(-d->Rv[k]);
-            vp<T>(d->kx)[k] = 0;
-            vp<T>(d->kr)[k] = r;
-            vp<T>(d->kh)[k] = r;
-            vp<T>(d->kp)[k] = 0;
-            vp<T>(d->kv)[k] = 0;
-            v[0] += (double)r * (double)r;
+        const int64_t k0 = node_pad<T>(d, tid) * BS;
+        const double* __restrict__ Rv = d->Rv;
+        T* __restrict__ x = vp<T>(d->kx);
+        T* __restrict__ r = vp<T>(d->kr);
+        T* __restrict__ h = vp<T>(d->kh);
+        T* __restrict__ pp = vp<T>(d->kp);
+        T* __restrict__ vv = vp<T>(d->kv);
+        T rv[BS];
+#pragma unroll
+        for (int a = 0; a < BS; ++a) rv[a] = (T)(-Rv[k0 + a]);
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+            x[k0 + a] = 0;
+            r[k0 + a] = rv[a];
+            h[k0 + a] = rv[a];
+            pp[k0 + a] = 0;
+            vv[k0 + a] = 0;
+            v[0] += (double)rv[a] * (double)rv[a];
         }
     }
     block_partials<1>(d, lb, v);
 }
 
 // p = r + beta (p - omega v)
-template <typename T>
+template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_p(Batch B) {
     PROB_PROLOGUE
     if (krylov_done(d) || tid >= d->Nnode) return;
-    const int64_t pn = node_pad<T>(d, tid);
-    const int bs = d->b;
+    const int64_t k0 = node_pad<T>(d, tid) * BS;
     const T beta = (T)d->scal[SC_BETA], om = (T)d->scal[SC_OMEGA];
-    for (int a = 0; a < bs; ++a) {
-        int64_t k = pn * bs + a;
-        T* p = vp<T>(d->kp);
-        p[k] = vp<T>(d->kr)[k] + beta * (p[k] - om * vp<T>(d->kv)[k]);
+    T* __restrict__ p = vp<T>(d->kp);
+    const T* __restrict__ r = vp<T>(d->kr);
+    const T* __restrict__ v = vp<T>(d->kv);
+    T pv[BS], rv[BS], vv[BS];
+#pragma unroll
+    for (int a = 0; a < BS; ++a) {
+        pv[a] = p[k0 + a];
+        rv[a] = r[k0 + a];
+        vv[a] = v[k0 + a];
     }
+#pragma unroll
+    for (int a = 0; a < BS; ++a) p[k0 + a] = rv[a] + beta * (pv[a] - om * vv[a]);
 }
 
 // s = r - alpha v; partial (s, s)
-template <typename T>
+template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_s(Batch B) {
     PROB_PROLOGUE
     double v[1] = {0.0};
     if (!krylov_done(d) && tid < d->Nnode) {
-        const int64_t pn = node_pad<T>(d, tid);
-        const int bs = d->b;
+        const int64_t k0 = node_pad<T>(d, tid) * BS;
         const T al = (T)d->scal[SC_ALPHA];
-        for (int a = 0; a < bs; ++a) {
-            int64_t k = pn * bs + a;
-            T sv = vp<T>(d->kr)[k] - al * vp<T>(d->kv)[k];
-            vp<T>(d->ks)[k] = sv;
+        const T* __restrict__ r = vp<T>(d->kr);
+        const T* __restrict__ vv = vp<T>(d->kv);
+        T* __restrict__ sp = vp<T>(d->ks);
+        T rv[BS], w[BS];
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+            rv[a] = r[k0 + a];
+            w[a] = vv[k0 + a];
+        }
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+            const T sv = rv[a] - al * w[a];
+            sp[k0 + a] = sv;
             v[0] += (double)sv * (double)sv;
         }
     }
@@ -137,21 +162,37 @@ __global__ void __launch_bounds__(TPB) k_bicg_s(Batch B) {
 }
 
 // x += alpha ph + omega sh; r = s - omega t; partials (rhat, r), (r, r)
-template <typename T>
+template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_xr(Batch B) {
     PROB_PROLOGUE
     double v[2] = {0.0, 0.0};
     if (!krylov_done(d) && tid < d->Nnode) {
-        const int64_t pn = node_pad<T>(d, tid);
-        const int bs = d->b;
+        const int64_t k0 = node_pad<T>(d, tid) * BS;
         const T al = (T)d->scal[SC_ALPHA], om = (T)d->scal[SC_OMEGA];
-        for (int a = 0; a < bs; ++a) {
-            int64_t k = pn * bs + a;
-            vp<T>(d->kx)[k] += al * vp<T>(d->kph)[k] + om * vp<T>(d->ksh)[k];
-            T r = vp<T>(d->ks)[k] - om * vp<T>(d->kt)[k];
-            vp<T>(d->kr)[k] = r;
-            v[0] += (double)vp<T>(d->kh)[k] * (double)r;
-            v[1] += (double)r * (double)r;
+        T* __restrict__ x = vp<T>(d->kx);
+        T* __restrict__ r = vp<T>(d->kr);
+        const T* __restrict__ ph = vp<T>(d->kph);
+        const T* __restrict__ sh = vp<T>(d->ksh);
+        const T* __restrict__ sp = vp<T>(d->ks);
+        const T* __restrict__ tp = vp<T>(d->kt);
+        const T* __restrict__ h = vp<T>(d->kh);
+        T xv[BS], pv[BS], qv[BS], sv[BS], tv[BS], hv[BS];
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+            xv[a] = x[k0 + a];
+            pv[a] = ph[k0 + a];
+            qv[a] = sh[k0 + a];
+            sv[a] = sp[k0 + a];
+            tv[a] = tp[k0 + a];
+            hv[a] = h[k0 + a];
+        }
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+            x[k0 + a] = xv[a] + (al * pv[a] + om * qv[a]);
+            const T rr = sv[a] - om * tv[a];
+            r[k0 + a] = rr;
+            v[0] += (double)hv[a] * (double)rr;
+            v[1] += (double)rr * (double)rr;
         }
     }
     block_partials<2>(d, lb, v);
@@ -246,15 +287,15 @@ static void krylov_iters_t(const Group& g, const std::vector<const Dev*>& hc, in
     const dim3 gN(Bn.pfx[Bn.n]), tb(TPB);
     // vector ids: 0 x, 1 r, 2 rhat, 3 p, 4 v, 5 s, 6 t, 7 ph, 8 sh
     for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(k_bicg_p<T>, gN, tb, 0, st, Bn);
+        hipLaunchKernelGGL((k_bicg_p<DIM + 1, T>), gN, tb, 0, st, Bn);
         launch_precond_apply(g, hc, 3, 7, st);
         PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gN, tb, 0, st, Bn, 7, 4, 2, 1, 1));
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 1, rtol, maxit);
-        hipLaunchKernelGGL(k_bicg_s<T>, gN, tb, 0, st, Bn);
+        hipLaunchKernelGGL((k_bicg_s<DIM + 1, T>), gN, tb, 0, st, Bn);
         launch_precond_apply(g, hc, 5, 8, st);
         PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gN, tb, 0, st, Bn, 8, 6, 5, 2, 1));
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 2, rtol, maxit);
-        hipLaunchKernelGGL(k_bicg_xr<T>, gN, tb, 0, st, Bn);
+        hipLaunchKernelGGL((k_bicg_xr<DIM + 1, T>), gN, tb, 0, st, Bn);
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 3, rtol, maxit);
     }
 }
@@ -262,8 +303,14 @@ static void krylov_iters_t(const Group& g, const std::vector<const Dev*>& hc, in
 void launch_krylov_init(const Group& g, double rtol, int maxit, hipStream_t st) {
     Batch Bn = make_batch(g.ddev, g.nnode, TPB);
     Batch B1 = make_batch_one_block(g.ddev);
-    if (g.mixed) hipLaunchKernelGGL(k_bicg_init<float>, dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn);
-    else hipLaunchKernelGGL(k_bicg_init<double>, dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn);
+    const dim3 gN(Bn.pfx[Bn.n]), tb(TPB);
+    if (g.dim == 2) {
+        if (g.mixed) hipLaunchKernelGGL((k_bicg_init<3, float>), gN, tb, 0, st, Bn);
+        else hipLaunchKernelGGL((k_bicg_init<3, double>), gN, tb, 0, st, Bn);
+    } else {
+        if (g.mixed) hipLaunchKernelGGL((k_bicg_init<4, float>), gN, tb, 0, st, Bn);
+        else hipLaunchKernelGGL((k_bicg_init<4, double>), gN, tb, 0, st, Bn);
+    }
     hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), dim3(TPB), 0, st, B1, 0, rtol, maxit);
 }
 
