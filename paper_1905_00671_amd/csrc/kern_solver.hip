@@ -19,25 +19,41 @@ namespace ppm {
 // ---------------------------------------------------------------------------------------------
 // SpMV on the fixed-stencil block rows: y = J x, optional dot products
 //   mode 1: partial (a, y)        mode 2: partials (y, a), (y, y)
+// FP64: one thread per scalar row (node, component a).  Wavefront W of the launch takes
+// component a = W mod b of the 64 consecutive nodes 64 (W div b) + lane, so each of its S b
+// Jacobian loads is one contiguous 64-row run, and b times as many wavefronts as with a thread
+// per node keep enough bytes in flight (2D config: 78 -> 54 us).  FP32: one thread per node and
+// all its b rows (half the bytes per load; splitting measured slower there).  Launched with
+// spmv_blocks(dim, Nnode, T is double) blocks.
 // ---------------------------------------------------------------------------------------------
 template <int DIM, int R, typename T>
 __global__ void __launch_bounds__(TPB) k_spmv(Batch B, int ix, int iy, int ia, int mode, int check_done) {
     PROB_PROLOGUE
+    constexpr bool SPLIT = sizeof(T) == 8;
     constexpr int BS = DIM + 1;
+    constexpr int NA = SPLIT ? 1 : BS;   // component rows per thread
     constexpr int SW = 2 * R + 1;
     constexpr int S = DIM == 2 ? SW * SW : SW * SW * SW;
     double dots[2] = {0.0, 0.0};
+    int a0 = 0;
+    int64_t row = tid;
+    if (SPLIT) {
+        const int64_t W = lb * (TPB / 64) + threadIdx.x / 64;
+        a0 = (int)(W % BS);
+        row = (W / BS) * 64 + (threadIdx.x & 63);
+    }
     bool skip = check_done && krylov_done(d);
-    if (!skip && tid < d->Nnode) {
+    if (!skip && row < d->Nnode) {
         void* const vecs[10] = {d->kx, d->kr, d->kh, d->kp, d->kv, d->ks, d->kt, d->kph, d->ksh, d->kbt};
         const T* __restrict__ x = vp<T>(vecs[ix]);
         T* __restrict__ y = vp<T>(vecs[iy]);
         const T* __restrict__ J = vp<T>(d->J);
         int c[3];
-        real_coords(tid, d->nn, DIM, c);
+        real_coords(row, d->nn, DIM, c);
         const int64_t pn = padded(c, d->np1, R, DIM);
-        double acc[BS];
-        for (int a = 0; a < BS; ++a) acc[a] = 0.0;
+        double acc[NA];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) acc[i] = 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int64_t pk = pn + stencil_offset(s, R, DIM, d->np1);
@@ -45,24 +61,27 @@ __global__ void __launch_bounds__(TPB) k_spmv(Batch B, int ix, int iy, int ia, i
 #pragma unroll
             for (int cc = 0; cc < BS; ++cc) xv[cc] = x[pk * BS + cc];
 #pragma unroll
-            for (int a = 0; a < BS; ++a) {
+            for (int i = 0; i < NA; ++i) {
+                const int a = a0 + i;
                 T t = 0;
 #pragma unroll
                 for (int cc = 0; cc < BS; ++cc) {
-                    const T* jp = &J[jidx<DIM>((s * BS + a) * BS + cc, tid, S * BS * BS, d->Nnode)];
+                    const T* jp = &J[jidx<DIM>((s * BS + a) * BS + cc, row, S * BS * BS, d->Nnode)];
                     // 3D: the Jacobian (GBs) streams from HBM, keep it out of the caches; 2D: it
                     // mostly stays in the Infinity Cache between launches, plain loads measured faster
                     t += (DIM == 3 ? __builtin_nontemporal_load(jp) : *jp) * xv[cc];
                 }
-                acc[a] += (double)t;
+                acc[i] += (double)t;
             }
         }
-        for (int a = 0; a < BS; ++a) y[pn * BS + a] = (T)acc[a];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) y[pn * BS + a0 + i] = (T)acc[i];
         if (mode) {
             const T* __restrict__ av = vp<T>(vecs[ia]);
-            for (int a = 0; a < BS; ++a) {
-                double yv = (double)(T)acc[a];
-                dots[0] += (double)av[pn * BS + a] * yv;
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                const double yv = (double)(T)acc[i];
+                dots[0] += (double)av[pn * BS + a0 + i] * yv;
                 dots[1] += yv * yv;
             }
         }
@@ -208,7 +227,8 @@ __global__ void k_bicg_scalars(Batch B, int stage, double rtol, int maxit) {
     const Dev* d = B.d[q];
     if (stage != 0 && krylov_done(d)) return;
     __shared__ double sh[2][TPB];
-    const int64_t nblk = (d->Nnode + TPB - 1) / TPB;
+    // stages 1 and 2 follow an SpMV (its own block shape), 0 and 3 a node-per-thread kernel
+    const int64_t nblk = (stage == 1 || stage == 2) ? spmv_blocks(d->dim, d->Nnode, !d->mixed) : (d->Nnode + TPB - 1) / TPB;
     double a = 0.0, b2 = 0.0;
     for (int64_t i = threadIdx.x; i < nblk; i += TPB) {
         a += d->partial[i * 4 + 0];
@@ -279,21 +299,28 @@ __global__ void __launch_bounds__(TPB) k_newton_update(Batch B) {
     }
 }
 
+static std::vector<int64_t> spmv_grid(const Group& g) {
+    std::vector<int64_t> v;
+    for (size_t q = 0; q < g.nnode.size(); ++q) v.push_back(spmv_blocks(g.dim, g.nnode[q], !g.mixed));
+    return v;
+}
+
 template <int DIM, int R, typename T>
 static void krylov_iters_t(const Group& g, const std::vector<const Dev*>& hc, int iters, double rtol, int maxit,
                            hipStream_t st) {
     Batch Bn = make_batch(g.ddev, g.nnode, TPB);
+    Batch Bs = make_batch_blocks(g.ddev, spmv_grid(g));
     Batch B1 = make_batch_one_block(g.ddev);
-    const dim3 gN(Bn.pfx[Bn.n]), tb(TPB);
+    const dim3 gN(Bn.pfx[Bn.n]), gS(Bs.pfx[Bs.n]), tb(TPB);
     // vector ids: 0 x, 1 r, 2 rhat, 3 p, 4 v, 5 s, 6 t, 7 ph, 8 sh
     for (int it = 0; it < iters; ++it) {
         hipLaunchKernelGGL((k_bicg_p<DIM + 1, T>), gN, tb, 0, st, Bn);
         launch_precond_apply(g, hc, 3, 7, st);
-        PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gN, tb, 0, st, Bn, 7, 4, 2, 1, 1));
+        PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gS, tb, 0, st, Bs, 7, 4, 2, 1, 1));
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 1, rtol, maxit);
         hipLaunchKernelGGL((k_bicg_s<DIM + 1, T>), gN, tb, 0, st, Bn);
         launch_precond_apply(g, hc, 5, 8, st);
-        PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gN, tb, 0, st, Bn, 8, 6, 5, 2, 1));
+        PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gS, tb, 0, st, Bs, 8, 6, 5, 2, 1));
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 2, rtol, maxit);
         hipLaunchKernelGGL((k_bicg_xr<DIM + 1, T>), gN, tb, 0, st, Bn);
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 3, rtol, maxit);
@@ -390,19 +417,20 @@ __global__ void k_set_state(Batch B, const double* __restrict__ U, const double*
 
 void launch_apply_jacobian(const Dev* dd, const Dev* hd, const double* v_nat, double* y_nat, hipStream_t st) {
     Batch Bn = make_batch({dd}, {hd->Nnode}, TPB);
-    const dim3 gN(Bn.pfx[1]), tb(TPB);
+    Batch Bs = make_batch_blocks({dd}, {spmv_blocks(hd->dim, hd->Nnode, !hd->mixed)});
+    const dim3 gN(Bn.pfx[1]), gS(Bs.pfx[1]), tb(TPB);
     int R = hd->R;
     if (hd->mixed) {
         hipLaunchKernelGGL(k_nat_to_pad<float>, gN, tb, 0, st, Bn, v_nat, 0);
-        if (hd->dim == 2 && R == 1) hipLaunchKernelGGL((k_spmv<2, 1, float>), gN, tb, 0, st, Bn, 3, 4, 0, 0, 0);
-        else if (hd->dim == 2) hipLaunchKernelGGL((k_spmv<2, 2, float>), gN, tb, 0, st, Bn, 3, 4, 0, 0, 0);
-        else hipLaunchKernelGGL((k_spmv<3, 1, float>), gN, tb, 0, st, Bn, 3, 4, 0, 0, 0);
+        if (hd->dim == 2 && R == 1) hipLaunchKernelGGL((k_spmv<2, 1, float>), gS, tb, 0, st, Bs, 3, 4, 0, 0, 0);
+        else if (hd->dim == 2) hipLaunchKernelGGL((k_spmv<2, 2, float>), gS, tb, 0, st, Bs, 3, 4, 0, 0, 0);
+        else hipLaunchKernelGGL((k_spmv<3, 1, float>), gS, tb, 0, st, Bs, 3, 4, 0, 0, 0);
         hipLaunchKernelGGL(k_pad_to_nat<float>, gN, tb, 0, st, Bn, y_nat, 0);
     } else {
         hipLaunchKernelGGL(k_nat_to_pad<double>, gN, tb, 0, st, Bn, v_nat, 0);
-        if (hd->dim == 2 && R == 1) hipLaunchKernelGGL((k_spmv<2, 1, double>), gN, tb, 0, st, Bn, 3, 4, 0, 0, 0);
-        else if (hd->dim == 2) hipLaunchKernelGGL((k_spmv<2, 2, double>), gN, tb, 0, st, Bn, 3, 4, 0, 0, 0);
-        else hipLaunchKernelGGL((k_spmv<3, 1, double>), gN, tb, 0, st, Bn, 3, 4, 0, 0, 0);
+        if (hd->dim == 2 && R == 1) hipLaunchKernelGGL((k_spmv<2, 1, double>), gS, tb, 0, st, Bs, 3, 4, 0, 0, 0);
+        else if (hd->dim == 2) hipLaunchKernelGGL((k_spmv<2, 2, double>), gS, tb, 0, st, Bs, 3, 4, 0, 0, 0);
+        else hipLaunchKernelGGL((k_spmv<3, 1, double>), gS, tb, 0, st, Bs, 3, 4, 0, 0, 0);
         hipLaunchKernelGGL(k_pad_to_nat<double>, gN, tb, 0, st, Bn, y_nat, 0);
     }
 }

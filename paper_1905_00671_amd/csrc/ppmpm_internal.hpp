@@ -157,6 +157,15 @@ __host__ __device__ __forceinline__ int64_t jidx(int e, int64_t row, int NE, int
 }
 __host__ __device__ __forceinline__ int64_t jrows_padded(int64_t nrow) { return (nrow + JB - 1) / JB * JB; }
 
+// SpMV launch shape, the number of blocks (and of reduction partials) of a problem.  FP64: one
+// wavefront per (component row a, run of 64 consecutive nodes), four wavefronts per block;
+// FP32: one thread per node.
+__host__ __device__ __forceinline__ int64_t spmv_blocks(int dim, int64_t nnode, bool fp64) {
+    if (!fp64) return (nnode + TPB - 1) / TPB;
+    const int64_t waves = (nnode + 63) / 64 * (dim + 1);
+    return (waves + 3) / 4;
+}
+
 // Batch of problems of one kernel variant, passed by value to every kernel.
 struct Batch {
     int n;

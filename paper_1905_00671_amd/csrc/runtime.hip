@@ -258,7 +258,8 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
     h.cinvS = c.take<char>((size_t)std::min<int64_t>(nS * nS, CMAX * CMAX) * TS);
     h.cwork = c.take<double>((size_t)CMAX * CMAX);
     int64_t maxrows = std::max<int64_t>(h.Nnode, np);
-    h.maxblocks = std::max<int64_t>((maxrows + TPB - 1) / TPB + 1, node_tiles(D, h.nn));
+    h.maxblocks = std::max<int64_t>(std::max<int64_t>((maxrows + TPB - 1) / TPB + 1, node_tiles(D, h.nn)),
+                                    spmv_blocks(D, h.Nnode, true));
     h.partial = c.take<double>((size_t)h.maxblocks * 4);
     h.scal = c.take<double>(NSCAL);
     h.flags = c.take<int>(NFLAG);
