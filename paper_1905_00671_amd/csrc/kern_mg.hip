@@ -735,8 +735,11 @@ __device__ __forceinline__ void lds_stencil(const Lv<T>& v, int64_t row, const d
     }
 }
 
+// Coarse levels (FULL) launch a few blocks only: the occupancy hint lets the compiler keep all of
+// a thread's operator loads in flight instead of trading registers for waves it never gets
+// (3D coarse down-sweep 91 -> 22 us).
 template <int DIM, int R, int BB, typename T, bool FULL>
-__global__ void __launch_bounds__(TPB) k_mg_down(Batch B, int fam, int l, VRef rhsv) {
+__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FULL ? 2 : 8))) k_mg_down(Batch B, int fam, int l, VRef rhsv) {
     using Tl = Tile<DIM, R>;
     const int q = batch_find(B, blockIdx.x);
     const Dev* __restrict__ d = B.d[q];
@@ -792,7 +795,7 @@ __global__ void __launch_bounds__(TPB) k_mg_down(Batch B, int fam, int l, VRef r
 }
 
 template <int DIM, int R, int BB, typename T, bool FULL>
-__global__ void __launch_bounds__(TPB) k_mg_up(Batch B, int fam, int l, VRef rhsv, VRef outv) {
+__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FULL ? 2 : 8))) k_mg_up(Batch B, int fam, int l, VRef rhsv, VRef outv) {
     using Tl = Tile<DIM, R>;
     const int q = batch_find(B, blockIdx.x);
     const Dev* __restrict__ d = B.d[q];
