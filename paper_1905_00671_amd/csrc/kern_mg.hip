@@ -646,9 +646,11 @@ __global__ void __launch_bounds__(TPB) k_mg_prolong(Batch B, int fam, int l, VRe
 
 // ---------------------------------------------------------------------------------------------
 // Halo-tiled sweeps for V(1,1): one kernel per level on the way down and one on the way up.
-// A block owns a tile of the level (64 x 4 or 32 x 4 x 2 nodes, long in x so that a wavefront
-// reads each operator stream in contiguous runs) and first fills LDS for the tile plus a halo of
-// R nodes (component-major, conflict-free), then each thread finishes its node from LDS:
+// A block owns a tile of the level (64 x 4 or 64 x 2 x 2 nodes: a wavefront is one x-run of 64
+// nodes, so it reads each operator stream in one contiguous run; 3D 32 x 4 x 2 tiles measured 8%
+// slower) and first fills LDS with x0 for the tile plus a halo of R nodes (component-major,
+// conflict-free; the rhs of the own node is read again from memory rather than kept in LDS, which
+// halves the LDS of the down sweep), then each thread finishes its node from LDS:
 //   down:  b = the level's rhs (on levels >= 1, P^T r_fine written before by k_mg_restrict, one
 //          thread per coarse node), x0 = omega Dinv b in LDS, then r = b - A x0 for the tile
 //          (x0 and r written);
@@ -745,7 +747,7 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
     const Dev* __restrict__ d = B.d[q];
     const int64_t tile = blockIdx.x - B.pfx[q];
     if (krylov_done(d) || l >= d->ltail || (fam == 1 && l > d->ls_stop)) return;
-    __shared__ double sx[Tl::NS * BB], sb[Tl::NS * BB];
+    __shared__ double sx[Tl::NS * BB];
     const Lv<T> v = lv_of<BB, T>(d, fam, l);
     View<T> rhs = resolve<T>(d, rhsv, fam, l, BB);
     View<T> x = resolve<T>(d, VRef{VK_LX, 0}, fam, l, BB);
@@ -773,7 +775,6 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
         }
 #pragma unroll
         for (int a = 0; a < BB; ++a) {
-            sb[a * Tl::NS + j] = bk[a];
             sx[a * Tl::NS + j] = xk[a];
         }
     }
@@ -784,7 +785,7 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
     const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
     double acc[BB];
 #pragma unroll
-    for (int a = 0; a < BB; ++a) acc[a] = sb[a * Tl::NS + slot];
+    for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
     lds_stencil<DIM, R, BB, T, FULL>(v, row, sx, slot, acc);
     if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * sx[slot];
 #pragma unroll

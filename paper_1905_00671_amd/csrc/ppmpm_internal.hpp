@@ -18,7 +18,7 @@ constexpr int TILE3X = 8, TILE3Y = 8, TILE3Z = 4;
 // node tiles of the multigrid sweeps: long in x, so that a wavefront reads every operator stream
 // in runs of 256-512 contiguous bytes
 constexpr int MGT2X = 64, MGT2Y = 4;
-constexpr int MGT3X = 32, MGT3Y = 4, MGT3Z = 2;
+constexpr int MGT3X = 64, MGT3Y = 2, MGT3Z = 2;
 
 // Particle state, structure of arrays: field f, component c of particle i lives at
 // base[(f + c) * stride + i].  Every variant uses the same slots (2D leaves some unused).
