@@ -875,6 +875,27 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
     const int L0 = d->ltail, L = d->nlev, nsm = d->mg_nsm;
     const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0}, SOL{VK_SOL, 0};
     const int nt = blockDim.x;
+    // Warm this CU's L2 with the operators and inverse diagonals of the first two tail levels,
+    // which the smoothing passes would otherwise fetch from HBM one dependent round trip at a
+    // time: one dword per 128-byte line, all issued before the first restriction (offsets clamped
+    // into each array) and consumed after it.
+    constexpr int PF = 8;
+    uint32_t pfv[4][PF];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int l = L0 + (m >> 1);
+        const bool ok = l >= 1 && l < L - 1;   // level 0 is a view of the Jacobian
+        const MgLevel& Q = d->lev[ok ? l : L0];
+        const void* p = (m & 1) ? (fam == 0 ? Q.Ad : Q.Sd) : (fam == 0 ? Q.A : Q.Sm);
+        const int64_t words = ok ? ((m & 1) ? Q.nrow : Q.nrow * d->S) * BB * BB * (int64_t)sizeof(T) / 4 : 0;
+        const uint32_t* base = words > 0 ? (const uint32_t*)p : (const uint32_t*)d->scal;
+        const int64_t last = words > 0 ? words - 1 : 0;
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const int64_t w = ((int64_t)j * nt + threadIdx.x) * 32;
+            pfv[m][j] = base[w < last ? w : last];
+        }
+    }
     if (L0 > 0) {
         // right-hand side of the first tail level from the residual of the level above it
         View<T> rf = resolve<T>(d, LR, fam, L0 - 1, BB);
@@ -882,6 +903,14 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
         const int64_t nc = d->lev[L0].nrow;
         for (int64_t i = threadIdx.x; i < nc; i += nt) row_restrict<DIM, R, BB, T>(d, fam, L0 - 1, i, rf, bc);
         __syncthreads();
+    }
+    {
+        uint32_t pf = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < PF; ++j) pf ^= pfv[m][j];
+        asm volatile("" ::"v"(pf));   // keeps the warming loads (no instruction)
     }
     for (int l = L0; l < L - 1; ++l) {
         const Lv<T> v = lv_of<BB, T>(d, fam, l);
