@@ -711,10 +711,36 @@ __device__ __forceinline__ bool own_node(const Lv<T>& v, const int* o, int* c, i
     return in;
 }
 
+// Operator row of a thread's own node.  PRE (coarse levels, rows of at most 100 entries): loaded
+// into registers at kernel start, so that its latency overlaps the halo loads instead of following
+// the barrier; otherwise read from memory where it is used.
+template <int DIM, int R, int BB, typename T, bool PRE>
+struct OwnRow {
+    static constexpr int N = PRE ? Sten<DIM, R>::S * BB * BB : 1;
+    T w[N];
+    __device__ __forceinline__ void load(const Lv<T>& v, int64_t row) {
+        if constexpr (PRE) {
+#pragma unroll
+            for (int s = 0; s < Sten<DIM, R>::S; ++s)
+#pragma unroll
+                for (int a = 0; a < BB; ++a)
+#pragma unroll
+                    for (int c = 0; c < BB; ++c) w[(s * BB + a) * BB + c] = (T)v.opv(s, a, c, row);
+        }
+    }
+    __device__ __forceinline__ double at(const Lv<T>& v, int s, int a, int c, int64_t row) const {
+        if constexpr (PRE) return (double)w[(s * BB + a) * BB + c];
+        else return v.opv(s, a, c, row);
+    }
+};
+template <int DIM, int R, int BB, bool FULL>
+constexpr bool own_row_pre() { return FULL && Sten<DIM, R>::S * BB * BB <= 100; }
+
 // acc -= sum_s A(s) xs[slot + offset(s)], the stencil walked per x-row (FULL, or scalar blocks,
 // whose rows hold few loads each: rows unrolled)
-template <int DIM, int R, int BB, typename T, bool FULL>
-__device__ __forceinline__ void lds_stencil(const Lv<T>& v, int64_t row, const double* xs, int slot, double* acc) {
+template <int DIM, int R, int BB, typename T, bool FULL, bool PRE>
+__device__ __forceinline__ void lds_stencil(const Lv<T>& v, const OwnRow<DIM, R, BB, T, PRE>& orow, int64_t row,
+                                            const double* xs, int slot, double* acc) {
     using Tl = Tile<DIM, R>;
     using St = Sten<DIM, R>;
     constexpr int SW = St::SW, NROW = St::S / SW;
@@ -731,7 +757,7 @@ __device__ __forceinline__ void lds_stencil(const Lv<T>& v, int64_t row, const d
             for (int cc = 0; cc < BB; ++cc) {
                 const double xv = xs[cc * Tl::NS + sk];
 #pragma unroll
-                for (int a = 0; a < BB; ++a) acc[a] -= v.opv(s, a, cc, row) * xv;
+                for (int a = 0; a < BB; ++a) acc[a] -= orow.at(v, s, a, cc, row) * xv;
             }
         }
     }
@@ -755,6 +781,20 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
     int o[3];
     tile_origin<DIM>(tile, v.n0, v.n1, o);
     const double om = d->omega;
+    constexpr bool PRE = own_row_pre<DIM, R, BB, FULL>();
+    int c[3], slot;
+    const bool own = own_node<DIM, R>(v, o, c, &slot);
+    const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
+    const int64_t pn = own ? level_pad<DIM, R>(v, c) : 0;
+    OwnRow<DIM, R, BB, T, PRE> orow;
+    double acc[BB];
+#pragma unroll
+    for (int a = 0; a < BB; ++a) acc[a] = 0.0;
+    if (own) {
+        orow.load(v, row);
+#pragma unroll
+        for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
+    }
     // all slots of a thread unrolled, so that their loads are in flight together
 #pragma unroll
     for (int jj = 0; jj < (Tl::NS + TPB - 1) / TPB; ++jj) {
@@ -779,14 +819,8 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
         }
     }
     __syncthreads();
-    int c[3], slot;
-    if (!own_node<DIM, R>(v, o, c, &slot)) return;
-    const int64_t pn = level_pad<DIM, R>(v, c);
-    const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
-    double acc[BB];
-#pragma unroll
-    for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
-    lds_stencil<DIM, R, BB, T, FULL>(v, row, sx, slot, acc);
+    if (!own) return;
+    lds_stencil<DIM, R, BB, T, FULL>(v, orow, row, sx, slot, acc);
     if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * sx[slot];
 #pragma unroll
     for (int a = 0; a < BB; ++a) {
@@ -813,6 +847,20 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
     View<T> out = resolve<T>(d, outv, fam, l, BB);
     int o[3];
     tile_origin<DIM>(tile, v.n0, v.n1, o);
+    constexpr bool PRE = own_row_pre<DIM, R, BB, FULL>();
+    int c[3], slot;
+    const bool own = own_node<DIM, R>(v, o, c, &slot);
+    const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
+    const int64_t pn = own ? level_pad<DIM, R>(v, c) : 0;
+    OwnRow<DIM, R, BB, T, PRE> orow;
+    double acc[BB];
+#pragma unroll
+    for (int a = 0; a < BB; ++a) acc[a] = 0.0;
+    if (own) {
+        orow.load(v, row);
+#pragma unroll
+        for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
+    }
 #pragma unroll
     for (int jj = 0; jj < (Tl::NS + TPB - 1) / TPB; ++jj) {
         const int j = threadIdx.x + jj * TPB;
@@ -835,14 +883,9 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
         for (int a = 0; a < BB; ++a) sx[a * Tl::NS + j] = xk[a];
     }
     __syncthreads();
-    int c[3], slot;
-    if (!own_node<DIM, R>(v, o, c, &slot)) return;
-    const int64_t pn = level_pad<DIM, R>(v, c);
-    const int64_t row = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
-    double acc[BB], y[BB];
-#pragma unroll
-    for (int a = 0; a < BB; ++a) acc[a] = (double)rhs.at(pn, a);
-    lds_stencil<DIM, R, BB, T, FULL>(v, row, sx, slot, acc);
+    if (!own) return;
+    double y[BB];
+    lds_stencil<DIM, R, BB, T, FULL>(v, orow, row, sx, slot, acc);
     if (fam == 1 && l == 0) acc[0] -= fs_term(d, pn) * sx[slot];
     dinv_apply<BB>(v, row, acc, y);
 #pragma unroll
