@@ -334,7 +334,13 @@ __global__ void __launch_bounds__(TPB) k_mg_dinv(Batch B, int fam, int l) {
 
 // Galerkin coarse operator of level l+1 (2D): thread per (coarse row, stencil entry), looping
 // over the candidate pairs of the two coarse nodes
-template <int BB, typename T>
+// Galerkin operator P^T A P of level l+1, one thread per (coarse node, stencil slot blockIdx.y).
+// DENSE: every (i, j) candidate pair is visited with unconditional loads (a pair that leaves the
+// grid or the fine stencil gets weight zero and clamped indices), so all loads can be in flight
+// together: the form for small levels, whose launch is one dependent chain (2D level of 15 nodes:
+// 150 -> 33 us).  Otherwise invalid pairs are skipped: on large levels, where most of the 81 pairs
+// fall outside the fine stencil and occupancy hides the latency, that reads less.
+template <int DIM, int BB, typename T, bool DENSE>
 __global__ void __launch_bounds__(TPB) k_mg_rap(Batch B, int fam, int l) {
     PROB_PROLOGUE
     if (l + 1 >= d->nlev || (fam == 1 && l + 1 > d->ls_stop)) return;
@@ -342,67 +348,85 @@ __global__ void __launch_bounds__(TPB) k_mg_rap(Batch B, int fam, int l) {
     const MgLevel& C = d->lev[l + 1];
     if (tid >= C.nrow) return;
     const int s = blockIdx.y;
-    const int dim = d->dim, R = d->R, SW = 2 * R + 1;
-    int I[3], Jc[3] = {0, 0, 0}, off[3] = {s % SW - R, (s / SW) % SW - R, dim == 3 ? s / (SW * SW) - R : 0};
-    real_coords(tid, C.n, dim, I);
+    const int R = d->R, SW = 2 * R + 1;
+    int I[3], Jc[3] = {0, 0, 0}, off[3] = {s % SW - R, (s / SW) % SW - R, DIM == 3 ? s / (SW * SW) - R : 0};
+    real_coords(tid, C.n, DIM, I);
     bool valid = true;
-    for (int a = 0; a < dim; ++a) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
         Jc[a] = I[a] + off[a];
         if (Jc[a] < 0 || Jc[a] >= C.n[a]) valid = false;
     }
     double blk[BB * BB];
+#pragma unroll
     for (int k = 0; k < BB * BB; ++k) blk[k] = 0.0;
     if (valid) {
-        Op<T> o = op_of<T>(d, fam, l);
-        const int nI = dim == 3 ? 27 : 9;
-        for (int ii = 0; ii < nI; ++ii) {
-            int ki[3] = {ii % 3, (ii / 3) % 3, ii / 9};
+        const Op<T> o = op_of<T>(d, fam, l);
+        constexpr int nI = DIM == 3 ? 27 : 9;
+        // contributions of fine candidate ii of I paired with every candidate of J
+        auto row_i = [&](int ii) {
+            const int ki[3] = {ii % 3, (ii / 3) % 3, ii / 9};
             int fi[3] = {0, 0, 0};
             double wi = 1.0;
-            for (int a = 0; a < dim; ++a) {
-                fi[a] = cand(I[a], ki[a], F.cz[a]);
-                if (fi[a] < 0 || fi[a] >= F.n[a]) { wi = 0.0; break; }
-                wi *= pwa(fi[a], I[a], F.n[a], F.cz[a]);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const int f = cand(I[a], ki[a], F.cz[a]);
+                const bool ok = f >= 0 && f < F.n[a];
+                wi = ok ? wi * pwa(f, I[a], F.n[a], F.cz[a]) : 0.0;
+                fi[a] = ok ? f : 0;
             }
-            if (wi == 0.0) continue;
-            int64_t frow = fi[0] + (int64_t)F.n[0] * (fi[1] + (int64_t)F.n[1] * fi[2]);
-            int64_t fpn = padded(fi, F.np, R, dim);
-            for (int jj = 0; jj < nI; ++jj) {
-                int kj[3] = {jj % 3, (jj / 3) % 3, jj / 9};
+            if (!DENSE && wi == 0.0) return;
+            const int64_t frow = fi[0] + (int64_t)F.n[0] * (fi[1] + (int64_t)F.n[1] * fi[2]);
+            const int64_t fpn = padded(fi, F.np, R, DIM);
+            double mi[BB];
+#pragma unroll
+            for (int a = 0; a < BB; ++a) mi[a] = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
+            auto pair = [&](int jj) {
+                const int kj[3] = {jj % 3, (jj / 3) % 3, jj / 9};
                 int fj[3] = {0, 0, 0};
-                double wj = 1.0;
+                double w = wi;
                 int fs = 0, mul = 1;
-                for (int a = 0; a < dim; ++a) {
-                    fj[a] = cand(Jc[a], kj[a], F.cz[a]);
-                    if (fj[a] < 0 || fj[a] >= F.n[a]) { wj = 0.0; break; }
-                    int dd = fj[a] - fi[a];
-                    if (dd < -R || dd > R) { wj = 0.0; break; }
-                    wj *= pwa(fj[a], Jc[a], F.n[a], F.cz[a]);
-                    fs += (dd + R) * mul;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const int f = cand(Jc[a], kj[a], F.cz[a]);
+                    const int dd = f - fi[a];
+                    const bool ok = f >= 0 && f < F.n[a] && dd >= -R && dd <= R;
+                    w = ok ? w * pwa(f, Jc[a], F.n[a], F.cz[a]) : 0.0;
+                    fj[a] = ok ? f : fi[a];
+                    fs += ((ok ? dd : 0) + R) * mul;
                     mul *= SW;
                 }
-                if (wj == 0.0) continue;
-                int64_t fpnj = padded(fj, F.np, R, dim);
-                double w = wi * wj;
-                for (int a = 0; a < BB; ++a) {
-                    double mi = l == 0 ? mask0(d, fam, fpn, a) : 1.0;
-                    if (mi == 0.0) continue;
+                if (!DENSE && w == 0.0) return;
+                const int64_t fpnj = padded(fj, F.np, R, DIM);
+#pragma unroll
+                for (int a = 0; a < BB; ++a)
+#pragma unroll
                     for (int c = 0; c < BB; ++c) {
-                        double mj = l == 0 ? mask0(d, fam, fpnj, c) : 1.0;
-                        if (mj == 0.0) continue;
+                        const double m = l == 0 ? mi[a] * mask0(d, fam, fpnj, c) : 1.0;
                         double v = o.at(fs, a, c, frow);
                         if (fam == 1 && l == 0 && fs == (d->S - 1) / 2) v += fs_term(d, fpn);
-                        blk[a * BB + c] += w * v;
+                        blk[a * BB + c] += w * m * v;
                     }
-                }
+            };
+            if constexpr (DENSE) {
+#pragma unroll
+                for (int jj = 0; jj < nI; ++jj) pair(jj);
+            } else {
+                for (int jj = 0; jj < nI; ++jj) pair(jj);
             }
-        }
+        };
+        // (DENSE: the pairs of one fine candidate of I are issued together, candidate by
+        // candidate, which keeps a row's loads within the register budget)
+        for (int ii = 0; ii < nI; ++ii) row_i(ii);
         if (s == (d->S - 1) / 2)
+#pragma unroll
             for (int a = 0; a < BB; ++a)
                 if (blk[a * BB + a] == 0.0) blk[a * BB + a] = 1.0;
     }
     T* out = (T*)(fam == 0 ? C.A : C.Sm);
+#pragma unroll
     for (int a = 0; a < BB; ++a)
+#pragma unroll
         for (int c = 0; c < BB; ++c) out[((int64_t)(s * BB + a) * BB + c) * C.nrow + tid] = (T)blk[a * BB + c];
 }
 
@@ -460,6 +484,24 @@ __global__ void __launch_bounds__(TPB) k_mg_rap2(Batch B, int fam, int l) {
         const int64_t frow = fi[0] + (int64_t)fn[0] * (fi[1] + (int64_t)fn[1] * fi[2]);
         const int64_t fpn = padded(fi, F.np, d->R, DIM);
         if (l == 0 && mask0(d, fam, fpn, a) == 0.0) continue;
+        // the fine row's S entries (and, on level 0, the column masks) loaded together before the
+        // scatter: the stored row holds zeros in the slots that leave the grid, and a ghost
+        // column's mask is read inside the padded array
+        double vs[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) vs[s] = o.at(s, a, c, frow);
+        if (l == 0) {
+            if (fam == 1) vs[(S - 1) / 2] += fs_term(d, fpn);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int dl[3] = {s % SW - R, (s / SW) % SW - R, DIM == 3 ? s / (SW * SW) - R : 0};
+                int fj[3] = {0, 0, 0};
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) fj[ax] = fi[ax] + dl[ax];
+                vs[s] *= mask0(d, fam, padded(fj, F.np, d->R, DIM), c);
+            }
+        }
+#pragma unroll
         for (int s = 0; s < S; ++s) {
             const int dl[3] = {s % SW - R, (s / SW) % SW - R, DIM == 3 ? s / (SW * SW) - R : 0};
             int fj[3] = {0, 0, 0};
@@ -469,9 +511,7 @@ __global__ void __launch_bounds__(TPB) k_mg_rap2(Batch B, int fam, int l) {
                 if (fj[ax] < 0 || fj[ax] >= fn[ax]) jok = false;
             }
             if (!jok) continue;
-            double v = o.at(s, a, c, frow);
-            if (fam == 1 && l == 0 && s == (S - 1) / 2) v += fs_term(d, fpn);
-            if (l == 0) v *= mask0(d, fam, padded(fj, F.np, d->R, DIM), c);
+            double v = vs[s];
             if (v == 0.0) continue;
             v *= wi;
             int off[3][2], np[3] = {1, 1, 1};
@@ -1118,8 +1158,17 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, b
         if (l > 0) {
             Batch Bc = make_batch(g.ddev, level_rows(hc, l), TPB);
             if constexpr (DIM == 2) {
-                PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l - 1));
-                if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap<1, T>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
+                const std::vector<int64_t> rows = level_rows(hc, l);
+                if (*std::max_element(rows.begin(), rows.end()) > 4096)
+                    PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, DIM, T, false>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l - 1));
+                else
+                    PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, DIM, T, true>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l - 1));
+                if (l < LmaxS) {
+                    if (*std::max_element(rows.begin(), rows.end()) > 4096)
+                        hipLaunchKernelGGL((k_mg_rap<DIM, 1, T, false>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
+                    else
+                        hipLaunchKernelGGL((k_mg_rap<DIM, 1, T, true>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
+                }
             } else {
                 PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap2<DIM, R, DIM, T>), dim3(Bc.pfx[Bc.n], DIM * DIM), dim3(TPB), 0, st, Bc, 0, l - 1));
                 if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap2<DIM, R, 1, T>), dim3(Bc.pfx[Bc.n], 1), dim3(TPB), 0, st, Bc, 1, l - 1);
