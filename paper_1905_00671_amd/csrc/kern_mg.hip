@@ -1170,8 +1170,16 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, b
                         hipLaunchKernelGGL((k_mg_rap<DIM, 1, T, true>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
                 }
             } else {
-                PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap2<DIM, R, DIM, T>), dim3(Bc.pfx[Bc.n], DIM * DIM), dim3(TPB), 0, st, Bc, 0, l - 1));
-                if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap2<DIM, R, 1, T>), dim3(Bc.pfx[Bc.n], 1), dim3(TPB), 0, st, Bc, 1, l - 1);
+                // 3D: the LDS scatter on large levels; on small ones (a latency chain either way)
+                // the pair loop, which reaches its loads sooner
+                const std::vector<int64_t> rows = level_rows(hc, l);
+                if (*std::max_element(rows.begin(), rows.end()) > 4096) {
+                    PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap2<DIM, R, DIM, T>), dim3(Bc.pfx[Bc.n], DIM * DIM), dim3(TPB), 0, st, Bc, 0, l - 1));
+                    if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap2<DIM, R, 1, T>), dim3(Bc.pfx[Bc.n], 1), dim3(TPB), 0, st, Bc, 1, l - 1);
+                } else {
+                    PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap<DIM, DIM, T, false>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 0, l - 1));
+                    if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap<DIM, 1, T, true>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
+                }
             }
         }
         Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
