@@ -587,13 +587,25 @@ __global__ void __launch_bounds__(256) k_mg_coarse_setup(Batch B, int fam) {
             }
     }
     __syncthreads();
+    static_assert(CMAX <= 128, "one thread per column and half the rows below");
+    const int cc = threadIdx.x & 127, rh = threadIdx.x >> 7;
     for (int k = 0; k < n; ++k) {
-        if (threadIdx.x == 0) {
-            int best = k;
-            double bv = fabs(M[k][k]);
-            for (int r = k + 1; r < n; ++r)
-                if (fabs(M[r][k]) > bv) { bv = fabs(M[r][k]); best = r; }
-            piv = best;
+        if (threadIdx.x < 64) {
+            // partial pivoting: largest |M[r][k]|, r >= k (the lowest row on ties), found by the
+            // first wavefront with a shuffle reduction
+            int best = -1;
+            double bv = -1.0;
+            for (int r = k + (int)threadIdx.x; r < n; r += 64) {
+                const double v = fabs(M[r][k]);
+                if (v > bv) { bv = v; best = r; }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o);
+                const int ob = __shfl_xor(best, o);
+                if (ov > bv || (ov == bv && ob >= 0 && (best < 0 || ob < best))) { bv = ov; best = ob; }
+            }
+            if (threadIdx.x == 0) piv = best < 0 ? k : best;
         }
         __syncthreads();
         const int pr = piv;
@@ -606,16 +618,17 @@ __global__ void __launch_bounds__(256) k_mg_coarse_setup(Batch B, int fam) {
         __syncthreads();
         double pv = M[k][k];
         if (pv == 0.0 || !isfinite(pv)) pv = 1.0;
-        __syncthreads();
+        // row k scaled by 1/pv off the diagonal; the diagonal takes 1/pv after the barrier, during
+        // the elimination, which reads neither it nor column k of row k
         for (int c = threadIdx.x; c < n; c += blockDim.x)
             if (c != k) M[k][c] /= pv;
         __syncthreads();
         if (threadIdx.x == 0) M[k][k] = 1.0 / pv;
-        __syncthreads();
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            int r = e / n, c = e % n;
-            if (r == k || c == k) continue;
-            M[r][c] -= M[r][k] * M[k][c];
+        if (cc < n && cc != k) {
+            const double mkc = M[k][cc];
+#pragma unroll 8
+            for (int r = rh; r < n; r += 2)
+                if (r != k) M[r][cc] -= M[r][k] * mkc;
         }
         __syncthreads();
         for (int r = threadIdx.x; r < n; r += blockDim.x)
@@ -958,19 +971,24 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
     const int L0 = d->ltail, L = d->nlev, nsm = d->mg_nsm;
     const VRef LX{VK_LX, 0}, LR{VK_LR, 0}, LB{VK_LB, 0}, SOL{VK_SOL, 0};
     const int nt = blockDim.x;
-    // Warm this CU's L2 with the operators and inverse diagonals of the first two tail levels,
-    // which the smoothing passes would otherwise fetch from HBM one dependent round trip at a
-    // time: one dword per 128-byte line, all issued before the first restriction (offsets clamped
-    // into each array) and consumed after it.
+    // Warm this CU's L2 with the operators and inverse diagonals of the first two tail levels (or
+    // the dense coarsest inverse, when the second is the coarsest), which the passes below would
+    // otherwise fetch from HBM one dependent round trip at a time: one dword per 128-byte line,
+    // all issued before the first restriction (offsets clamped into each array) and consumed
+    // after it.
     constexpr int PF = 8;
     uint32_t pfv[4][PF];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int l = L0 + (m >> 1);
         const bool ok = l >= 1 && l < L - 1;   // level 0 is a view of the Jacobian
+        const bool dense = m == 2 && l == L - 1;
         const MgLevel& Q = d->lev[ok ? l : L0];
-        const void* p = (m & 1) ? (fam == 0 ? Q.Ad : Q.Sd) : (fam == 0 ? Q.A : Q.Sm);
-        const int64_t words = ok ? ((m & 1) ? Q.nrow : Q.nrow * d->S) * BB * BB * (int64_t)sizeof(T) / 4 : 0;
+        const int64_t nc = d->lev[L - 1].nrow * BB;
+        const void* p = dense ? (fam == 0 ? d->cinvA : d->cinvS)
+                              : (m & 1) ? (fam == 0 ? Q.Ad : Q.Sd) : (fam == 0 ? Q.A : Q.Sm);
+        const int64_t words = ok ? ((m & 1) ? Q.nrow : Q.nrow * d->S) * BB * BB * (int64_t)sizeof(T) / 4
+                                 : dense && nc <= CMAX ? nc * nc * (int64_t)sizeof(T) / 4 : 0;
         const uint32_t* base = words > 0 ? (const uint32_t*)p : (const uint32_t*)d->scal;
         const int64_t last = words > 0 ? words - 1 : 0;
 #pragma unroll

@@ -10,7 +10,7 @@ namespace ppm {
 constexpr int MAXB = 64;      // problems per batched launch
 constexpr int TPB = 256;      // threads per block of the streaming kernels
 constexpr int MAXLEV = 12;    // multigrid levels
-constexpr int CMAX = 81;      // largest coarsest-level system solved by a dense inverse (LDS)
+constexpr int CMAX = 112;     // largest coarsest-level system solved by a dense inverse (LDS, 101 KB)
 constexpr int TAILMAX = 200;  // levels with at most this many nodes run inside one fused kernel
 // node tiles of the gather kernels (one block of TPB threads per tile)
 constexpr int TILE2X = 16, TILE2Y = 16;
