@@ -294,6 +294,17 @@ double stab_tau(const ppmpm_options* o, double lam, double G, double kappa, doub
 // ends there (level 0: no coarse levels at all; V(1,1) only; ltail or more means the full
 // hierarchy).  On the 2D footing (Fo_0 = 0.86) ending at level 0 took fewer Krylov iterations
 // than one more level with its coarse correction (240 vs 260 over six steps).
+// Damping of the block-Jacobi smoother, below 4 / (3 lambda_max(D^-1 A)) (lambda_max near 2 for
+// the 2D stencils, 3.2 for the 27-point trilinear one), chosen by Krylov counts: 2D GIMP footing
+// 0.5 / 0.55 / 0.6 / 0.7 / 0.8 took 226 / 212 / 207 / 240 / (no convergence) FP64 iterations over
+// six steps; the serving stream (small grids, half of them original-MPM consolidation) took more
+// iterations with 0.6 everywhere than with 0.7 (351k vs 340k; 347k with this rule), hence 0.7
+// for the 9-point stencil; 3D 0.4 / 0.45 / 0.5 took 172 / 164 / 165 over three steps.
+double smoother_damping(const Dev& h) {
+    if (h.dim == 3) return 0.5;
+    return h.R == 2 ? 0.6 : 0.7;
+}
+
 int schur_truncation(const Dev& h) {
     if (h.mg_nsm != 1) return MAXLEV;
     const double kK = h.kappa * h.Kfs / h.ct;
@@ -383,9 +394,7 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
         h.hc2 = o->dynamic ? (1.0 - 0.5 * o->gamma / o->beta) * t : 0.0;
         h.tau = stab_tau(o, h.lam, h.G, h.kappa, h.h, t);
         h.Kfs = h.lam + 2.0 * h.G / h.dim;
-        // damping of the block-Jacobi smoother, about 4 / (3 lambda_max(D^-1 A)): lambda_max is near
-        // 2 for the 2D stencils and near 3.2 for the 27-point trilinear one
-        h.omega = h.dim == 3 ? 0.5 : 0.7;
+        h.omega = smoother_damping(h);
         h.mg_nsm = std::max(1, o->mg_smooth);
         h.ls_stop = schur_truncation(h);
         ppmpm_status s = upload_desc(p);
@@ -477,7 +486,7 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     h.dt = 1.0;
     h.beta = opt->beta;
     h.gamma = opt->gamma;
-    h.omega = h.dim == 3 ? 0.5 : 0.7;
+    h.omega = smoother_damping(h);
     h.mg_nsm = std::max(1, opt->mg_smooth);
     h.ls_stop = MAXLEV;
     {
