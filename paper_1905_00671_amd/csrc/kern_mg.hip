@@ -882,7 +882,9 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
     }
 }
 
-template <int DIM, int R, int BB, typename T, bool FULL>
+// ZERO: the iterate is omega Dinv rhs, formed here (a Schur cycle that ends on level 0 is two
+// Jacobi sweeps from zero, one launch instead of the level's down and up kernels).
+template <int DIM, int R, int BB, typename T, bool FULL, bool ZERO = false>
 __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FULL ? 2 : 8))) k_mg_up(Batch B, int fam, int l, VRef rhsv, VRef outv) {
     using Tl = Tile<DIM, R>;
     const int q = batch_find(B, blockIdx.x);
@@ -924,13 +926,24 @@ __global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FUL
         for (int a = 0; a < BB; ++a) xk[a] = 0.0;
         if (slot_node<DIM, R>(v, o, j, c)) {
             const int64_t pn = level_pad<DIM, R>(v, c);
-            double pc[BB];
+            if constexpr (ZERO) {
+                // as the down sweep forms (and stores in precision T) its first iterate
+                double bk[BB];
 #pragma unroll
-            for (int a = 0; a < BB; ++a) pc[a] = 0.0;
-            if (coarse) prolong_node<DIM, R, BB, T>(d, fam, l, c, pn, xc, pc);
-            // the iterate is stored in precision T after the prolongation
+                for (int a = 0; a < BB; ++a) bk[a] = (double)rhs.at(pn, a);
+                const int64_t srow = c[0] + (int64_t)v.n0 * (c[1] + (int64_t)v.n1 * c[2]);
+                dinv_apply<BB>(v, srow, bk, xk);
 #pragma unroll
-            for (int a = 0; a < BB; ++a) xk[a] = (double)(T)((double)x.at(pn, a) + pc[a]);
+                for (int a = 0; a < BB; ++a) xk[a] = (double)(T)(d->omega * xk[a]);
+            } else {
+                double pc[BB];
+#pragma unroll
+                for (int a = 0; a < BB; ++a) pc[a] = 0.0;
+                if (coarse) prolong_node<DIM, R, BB, T>(d, fam, l, c, pn, xc, pc);
+                // the iterate is stored in precision T after the prolongation
+#pragma unroll
+                for (int a = 0; a < BB; ++a) xk[a] = (double)(T)((double)x.at(pn, a) + pc[a]);
+            }
         }
 #pragma unroll
         for (int a = 0; a < BB; ++a) sx[a * Tl::NS + j] = xk[a];
@@ -1290,6 +1303,17 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
     }
     const VRef LR{VK_LR, 0}, LB{VK_LB, 0}, LX{VK_LX, 0};
     const dim3 tb(TPB);
+    if (fam == 1 && nsm == 1) {
+        bool level0 = true;
+        for (auto* h : hc) level0 = level0 && h->ls_stop == 0;
+        if (level0) {
+            Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, 0));
+            PPM_TIMED(KT_MG0_RESID, st,
+                      hipLaunchKernelGGL((k_mg_up<DIM, R, BB, T, false, true>), dim3(Bt.pfx[Bt.n]), tb, 0, st, Bt, fam, 0,
+                                         rhs0, out0));
+            return;
+        }
+    }
     if (nsm == 1) {
         for (int l = 0; l < Lstd; ++l) {
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
