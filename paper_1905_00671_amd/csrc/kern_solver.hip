@@ -153,41 +153,63 @@ __global__ void __launch_bounds__(TPB) k_bicg_p(Batch B) {
     for (int a = 0; a < BS; ++a) p[k0 + a] = rv[a] + beta * (pv[a] - om * vv[a]);
 }
 
-// s = r - alpha v; partial (s, s)
+// alpha = rho / (rhat, v) from the SpMV's partials (each block reduces them itself, in the
+// order of the scalar kernel, so all blocks agree; block 0 records alpha), then s = r - alpha v.
+// A zero or non-finite (rhat, v) is a breakdown: the problem is marked done.
 template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_s(Batch B) {
     PROB_PROLOGUE
-    double v[1] = {0.0};
-    if (!krylov_done(d) && tid < d->Nnode) {
-        const int64_t k0 = node_pad<T>(d, tid) * BS;
-        const T al = (T)d->scal[SC_ALPHA];
-        const T* __restrict__ r = vp<T>(d->kr);
-        const T* __restrict__ vv = vp<T>(d->kv);
-        T* __restrict__ sp = vp<T>(d->ks);
-        T rv[BS], w[BS];
-#pragma unroll
-        for (int a = 0; a < BS; ++a) {
-            rv[a] = r[k0 + a];
-            w[a] = vv[k0 + a];
-        }
-#pragma unroll
-        for (int a = 0; a < BS; ++a) {
-            const T sv = rv[a] - al * w[a];
-            sp[k0 + a] = sv;
-            v[0] += (double)sv * (double)sv;
+    if (krylov_done(d)) return;
+    double s0, s1;
+    sum_partials(d, spmv_blocks(d->dim, d->Nnode, !d->mixed), &s0, &s1);
+    (void)s1;
+    const bool brk = s0 == 0.0 || !isfinite(s0);
+    const double alpha = brk ? 0.0 : d->scal[SC_RHO] / s0;
+    if (lb == 0 && threadIdx.x == 0) {
+        d->scal[SC_RV] = s0;
+        if (brk) {
+            d->scal[SC_BREAK] = 1.0;
+            d->scal[SC_DONE] = 1.0;
+        } else {
+            d->scal[SC_ALPHA] = alpha;
         }
     }
-    block_partials<1>(d, lb, v);
+    if (brk || tid >= d->Nnode) return;
+    const int64_t k0 = node_pad<T>(d, tid) * BS;
+    const T al = (T)alpha;
+    const T* __restrict__ r = vp<T>(d->kr);
+    const T* __restrict__ vv = vp<T>(d->kv);
+    T* __restrict__ sp = vp<T>(d->ks);
+    T rv[BS], w[BS];
+#pragma unroll
+    for (int a = 0; a < BS; ++a) {
+        rv[a] = r[k0 + a];
+        w[a] = vv[k0 + a];
+    }
+#pragma unroll
+    for (int a = 0; a < BS; ++a) sp[k0 + a] = rv[a] - al * w[a];
 }
 
-// x += alpha ph + omega sh; r = s - omega t; partials (rhat, r), (r, r)
+// omega = (t, s) / (t, t) from the SpMV's partials (reduced by every block, as in k_bicg_s;
+// t = 0 means s is already the exact residual of x + alpha ph: omega = 0), then
+// x += alpha ph + omega sh; r = s - omega t; partials (rhat, r), (r, r) in slots 2 and 3 (slots
+// 0 and 1 hold the SpMV's, which other blocks may still be reading).
 template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_xr(Batch B) {
     PROB_PROLOGUE
+    if (krylov_done(d)) return;
+    double ts, tt;
+    sum_partials(d, spmv_blocks(d->dim, d->Nnode, !d->mixed), &ts, &tt);
+    const double omega = (tt == 0.0 || !isfinite(tt)) ? 0.0 : ts / tt;
+    if (lb == 0 && threadIdx.x == 0) {
+        d->scal[SC_TS] = ts;
+        d->scal[SC_TT] = tt;
+        d->scal[SC_OMEGA] = omega;
+    }
     double v[2] = {0.0, 0.0};
-    if (!krylov_done(d) && tid < d->Nnode) {
+    if (tid < d->Nnode) {
         const int64_t k0 = node_pad<T>(d, tid) * BS;
-        const T al = (T)d->scal[SC_ALPHA], om = (T)d->scal[SC_OMEGA];
+        const T al = (T)d->scal[SC_ALPHA], om = (T)omega;
         T* __restrict__ x = vp<T>(d->kx);
         T* __restrict__ r = vp<T>(d->kr);
         const T* __restrict__ ph = vp<T>(d->kph);
@@ -214,25 +236,24 @@ __global__ void __launch_bounds__(TPB) k_bicg_xr(Batch B) {
             v[1] += (double)rr * (double)rr;
         }
     }
-    block_partials<2>(d, lb, v);
+    block_partials<2>(d, lb, v, 2);
 }
 
 // scalar updates, one block per problem; stage:
-//   0 after init: rho = (r,r), tol2, alpha = omega = 1, beta = 0
-//   1 after v = J ph: alpha = rho / (rhat, v)
-//   2 after t = J sh: omega = (t, s) / (t, t)
-//   3 after x, r: beta, rho, convergence
+//   0 after init: rho = (r,r), tol2, alpha = omega = 1, beta = 0   (partials in slot 0)
+//   3 after x, r: beta, rho, convergence                           (partials in slots 2, 3)
+// (alpha and omega are formed by k_bicg_s and k_bicg_xr from the SpMV partials)
 __global__ void k_bicg_scalars(Batch B, int stage, double rtol, int maxit) {
     const int q = blockIdx.x;
     const Dev* d = B.d[q];
     if (stage != 0 && krylov_done(d)) return;
     __shared__ double sh[2][TPB];
-    // stages 1 and 2 follow an SpMV (its own block shape), 0 and 3 a node-per-thread kernel
-    const int64_t nblk = (stage == 1 || stage == 2) ? spmv_blocks(d->dim, d->Nnode, !d->mixed) : (d->Nnode + TPB - 1) / TPB;
+    const int64_t nblk = (d->Nnode + TPB - 1) / TPB;
+    const int slot = stage == 3 ? 2 : 0;
     double a = 0.0, b2 = 0.0;
     for (int64_t i = threadIdx.x; i < nblk; i += TPB) {
-        a += d->partial[i * 4 + 0];
-        b2 += d->partial[i * 4 + 1];
+        a += d->partial[i * 4 + slot];
+        b2 += d->partial[i * 4 + slot + 1];
     }
     sh[0][threadIdx.x] = a;
     sh[1][threadIdx.x] = b2;
@@ -257,19 +278,6 @@ __global__ void k_bicg_scalars(Batch B, int stage, double rtol, int maxit) {
         sc[SC_ITER] = 0.0;
         sc[SC_BREAK] = 0.0;
         sc[SC_DONE] = (s0 == 0.0 || maxit <= 0) ? 1.0 : 0.0;
-    } else if (stage == 1) {
-        sc[SC_RV] = s0;
-        if (s0 == 0.0 || !isfinite(s0)) { sc[SC_BREAK] = 1.0; sc[SC_DONE] = 1.0; return; }
-        sc[SC_ALPHA] = sc[SC_RHO] / s0;
-    } else if (stage == 2) {
-        sc[SC_TS] = s0;
-        sc[SC_TT] = s1;
-        if (s1 == 0.0 || !isfinite(s1)) {
-            // t = 0: s is already the exact residual of x + alpha ph; take omega = 0
-            sc[SC_OMEGA] = 0.0;
-            return;
-        }
-        sc[SC_OMEGA] = s0 / s1;
     } else {
         double rho_new = s0;
         sc[SC_RR] = s1;
@@ -317,11 +325,9 @@ static void krylov_iters_t(const Group& g, const std::vector<const Dev*>& hc, in
         hipLaunchKernelGGL((k_bicg_p<DIM + 1, T>), gN, tb, 0, st, Bn);
         launch_precond_apply(g, hc, 3, 7, st);
         PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gS, tb, 0, st, Bs, 7, 4, 2, 1, 1));
-        hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 1, rtol, maxit);
         hipLaunchKernelGGL((k_bicg_s<DIM + 1, T>), gN, tb, 0, st, Bn);
         launch_precond_apply(g, hc, 5, 8, st);
         PPM_TIMED(KT_SPMV, st, hipLaunchKernelGGL((k_spmv<DIM, R, T>), gS, tb, 0, st, Bs, 8, 6, 5, 2, 1));
-        hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 2, rtol, maxit);
         hipLaunchKernelGGL((k_bicg_xr<DIM + 1, T>), gN, tb, 0, st, Bn);
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 3, rtol, maxit);
     }

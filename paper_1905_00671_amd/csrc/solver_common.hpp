@@ -29,9 +29,9 @@ __device__ __forceinline__ int64_t stencil_offset(int s, int R, int dim, const i
     return (int64_t)dx + (int64_t)np[0] * (dy + (int64_t)np[1] * dz);
 }
 
-// block reduction of NV values into partial[lb*4 + k] (fixed tree order: deterministic)
+// block reduction of NV values into partial[lb*4 + slot + k] (fixed tree order: deterministic)
 template <int NV>
-__device__ __forceinline__ void block_partials(const Dev* d, int64_t lb, const double* v) {
+__device__ __forceinline__ void block_partials(const Dev* d, int64_t lb, const double* v, int slot = 0) {
     __shared__ double sh[NV][TPB];
     for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] = v[k];
     __syncthreads();
@@ -41,7 +41,32 @@ __device__ __forceinline__ void block_partials(const Dev* d, int64_t lb, const d
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < NV; ++k) d->partial[lb * 4 + k] = sh[k][0];
+        for (int k = 0; k < NV; ++k) d->partial[lb * 4 + slot + k] = sh[k][0];
+}
+
+// Sum over nblk blocks of partial[i*4 + k], k < 2, returned to every thread of the block: thread t
+// adds blocks t, t + TPB, ..., then a fixed tree, so every block (and the one-block scalar kernel)
+// gets the same bits.  Ends with a barrier; the block's threads must all call it.
+__device__ __forceinline__ void sum_partials(const Dev* d, int64_t nblk, double* s0, double* s1) {
+    __shared__ double sh[2][TPB];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < nblk; i += TPB) {
+        a += d->partial[i * 4 + 0];
+        b += d->partial[i * 4 + 1];
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + off];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    *s0 = sh[0][0];
+    *s1 = sh[1][0];
+    __syncthreads();
 }
 
 __device__ __forceinline__ bool krylov_done(const Dev* d) { return d->scal[SC_DONE] != 0.0; }
