@@ -1116,31 +1116,53 @@ __global__ void __launch_bounds__(TAIL_TPB) k_mg_tail(Batch B, int fam, VRef rhs
 }
 
 // t_u = y_u - B1 z_p on level 0 (B1 = displacement rows, pressure columns of J)
+// Block count of the coupling product: 2D FP64 one wavefront per (component a, run of 64
+// nodes), as the SpMV (16.2 -> 14.6 us on the 2D footing); otherwise one thread per node with all
+// components (the split measured slower in 3D: 142 -> 160 us).
+inline int64_t b1_blocks(int dim, int64_t nnode, bool fp64) {
+    if (!fp64 || dim == 3) return (nnode + TPB - 1) / TPB;
+    return ((nnode + 63) / 64 * dim + 3) / 4;
+}
+
+// t = y_u - B1 z_p (rhs of the displacement cycle)
 template <int DIM, int R, typename T>
 __global__ void __launch_bounds__(TPB) k_b1(Batch B, VRef yv, VRef zv) {
     PROB_PROLOGUE
-    if (krylov_done(d) || tid >= d->Nnode) return;
+    constexpr bool SPLIT = sizeof(T) == 8 && DIM == 2;
+    constexpr int NA = SPLIT ? 1 : DIM;   // components per thread
+    int a0 = 0;
+    int64_t row = tid;
+    if (SPLIT) {
+        const int64_t W = lb * (TPB / 64) + threadIdx.x / 64;
+        a0 = (int)(W % DIM);
+        row = (W / DIM) * 64 + (threadIdx.x & 63);
+    }
+    if (krylov_done(d) || row >= d->Nnode) return;
     using St = Sten<DIM, R>;
     View<T> y = resolve<T>(d, yv, 0, 0, DIM), z = resolve<T>(d, zv, 0, 0, 1);
     View<T> t = resolve<T>(d, VRef{VK_BT, 0}, 0, 0, DIM);
     constexpr int bs = DIM + 1;
     int c[3];
-    real_coords(tid, d->nn, DIM, c);
+    real_coords(row, d->nn, DIM, c);
     const int64_t pn = padded(c, d->np1, R, DIM);
     const int np0 = d->np1[0], np1 = d->np1[1];
     const T* J = (const T*)d->J;
-    double acc[DIM];
+    double acc[NA];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) acc[a] = (double)y.at(pn, a);
+    for (int i = 0; i < NA; ++i) acc[i] = (double)y.at(pn, a0 + i);
 #pragma unroll
     for (int s = 0; s < St::S; ++s) {
         const int64_t pk = pn + St::ox(s) + (int64_t)np0 * (St::oy(s) + (int64_t)np1 * St::oz(s));
         const double zp = (double)z.at(pk, 0);
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) acc[a] -= (double)J[jidx<DIM>((s * bs + a) * bs + DIM, tid, St::S * bs * bs, d->Nnode)] * zp;
+        for (int i = 0; i < NA; ++i) {
+            const T* jp = &J[jidx<DIM>((s * bs + a0 + i) * bs + DIM, row, St::S * bs * bs, d->Nnode)];
+            // 3D: streamed from HBM as in the SpMV
+            acc[i] -= (double)(DIM == 3 ? __builtin_nontemporal_load(jp) : *jp) * zp;
+        }
     }
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) t.at(pn, a) = (T)acc[a];
+    for (int i = 0; i < NA; ++i) t.at(pn, a0 + i) = (T)acc[i];
 }
 // ---------------------------------------------------------------------------------------------
 // host side
@@ -1361,7 +1383,9 @@ template <int DIM, int R, typename T>
 static void precond_apply_t(const Group& g, const std::vector<const Dev*>& hc, int iy, int iz, hipStream_t st) {
     const int nsm = hc[0]->mg_nsm;
     vcycle<DIM, R, 1, T>(g, hc, 1, VRef{iy, DIM}, VRef{iz, DIM}, nsm, st);
-    Batch Bn = make_batch(g.ddev, g.nnode, TPB);
+    std::vector<int64_t> nb;
+    for (size_t q = 0; q < g.nnode.size(); ++q) nb.push_back(b1_blocks(DIM, g.nnode[q], sizeof(T) == 8));
+    Batch Bn = make_batch_blocks(g.ddev, nb);
     hipLaunchKernelGGL((k_b1<DIM, R, T>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn, VRef{iy, 0}, VRef{iz, DIM});
     vcycle<DIM, R, DIM, T>(g, hc, 0, VRef{VK_BT, 0}, VRef{iz, 0}, nsm, st);
 }
