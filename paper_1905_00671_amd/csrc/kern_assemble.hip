@@ -4,9 +4,9 @@
 //   k_records   one thread per (sorted) material point: basis at x_n, relative deformation
 //               dF = 1 + sum U (x) grad_n S, stress, tangent and every per-point coefficient the
 //               residual and the Jacobian need (the point's "quadrature record", see RecRef);
-//   k_residual  one thread per grid node (blocks cover 16x16 / 8x8x4 node tiles): gathers R_i
-//               from the points whose basis reaches node i (no atomics, fixed summation order),
-//               applies the boundary conditions and writes per-block partial norms;
+//   k_residual  blocks of 64-node tiles (16x4 / 8x8x1), four wavefronts per tile each gathering a
+//               quarter of the basis-window buckets: R_i from the points whose basis reaches node i
+//               (no atomics, fixed summation order), boundary conditions, per-block partial norms;
 //   k_jacobian  one thread per (grid node i, row component, column component), the component
 //               pair uniform per block: for each point reaching node i, the entries of all its
 //               column blocks J_ik come from one set of record loads; the node's fixed-stencil
@@ -259,10 +259,11 @@ __device__ __forceinline__ bool bucket_of(const Dev* d, const int* n, int64_t* c
 
 // Residual contributions to node n of the points of bucket n - l (LI = window index of n).
 template <int DIM, int SHAPE, int LI>
-__device__ __forceinline__ void res_bucket(const Dev* __restrict__ d, const int* n, double* r) {
+__device__ __forceinline__ void res_bucket(const Dev* __restrict__ d, const int* n, double* r, int part) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int NN = DIM == 2 ? WB * WB : WB * WB * WB;
     if constexpr (LI < NN) {
+      if (LI * RES_PARTS / NN == part) {
         constexpr int li[3] = {LI % WB, (LI / WB) % WB, DIM == 3 ? LI / (WB * WB) : 0};
         using L = RecLayout<DIM, WB>;
         int64_t cid;
@@ -308,27 +309,41 @@ __device__ __forceinline__ void res_bucket(const Dev* __restrict__ d, const int*
             for (int a = 0; a < DIM; ++a) gw += gS[a] * rc[L::QW_ + a];
             r[DIM] += Sv * rc[L::DT_] + rc[L::DK_] * gw + rc[L::ST_] * (Sv - Pi);
         }
-        res_bucket<DIM, SHAPE, LI + 1>(d, n, r);
+      }
+        res_bucket<DIM, SHAPE, LI + 1>(d, n, r, part);
     }
 }
 
+// One block per tile of RES_NODES grid nodes, RES_PARTS wavefronts per tile: wavefront j gathers
+// the buckets LI with LI * RES_PARTS / NN = j for all nodes of the tile (the gather is latency-bound;
+// four times as many wavefronts, each walking a quarter of a node's points), then the parts are
+// added in LDS in a fixed order and the first wavefront finishes its nodes.
 template <int DIM, int SHAPE>
 __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
+    static_assert(RES_NODES * RES_PARTS == TPB, "one wavefront per part");
     const int q = batch_find(B, blockIdx.x);
     const Dev* __restrict__ d = B.d[q];
     const int64_t lb = blockIdx.x - B.pfx[q];
     const int bs = DIM + 1;
+    const int part = threadIdx.x / RES_NODES, ln = threadIdx.x % RES_NODES;
+    __shared__ double sr[RES_PARTS][DIM + 1][RES_NODES];
     double ru2 = 0.0, rp2 = 0.0;
     bool bad = false;
     int n[3];
     int64_t row;
-    if (tile_node<DIM>(d, lb, threadIdx.x, n, &row)) {
+    const bool in = tile_node<DIM>(d, lb, ln, n, &row);
+    double r[DIM + 1];
+    for (int c = 0; c <= DIM; ++c) r[c] = 0.0;
+    if (in) res_bucket<DIM, SHAPE, 0>(d, n, r, part);
+    for (int c = 0; c <= DIM; ++c) sr[part][c][ln] = r[c];
+    __syncthreads();
+    if (part == 0 && in) {
         const int64_t pn = pad_index(d, n[0], n[1], n[2]);
-        double r[DIM + 1];
-        for (int c = 0; c <= DIM; ++c) r[c] = 0.0;
-        res_bucket<DIM, SHAPE, 0>(d, n, r);
         for (int c = 0; c <= DIM; ++c) {
-            double v = r[c] + d->fext[pn * bs + c];
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < RES_PARTS; ++j) v += sr[j][c][ln];
+            v += d->fext[pn * bs + c];
             if (!d->dfree[pn * bs + c]) v = 0.0;
             if (!isfinite(v)) bad = true;
             d->Rv[pn * bs + c] = v;

@@ -12,9 +12,10 @@ constexpr int TPB = 256;      // threads per block of the streaming kernels
 constexpr int MAXLEV = 12;    // multigrid levels
 constexpr int CMAX = 112;     // largest coarsest-level system solved by a dense inverse (LDS, 101 KB)
 constexpr int TAILMAX = 200;  // levels with at most this many nodes run inside one fused kernel
-// node tiles of the gather kernels (one block of TPB threads per tile)
-constexpr int TILE2X = 16, TILE2Y = 16;
-constexpr int TILE3X = 8, TILE3Y = 8, TILE3Z = 4;
+// node tiles of the residual gather (RES_NODES nodes, one block of RES_PARTS wavefronts per tile)
+constexpr int TILE2X = 16, TILE2Y = 4;
+constexpr int TILE3X = 8, TILE3Y = 8, TILE3Z = 1;
+constexpr int RES_NODES = 64, RES_PARTS = 4;  // residual gather: nodes per tile, wavefronts per node set
 // node tiles of the multigrid sweeps: long in x, so that a wavefront reads every operator stream
 // in runs of 256-512 contiguous bytes
 constexpr int MGT2X = 64, MGT2Y = 4;
