@@ -113,29 +113,45 @@ __global__ void k_sort_keys(Batch B) {
     d->slot[tid] = atomicAdd(&d->ccount[cid], 1);
 }
 
-// Exclusive scan of the cell counts: one 1024-thread block per problem, chunked.
+// Exclusive scan of the cell counts: one 1024-thread block per problem over chunks of 4096
+// counts, four consecutive counts per thread, a shuffle scan per wavefront and one over the
+// sixteen wavefront totals (two barriers per chunk).
 __global__ void __launch_bounds__(1024) k_scan_cells(Batch B) {
     const int q = blockIdx.x;
     const Dev* d = B.d[q];
-    __shared__ int buf[1024];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
+    constexpr int NW = 1024 / 64;
+    __shared__ int wsum[NW];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = d->Ncell;
-    for (int64_t base = 0; base < n; base += 1024) {
-        int64_t i = base + threadIdx.x;
-        int v = i < n ? d->ccount[i] : 0;
-        buf[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            int t = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
-            __syncthreads();
-            buf[threadIdx.x] += t;
-            __syncthreads();
+    int carry = 0;   // same value in every thread
+    for (int64_t base = 0; base < n; base += 4096) {
+        const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
+        int v[4], incl[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = i0 + k < n ? d->ccount[i0 + k] : 0;
+        incl[0] = v[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) incl[k] = incl[k - 1] + v[k];
+        int x = incl[3];   // inclusive scan of the thread totals within the wavefront
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(x, off);
+            if (lane >= off) x += t;
         }
-        if (i < n) d->cstart[i] = carry + buf[threadIdx.x] - v;
+        if (lane == 63) wsum[wid] = x;
         __syncthreads();
-        if (threadIdx.x == 1023) carry += buf[1023];
+        int wpre = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int ws = wsum[w];
+            wpre += w < wid ? ws : 0;
+            total += ws;
+        }
+        const int before = carry + wpre + (x - incl[3]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k < n) d->cstart[i0 + k] = before + incl[k] - v[k];
+        carry += total;
         __syncthreads();
     }
     if (threadIdx.x == 0) d->cstart[n] = carry;
