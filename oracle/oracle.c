@@ -35,7 +35,12 @@ typedef struct {
     double kappa;    /* mobility k / mu_f (Darcy law, Sec. 2.2) */
     double rho_f;
     double g[3];
+    double phi0;     /* initial porosity of the Kozeny-Carman law (Sec. 2.2); <= 0: kappa constant */
 } or_mat;
+
+/* Porosity below which the Kozeny-Carman mobility is held constant (the law degenerates at
+ * phi = 0, where the grains alone would fill the volume). */
+#define OR_PHI_MIN 1e-4
 
 typedef struct {
     int shape;       /* 0 original MPM, 1 GIMP */
@@ -377,10 +382,32 @@ typedef struct {
     const double* qe;   /* [ncell*2^dim] original-MPM projection: cell moments */
 } or_nodal;
 
+/* Mobility kappa(J) = kappa0 k(phi)/k0 of the Kozeny-Carman law (Sec. 2.2, eq. kozeny-carman),
+ * with the porosity of a skeleton of incompressible grains, phi = 1 - (1 - phi0)/J, J the volume
+ * ratio to the initial configuration.  *dk = d kappa / d J by the chain rule through phi (zero
+ * where phi is held at OR_PHI_MIN).  phi0 <= 0 gives the constant mobility kappa0. */
+void or_mobility(double kappa0, double phi0, double J, double* k, double* dk) {
+    if (!(phi0 > 0.0)) {
+        *k = kappa0;
+        *dk = 0.0;
+        return;
+    }
+    double phi = 1.0 - (1.0 - phi0) / J;
+    int held = phi < OR_PHI_MIN;
+    if (held) phi = OR_PHI_MIN;
+    double c0 = (1.0 - phi0) * (1.0 - phi0) / (phi0 * phi0 * phi0);
+    double q = 1.0 - phi;
+    *k = kappa0 * c0 * phi * phi * phi / (q * q);
+    /* dk/dphi = kappa0 c0 [3 phi^2 / q^2 + 2 phi^3 / q^3],  dphi/dJ = (1 - phi0) / J^2 */
+    double dk_dphi = kappa0 * c0 * (3.0 * phi * phi / (q * q) + 2.0 * phi * phi * phi / (q * q * q));
+    *dk = held ? 0.0 : dk_dphi * (1.0 - phi0) / (J * J);
+}
+
 /* Local residual r[nn*(d+1)] and local Jacobian Jl[(nn*(d+1))^2] (row-major, may be NULL) of
  * one material point.  Terms (Sec. 3.1-3.4, 4.2):
  *   R_mom_i  = -(V_n/J_n) tau' gradS_i + dv p^h gradS_i + m S_i (g - a^h)          (eq. residual-momentum)
  *   R_mass_i = dv S_i theta + dv kappa gradS_i . (grad p^h - rho_f (g - a^h))      (eq. residual-mass, darcy-law)
+ *              with kappa = kappa(J), J = det(dF) det(F_n), when phi0 > 0 (eq. kozeny-carman)
  *              + tau V_n (S_i - Pi_i) sum_j (S_j - Pi_j) pdot_j                    (eq. stab-term-ppp)
  * with dF = 1 + sum U (x) grad_n S, dv = det(dF) V_n, gradS = dF^{-T} grad_n S (Sec. 3.3),
  * theta = ln(dJ)/dt (eq. implicit-euler) or div v^h with Newmark v (eq. newmark),
@@ -414,6 +441,8 @@ int or_particle(const or_grid* g, const or_mat* mt, const or_opt* op, const doub
     or_kirchhoff(mt->model, mt->lam, mt->G, d, F, tau);
     double Jn = det_n(d, Fn);
     double V0 = Vn / Jn, dv = dJ * Vn;
+    double Jt = dJ * Jn, kap, dkap;
+    or_mobility(mt->kappa, mt->phi0, Jt, &kap, &dkap);
     double gS[OR_MAXN * 3];
     for (int k = 0; k < nn; k++)
         for (int a = 0; a < d; a++) {
@@ -470,7 +499,7 @@ int or_particle(const or_grid* g, const or_mat* mt, const or_opt* op, const doub
         }
         double dw = 0;
         for (int a = 0; a < d; a++) dw += gS[k * d + a] * w[a];
-        r[k * nd1 + d] = dv * S[k] * theta + dv * mt->kappa * dw + op->tau * Vn * (S[k] - Pi[k]) * pstab;
+        r[k * nd1 + d] = dv * S[k] * theta + dv * kap * dw + op->tau * Vn * (S[k] - Pi[k]) * pstab;
     }
     if (!Jl) return nn;
     /* Jacobian: one column at a time */
@@ -515,7 +544,9 @@ int or_particle(const or_grid* g, const or_mat* mt, const or_opt* op, const doub
                     dgw += dgS[a] * w[a];
                     gdw += gS[k * d + a] * dw[a];
                 }
-                double v = ddv * S[k] * theta + dv * S[k] * dth + mt->kappa * (ddv * gw + dv * dgw + dv * gdw);
+                /* d(J)/dU = J trL, so d(kappa)/dU = dkap J trL */
+                double v = ddv * S[k] * theta + dv * S[k] * dth + kap * (ddv * gw + dv * dgw + dv * gdw) +
+                           dkap * Jt * trL * dv * gw;
                 Jl[(k * nd1 + d) * nl + col] = v;
             }
         }
@@ -526,7 +557,7 @@ int or_particle(const or_grid* g, const or_mat* mt, const or_opt* op, const doub
             double gg = 0;
             for (int a = 0; a < d; a++) gg += gS[k * d + a] * gS[kb * d + a];
             Jl[(k * nd1 + d) * nl + col] =
-                dv * mt->kappa * gg + op->tau * ct * Vn * (S[k] - Pi[k]) * (S[kb] - Pi[kb]);
+                dv * kap * gg + op->tau * ct * Vn * (S[k] - Pi[k]) * (S[kb] - Pi[kb]);
         }
     }
     return nn;

@@ -49,7 +49,7 @@ class _Grid(ctypes.Structure):
 class _Mat(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("lam", ctypes.c_double), ("G", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("rho_f", ctypes.c_double),
-                ("g", ctypes.c_double * 3)]
+                ("g", ctypes.c_double * 3), ("phi0", ctypes.c_double)]
 
 
 class _Opt(ctypes.Structure):
@@ -77,6 +77,7 @@ def lib():
         _lib.or_cell_proj.argtypes = [vp, l, vp, vp, vp, vp]
         _lib.or_particle.restype = i
         _lib.or_particle.argtypes = [vp, vp, vp, vp, vp, vp, d, d, i, vp, vp, vp, vp]
+        _lib.or_mobility.argtypes = [d, d, d, vp, vp]
         _lib.or_assemble.restype = l
         _lib.or_assemble.argtypes = [vp, vp, vp, l, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, l, vp, vp]
         _lib.or_g2p.restype = l
@@ -95,6 +96,14 @@ def _a(s) -> int:
 def lame(E: float, nu: float):
     """Lame parameters from Young's modulus and Poisson's ratio."""
     return E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), E / (2.0 * (1.0 + nu))
+
+
+def mobility(kappa0: float, phi0: float, J: float):
+    """Kozeny-Carman mobility at volume ratio J (Sec. 2.2, eq. kozeny-carman) and its derivative
+    d kappa / d J, from ``or_mobility``; phi0 <= 0 gives the constant kappa0."""
+    k, dk = ctypes.c_double(), ctypes.c_double()
+    lib().or_mobility(float(kappa0), float(phi0), float(J), ctypes.byref(k), ctypes.byref(dk))
+    return k.value, dk.value
 
 
 def stab_parameter(kind: int, scale: float, E: float, nu: float, kappa: float, h: float,
@@ -149,8 +158,10 @@ class OracleProblem:
         self._g = _Grid(d, (ctypes.c_int * 3)(*(list(grid.ncell) + [1] * (3 - d))[:3]), grid.h,
                         (ctypes.c_double * 3)(*(list(grid.origin) + [0.0] * 3)[:3]))
         gv = list(material.g) + [0.0] * 3
+        # initial porosity of the Kozeny-Carman law when the material asks for it, else 0
+        kc = material.phi0 if getattr(material, "kozeny_carman", False) else 0.0
         self._m = _Mat(material.model, lam, G, self.kappa, material.rho_f,
-                       (ctypes.c_double * 3)(*gv[:3]))
+                       (ctypes.c_double * 3)(*gv[:3]), kc)
         self.history = []
         self.rtol = options.newton_rtol
         self.newton_max = options.newton_max

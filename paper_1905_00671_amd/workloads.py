@@ -65,8 +65,9 @@ class Grid:
 
 @dataclass
 class Material:
-    """Constants of Sec. 2: skeleton elasticity (E, nu), permeability k, fluid viscosity mu_f,
-    intrinsic densities, initial porosity and gravity."""
+    """Constants of Sec. 2: skeleton elasticity (E, nu), permeability k (the initial one when
+    kozeny_carman is set), fluid viscosity mu_f, intrinsic densities, initial porosity and
+    gravity."""
     model: int = NEO_HOOKEAN
     E: float = 10e6
     nu: float = 0.3
@@ -76,6 +77,7 @@ class Material:
     rho_f: float = 1000.0
     phi0: float = 0.33
     g: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    kozeny_carman: bool = False     # k(phi) from phi0 and the volume ratio (eq. kozeny-carman)
 
     @property
     def rho0(self) -> float:

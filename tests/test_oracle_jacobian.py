@@ -8,7 +8,7 @@ from oracle import oracle as O
 from paper_1905_00671_amd import workloads as W
 
 
-def _problem(dim, shape, dynamic, model, tau_kind, seed, g=(0.0, 0.0, 0.0)):
+def _problem(dim, shape, dynamic, model, tau_kind, seed, g=(0.0, 0.0, 0.0), kozeny_carman=False):
     rng = np.random.default_rng(seed)
     if dim == 2:
         grid = W.Grid(2, (4, 4), 0.5, (0.0, 0.0, 0.0))
@@ -16,7 +16,7 @@ def _problem(dim, shape, dynamic, model, tau_kind, seed, g=(0.0, 0.0, 0.0)):
     else:
         grid = W.Grid(3, (3, 3, 3), 0.5, (0.0, 0.0, 0.0))
         lo, hi = (1, 1, 1), (2, 2, 2)
-    mat = W.Material(model=model, k=1e-9, g=g)
+    mat = W.Material(model=model, k=1e-9, g=g, kozeny_carman=kozeny_carman)
     opt = W.Options(shape=shape, dynamic=dynamic, beta=0.3025, gamma=0.6, tau_kind=tau_kind)
     parts = W.fill_particles(grid, lo, hi, mat.rho0, jitter=0.8, rng=rng)
     pr = O.OracleProblem(grid, mat, opt, parts)
@@ -42,10 +42,18 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("dim,shape,dynamic,model,tau_kind", CASES)
-def test_jacobian_matches_central_differences(dim, shape, dynamic, model, tau_kind):
+# Kozeny-Carman permeability (eq. kozeny-carman) adds the derivative of the mobility through the
+# volume ratio; checked quasi-static and Newmark, 2D and 3D
+KC_CASES = [(2, 1, 0, 1, 1, True), (2, 0, 1, 0, 1, True), (3, 0, 0, 1, 1, True)]
+
+
+@pytest.mark.parametrize("dim,shape,dynamic,model,tau_kind,kc", [c + (False,) for c in CASES] + KC_CASES)
+def test_jacobian_matches_central_differences(dim, shape, dynamic, model, tau_kind, kc):
     pr, nodal, U, P, rng = _problem(dim, shape, dynamic, model, tau_kind, seed=dim * 100 + shape * 10 + dynamic,
-                                    g=(0.3, -9.81, 0.0) if dim == 2 else (0.0, 0.2, -9.81))
+                                    g=(0.3, -9.81, 0.0) if dim == 2 else (0.0, 0.2, -9.81), kozeny_carman=kc)
+    if kc:
+        # volume changes of several percent, so that the mobility varies from point to point
+        U = U * 20.0
     dt = 0.01
     R, J, _ = pr.assemble(U, P, nodal, dt)
     nn = pr.grid.nnode

@@ -284,3 +284,27 @@ def test_free_fall_newmark_closed_form():
         # rounding level against the hydrostatic scale rho g h = 5e3 Pa
         assert np.abs(pr.p).max() < 1e-4
         assert np.abs(pr.sig).max() < 1e-4
+
+
+def test_kozeny_carman_mobility_values():
+    """Kozeny-Carman law (eq. kozeny-carman) with phi = 1 - (1 - phi0)/J: the initial state gives
+    k0; phi0 = 1/2 and J = 2 give phi = 3/4 and k/k0 = (1/4 / 1/8) (27/64 / 1/16) = 2 x 27/4 = 13.5;
+    phi0 = 1/2 and J = 4/5 give phi = 3/8 and k/k0 = 2 (27/512) / (25/64) = 27/100; the derivative
+    agrees with central differences; phi0 = 0 keeps the constant mobility."""
+    from oracle import oracle as O
+    k, _ = O.mobility(2.0, 0.3, 1.0)
+    assert abs(k - 2.0) <= 1e-15
+    k, _ = O.mobility(1.0, 0.5, 2.0)
+    assert abs(k - 13.5) <= 1e-13
+    k, _ = O.mobility(1.0, 0.5, 0.8)
+    assert abs(k - 27.0 / 100.0) <= 1e-15
+    for phi0, J in ((0.33, 0.9), (0.33, 1.2), (0.5, 2.0), (0.1, 1.05)):
+        _, dk = O.mobility(1.0, phi0, J)
+        e = 1e-6
+        fd = (O.mobility(1.0, phi0, J + e)[0] - O.mobility(1.0, phi0, J - e)[0]) / (2 * e)
+        assert abs(dk - fd) <= 1e-7 * abs(fd), (phi0, J, dk, fd)
+    assert O.mobility(3.0, 0.0, 1.7) == (3.0, 0.0)
+    # below the porosity floor the mobility is held: constant, zero derivative
+    k1, d1 = O.mobility(1.0, 0.3, 0.7)
+    k2, d2 = O.mobility(1.0, 0.3, 0.6)
+    assert d1 == 0.0 and d2 == 0.0 and k1 == k2
