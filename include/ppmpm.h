@@ -65,11 +65,16 @@ typedef struct {
 /* Constants of Sec. 2: E, nu of the skeleton (Lame parameters derived from them), intrinsic
  * permeability k and fluid viscosity mu_f (mobility k/mu_f of the Darcy law), intrinsic fluid
  * density, gravity.  model: PPMPM_HENCKY (plane strain only) or PPMPM_NEO_HOOKEAN
- * (tau' = G (b - 1) + lambda ln J 1). */
+ * (tau' = G (b - 1) + lambda ln J 1).
+ * phi0: 0 keeps k constant; in (0, 1) it is the initial porosity of the Kozeny-Carman law
+ * (eq. kozeny-carman), k then being the initial permeability and the porosity that of a skeleton
+ * of incompressible grains, phi = 1 - (1 - phi0)/J with J = det F, held at 1e-4 below that.
+ * Other values: PPMPM_E_INVALID. */
 typedef struct {
     int model;
     double E, nu, k, mu_f, rho_f;
     double g[3];
+    double phi0;
 } ppmpm_material;
 
 /* Method options.

@@ -36,7 +36,7 @@ class Grid(ctypes.Structure):
 class Material(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("E", ctypes.c_double), ("nu", ctypes.c_double),
                 ("k", ctypes.c_double), ("mu_f", ctypes.c_double), ("rho_f", ctypes.c_double),
-                ("g", ctypes.c_double * 3)]
+                ("g", ctypes.c_double * 3), ("phi0", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -140,7 +140,8 @@ def make_grid(g) -> Grid:
 
 def make_material(m) -> Material:
     gv = list(m.g) + [0.0] * 3
-    return Material(m.model, m.E, m.nu, m.k, m.mu_f, m.rho_f, (ctypes.c_double * 3)(*gv[:3]))
+    kc = m.phi0 if getattr(m, "kozeny_carman", False) else 0.0
+    return Material(m.model, m.E, m.nu, m.k, m.mu_f, m.rho_f, (ctypes.c_double * 3)(*gv[:3]), kc)
 
 
 def make_options(o, precision: int = FP64, **over) -> Options:

@@ -14,7 +14,8 @@
 // Points are bucketed by the first cell of their basis window, so the points that see node i at
 // window position l are exactly those of bucket i - l: both gathers loop over l at compile time
 // and every lane of a wavefront runs the same specialized code.
-// Residual terms (current configuration, dv = det(dF) V_n, grad S = dF^{-T} grad_n S):
+// Residual terms (current configuration, dv = det(dF) V_n, grad S = dF^{-T} grad_n S; kappa is
+// constant or the Kozeny-Carman mobility of the volume ratio det(dF) det(F_n), eq. kozeny-carman):
 //   R_mom_i  = -(V_n/J_n) tau' grad S_i + dv p^h grad S_i + m S_i (g - a^h)       eq. residual-momentum
 //   R_mass_i = dv S_i theta + dv kappa grad S_i.(grad p^h - rho_f (g - a^h))       eq. residual-mass
 //              + tau V_n (S_i - Pi S_i)(pdot^h - Pi pdot^h)                       eq. stab-term-ppp
@@ -111,6 +112,9 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     const double Vn = P[PV * s + i], m = P[PM * s + i];
     const double V0 = Vn / detFn;
     const double dv = dJ * Vn;
+    // mobility: constant, or Kozeny-Carman in the volume ratio dJ det(F_n)
+    double kap = d->kappa, kapj = 0.0;
+    if (d->phi0 > 0.0) kozeny_carman(d->kappa, d->phi0, dJ * detFn, &kap, &kapj);
     // pass 2: pressure, its gradient, the stabilization term and (Newmark) a^h, grad v
     double ph = 0.0, gp[DIM], ah[DIM], l[DIM * DIM], pst = 0.0;
 #pragma unroll
@@ -215,13 +219,14 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     rec[L::DV_] = dv;
     rec[L::CM_] = dyn ? m / (be * dt * dt) : 0.0;
     rec[L::BV_] = dyn ? dv * (theta + ga / (be * dt)) : dv * (1.0 + log(dJ)) / dt;
-    rec[L::DK_] = dv * d->kappa;
+    rec[L::DK_] = dv * kap;
+    rec[L::KJ_] = dv * kapj;
     for (int a = 0; a < DIM; ++a) {
         rec[L::GP_ + a] = gp[a];
         rec[L::QW_ + a] = wv[a];
         rec[L::BF_ + a] = m * (d->g[a] - ah[a]);
     }
-    rec[L::EE_] = dyn ? dv * d->kappa * d->rho_f / (be * dt * dt) : 0.0;
+    rec[L::EE_] = dyn ? dv * kap * d->rho_f / (be * dt * dt) : 0.0;
     rec[L::TC_] = d->tau * d->ct * Vn;
     rec[L::DT_] = dv * theta;
     rec[L::ST_] = d->tau * Vn * pst;
@@ -377,12 +382,12 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
 //   ca, cc <  dim : gi . Abar_{ca . cc .} gk - d_ac m/(beta dt^2) S_i S_k
 //   ca <  dim = cc: dv S_k gi_ca
 //   ca = dim > cc : S_i (bv gk_cc - (LV^T gk)_cc) + dv kappa (gk_cc gi.w - gi_cc gk.w - gi.gk gp_cc)
-//                   + dv kappa rho_f/(beta dt^2) gi_cc S_k
+//                   + dv kappa rho_f/(beta dt^2) gi_cc S_k  [+ dv J kappa'(J) gk_cc gi.w, Kozeny-Carman]
 //   ca = cc = dim : dv kappa gi.gk + tau c_t V_n (S_i - Pi_i)(S_k - Pi_k)
 // each written as u . gk + alpha S_k - gamma Pi_k = (f u) . grad_n S_k + alpha S_k - gamma Pi_k.
 // pic: the cell's Pi S_k (original MPM, PPP class only).
 template <int DIM, int SHAPE, int LI>
-__device__ __forceinline__ void jac_point(const RecRef rc, const double* pic, int ca, int cc,
+__device__ __forceinline__ void jac_point(const RecRef rc, const double* pic, int ca, int cc, bool kc,
                                           double* acc) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int RR = SHAPE ? 2 : 1;
@@ -454,6 +459,7 @@ __device__ __forceinline__ void jac_point(const RecRef rc, const double* pic, in
         for (int e = 0; e < DIM; ++e)
             u[e] = Si * ((e == cc ? bv : 0.0) - rc[L::LV_ + e * DIM + cc]) +
                    dk * ((e == cc ? giq : 0.0) - gic * qw[e] - gi[e] * gpc);
+        if (kc) u[cc] += rc[L::KJ_] * giq;   // mobility varying with the volume ratio
         alpha = rc[L::EE_] * gic;
     } else {
         const double dk = rc[L::DK_];
@@ -526,7 +532,8 @@ __device__ __forceinline__ void jac_bucket(const Dev* __restrict__ d, const int*
 #pragma unroll
                 for (int k = 0; k < NN; ++k) pic[k] = d->cellpi[cid * NN + k];
             }
-            for (int p = p0; p < p1; ++p) jac_point<DIM, SHAPE, LI>(RecRef(d->rec, p, L::N), pic, ca, cc, acc);
+            const bool kc = d->phi0 > 0.0;
+            for (int p = p0; p < p1; ++p) jac_point<DIM, SHAPE, LI>(RecRef(d->rec, p, L::N), pic, ca, cc, kc, acc);
         }
         jac_bucket<DIM, SHAPE, LI + 1>(d, n, ca, cc, acc);
     }

@@ -92,6 +92,7 @@ struct Dev {
     int64_t Np, Ncell, Nnode, Npad;
     double h, x0[3], hi[3];
     double lam, G, kappa, rho_f, g[3];
+    double phi0;  // initial porosity of the Kozeny-Carman law, 0: constant mobility
     // per-step parameters
     double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
     int nlev;
@@ -204,7 +205,8 @@ struct RecLayout {
     static constexpr int BF_ = SG_ + DIM * DIM;        // m (g - a) [DIM]
     static constexpr int DT_ = BF_ + DIM;              // dv theta
     static constexpr int ST_ = DT_ + 1;                // tau V_n (pdot - Pi pdot)
-    static constexpr int N = ST_ + 1;
+    static constexpr int KJ_ = ST_ + 1;                // dv J dkappa/dJ (Kozeny-Carman; else 0)
+    static constexpr int N = KJ_ + 1;
 };
 
 // Record of point p: NREC contiguous words (the gathers read ~30 fields of one point per visit,
@@ -215,6 +217,20 @@ struct RecRef {
     __device__ __forceinline__ double& operator[](int f) const { return b[f]; }
 };
 __host__ __device__ __forceinline__ int64_t rec_points_padded(int64_t np) { return np; }
+
+// Kozeny-Carman mobility (Sec. 2.2, eq. kozeny-carman) at volume ratio J for initial porosity
+// phi0 > 0: with phi = 1 - (1 - phi0)/J (incompressible grains), kappa = kappa0 (phi/phi0)^3
+// ((1 - phi0)/(1 - phi))^2.  Also *kj = J dkappa/dJ = kappa (3 - phi)/phi, the extra factor of the
+// mass-balance linearization; below KC_PHI_MIN the porosity is held there and *kj = 0.
+constexpr double KC_PHI_MIN = 1e-4;
+__device__ __forceinline__ void kozeny_carman(double kappa0, double phi0, double J, double* k, double* kj) {
+    double phi = 1.0 - (1.0 - phi0) / J;
+    const bool held = !(phi >= KC_PHI_MIN);
+    if (held) phi = KC_PHI_MIN;
+    const double r = phi / phi0, q = (1.0 - phi0) / (1.0 - phi);
+    *k = kappa0 * r * r * r * q * q;
+    *kj = held ? 0.0 : *k * (3.0 - phi) / phi;
+}
 
 // ------------------------------------------------------------------------------------------------
 // basis functions (Sec. 3.1)

@@ -455,6 +455,7 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     if (mat->model == PPMPM_HENCKY && grid->dim == 3) return fail(PPMPM_E_INVALID, "Hencky is plane strain only");
     if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->mu_f > 0) || !(mat->k >= 0))
         return fail(PPMPM_E_INVALID, "bad material constants");
+    if (!(mat->phi0 >= 0.0 && mat->phi0 < 1.0)) return fail(PPMPM_E_INVALID, "initial porosity outside [0, 1)");
     if (((uintptr_t)workspace & 255) != 0) return fail(PPMPM_E_INVALID, "workspace must be 256-byte aligned");
     size_t need = ppmpm_workspace_bytes(grid, np, opt);
     if (need == 0) return PPMPM_E_INVALID;   // message set by ppmpm_workspace_bytes
@@ -481,6 +482,7 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     h.lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
     h.G = mat->E / (2.0 * (1.0 + mat->nu));
     h.kappa = mat->k / mat->mu_f;
+    h.phi0 = mat->phi0;
     h.rho_f = mat->rho_f;
     for (int a = 0; a < 3; ++a) h.g[a] = a < grid->dim ? mat->g[a] : 0.0;
     h.dt = 1.0;

@@ -20,6 +20,12 @@ def _binding():
     return B
 
 
+def _kc(w):
+    """The workload with Kozeny-Carman permeability (eq. kozeny-carman) from its porosity."""
+    w.material.kozeny_carman = True
+    return w
+
+
 def _assembly_case(name):
     rng = np.random.default_rng(abs(hash(name)) % 1000)
     if name == "box_linear_qs":
@@ -38,6 +44,10 @@ def _assembly_case(name):
         w = W.config(3, nx=32, ny=16, width=2.0, empty_rows=3, nsteps=2)
     elif name == "footing3d":
         w = W.footing3d(n=5, size=1.25, half_b=0.25, nsteps=2)
+    elif name == "footing_gimp_kc":
+        w = _kc(W.config(3, nx=32, ny=16, width=2.0, empty_rows=3, nsteps=2))
+    elif name == "footing3d_kc":
+        w = _kc(W.footing3d(n=5, size=1.25, half_b=0.25, nsteps=2))
     elif name == "footing3d_dyn":
         w = W.footing3d(n=4, size=1.0, half_b=0.25, nsteps=2)
         w.options.dynamic = 1
@@ -49,7 +59,7 @@ def _assembly_case(name):
 
 
 ASSEMBLY_CASES = ["box_linear_qs", "box_gimp_qs", "box_gimp_dyn", "box_linear_dyn_hencky", "terzaghi",
-                  "footing_gimp", "footing3d", "footing3d_dyn"]
+                  "footing_gimp", "footing3d", "footing3d_dyn", "footing_gimp_kc", "footing3d_kc"]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -119,6 +129,7 @@ STEP_CASES = {
     "footing2d_qs_gimp": (lambda: W.config(3, nx=32, ny=16, width=2.0, empty_rows=2, nsteps=4), 4),
     "consolidation_linear": (lambda: W.consolidation2d(16, 1e-13, nsteps=3), 3),
     "footing3d": (lambda: W.footing3d(n=6, size=1.5, half_b=0.25, nsteps=2), 2),
+    "footing2d_qs_gimp_kc": (lambda: _kc(W.config(3, nx=32, ny=16, width=2.0, empty_rows=2, nsteps=4)), 4),
     # large enough for per-level multigrid kernels on two 3D levels below the fine grid
     "footing3d_mg": (lambda: W.footing3d(n=12, size=1.5, half_b=0.25, nsteps=2), 2),
 }
@@ -141,7 +152,7 @@ def test_step_parity_fp64(name):
             assert kt <= 60 * ng, errs
 
 
-@pytest.mark.parametrize("name", ["terzaghi", "footing2d_qs_gimp", "footing3d"])
+@pytest.mark.parametrize("name", ["terzaghi", "footing2d_qs_gimp", "footing3d", "footing2d_qs_gimp_kc"])
 def test_step_parity_mixed(name):
     make, nsteps = STEP_CASES[name]
     w = make()
@@ -288,3 +299,27 @@ def test_step_parity_two_smoothing_sweeps():
     errs = _run_steps(w, nsteps, 0, mg_smooth=2)
     for eu, ep, no, ng, kt in errs:
         assert eu < 1e-10 and ep < 1e-10, errs
+
+
+def test_kozeny_carman_changes_the_solution_and_rejects_bad_porosity():
+    """The porosity law is live on the device (the states differ from constant permeability once
+    the footing compacts the soil) and an initial porosity outside [0, 1) is refused."""
+    B = _binding()
+    make, nsteps = STEP_CASES["footing2d_qs_gimp"]
+    out = []
+    for kc in (False, True):
+        w = make()
+        w.material.kozeny_carman = kc
+        gp = B.Problem.from_workload(w, precision=0)
+        try:
+            for n in range(1, 3):
+                gp.step(w.dt, w.bc(n))
+            out.append(gp.get("p"))
+        finally:
+            gp.close()
+    assert rel_l2(out[1], out[0]) > 1e-6
+    w = make()
+    w.material.kozeny_carman = True
+    w.material.phi0 = 1.2
+    with pytest.raises(B.PPMPMError):
+        B.Problem.from_workload(w, precision=0)
