@@ -385,96 +385,97 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
 //                   + dv kappa rho_f/(beta dt^2) gi_cc S_k  [+ dv J kappa'(J) gk_cc gi.w, Kozeny-Carman]
 //   ca = cc = dim : dv kappa gi.gk + tau c_t V_n (S_i - Pi_i)(S_k - Pi_k)
 // each written as u . gk + alpha S_k - gamma Pi_k = (f u) . grad_n S_k + alpha S_k - gamma Pi_k.
-// pic: the cell's Pi S_k (original MPM, PPP class only).
-template <int DIM, int SHAPE, int LI>
-__device__ __forceinline__ void jac_point(const RecRef rc, const double* pic, int ca, int cc, bool kc,
-                                          double* acc) {
+// pic: the cell's Pi S_k (original MPM, PPP class only).  C is the arithmetic type of the entries
+// (double, or float for the FP32 Jacobian); the record fields are FP64 and are rounded on load.
+template <int DIM, int SHAPE, int LI, typename C>
+__device__ __forceinline__ void jac_point(const RecRef rc, const C* pic, int ca, int cc, bool kc,
+                                          C* acc) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int RR = SHAPE ? 2 : 1;
     constexpr int SW = 2 * RR + 1;
     constexpr int NN = DIM == 2 ? WB * WB : WB * WB * WB;
     constexpr int li[3] = {LI % WB, (LI / WB) % WB, DIM == 3 ? LI / (WB * WB) : 0};
     using L = RecLayout<DIM, WB>;
-    double w[DIM][WB], dw[DIM][WB];
+    C w[DIM][WB], dw[DIM][WB];
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
         for (int k = 0; k < WB; ++k) {
-            w[a][k] = rc[L::W_ + a * WB + k];
-            dw[a][k] = rc[L::DW_ + a * WB + k];
+            w[a][k] = (C)rc[L::W_ + a * WB + k];
+            dw[a][k] = (C)rc[L::DW_ + a * WB + k];
         }
-    double Si = 1.0, Gi[DIM];
+    C Si = C(1), Gi[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) Si *= w[a][li[a]];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        double g = 1.0;
+        C g = C(1);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) g *= (c == a) ? dw[c][li[c]] : w[c][li[c]];
         Gi[a] = g;
     }
-    double f[DIM * DIM], gi[DIM];
+    C f[DIM * DIM], gi[DIM];
 #pragma unroll
-    for (int e = 0; e < DIM * DIM; ++e) f[e] = rc[L::FI_ + e];
+    for (int e = 0; e < DIM * DIM; ++e) f[e] = (C)rc[L::FI_ + e];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        double t = 0.0;
+        C t = C(0);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) t += f[c * DIM + a] * Gi[c];
         gi[a] = t;
     }
-    double u[DIM], alpha = 0.0, gamma = 0.0, pik[NN];
+    C u[DIM], alpha = C(0), gamma = C(0), pik[NN];
 #pragma unroll
-    for (int k = 0; k < NN; ++k) pik[k] = 0.0;
+    for (int k = 0; k < NN; ++k) pik[k] = C(0);
     const bool ppp = ca == DIM && cc == DIM;
     if (ca < DIM && cc < DIM) {
 #pragma unroll
         for (int e = 0; e < DIM; ++e) {
-            double t = 0.0;
+            C t = C(0);
 #pragma unroll
-            for (int bb = 0; bb < DIM; ++bb) t += gi[bb] * rc[L::AB_ + ((ca * DIM + bb) * DIM + cc) * DIM + e];
+            for (int bb = 0; bb < DIM; ++bb) t += gi[bb] * (C)rc[L::AB_ + ((ca * DIM + bb) * DIM + cc) * DIM + e];
             u[e] = t;
         }
-        if (ca == cc) alpha = -rc[L::CM_] * Si;
+        if (ca == cc) alpha = -(C)rc[L::CM_] * Si;
     } else if (ca < DIM) {
 #pragma unroll
-        for (int e = 0; e < DIM; ++e) u[e] = 0.0;
-        double gia = 0.0;
+        for (int e = 0; e < DIM; ++e) u[e] = C(0);
+        C gia = C(0);
 #pragma unroll
-        for (int e = 0; e < DIM; ++e) gia += (e == ca) ? gi[e] : 0.0;
-        alpha = rc[L::DV_] * gia;
+        for (int e = 0; e < DIM; ++e) gia += (e == ca) ? gi[e] : C(0);
+        alpha = (C)rc[L::DV_] * gia;
     } else if (cc < DIM) {
-        const double bv = rc[L::BV_], dk = rc[L::DK_];
-        double qw[DIM], giq = 0.0;
+        const C bv = (C)rc[L::BV_], dk = (C)rc[L::DK_];
+        C qw[DIM], giq = C(0);
 #pragma unroll
         for (int e = 0; e < DIM; ++e) {
-            qw[e] = rc[L::QW_ + e];
+            qw[e] = (C)rc[L::QW_ + e];
             giq += gi[e] * qw[e];
         }
-        const double gpc = rc[L::GP_ + cc];
-        double gic = 0.0;
+        const C gpc = (C)rc[L::GP_ + cc];
+        C gic = C(0);
 #pragma unroll
-        for (int e = 0; e < DIM; ++e) gic += (e == cc) ? gi[e] : 0.0;
+        for (int e = 0; e < DIM; ++e) gic += (e == cc) ? gi[e] : C(0);
 #pragma unroll
         for (int e = 0; e < DIM; ++e)
-            u[e] = Si * ((e == cc ? bv : 0.0) - rc[L::LV_ + e * DIM + cc]) +
-                   dk * ((e == cc ? giq : 0.0) - gic * qw[e] - gi[e] * gpc);
-        if (kc) u[cc] += rc[L::KJ_] * giq;   // mobility varying with the volume ratio
-        alpha = rc[L::EE_] * gic;
+            u[e] = Si * ((e == cc ? bv : C(0)) - (C)rc[L::LV_ + e * DIM + cc]) +
+                   dk * ((e == cc ? giq : C(0)) - gic * qw[e] - gi[e] * gpc);
+        if (kc) u[cc] += (C)rc[L::KJ_] * giq;   // mobility varying with the volume ratio
+        alpha = (C)rc[L::EE_] * gic;
     } else {
-        const double dk = rc[L::DK_];
+        const C dk = (C)rc[L::DK_];
 #pragma unroll
         for (int e = 0; e < DIM; ++e) u[e] = dk * gi[e];
         if (SHAPE) {
-            double s0[DIM][WB];
+            C s0[DIM][WB];
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
 #pragma unroll
-                for (int k = 0; k < WB; ++k) s0[a][k] = rc[L::S0_ + a * WB + k];
+                for (int k = 0; k < WB; ++k) s0[a][k] = (C)rc[L::S0_ + a * WB + k];
 #pragma unroll
             for (int k = 0; k < NN; ++k) {
                 const int lk[3] = {k % WB, (k / WB) % WB, DIM == 3 ? k / (WB * WB) : 0};
-                double v = 1.0;
+                C v = C(1);
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) v *= s0[a][lk[a]];
                 pik[k] = v;
@@ -483,13 +484,13 @@ __device__ __forceinline__ void jac_point(const RecRef rc, const double* pic, in
 #pragma unroll
             for (int k = 0; k < NN; ++k) pik[k] = pic[k];
         }
-        gamma = rc[L::TC_] * (Si - pik[LI]);
+        gamma = (C)rc[L::TC_] * (Si - pik[LI]);
         alpha = gamma;
     }
-    double ut[DIM];
+    C ut[DIM];
 #pragma unroll
     for (int m = 0; m < DIM; ++m) {
-        double t = 0.0;
+        C t = C(0);
 #pragma unroll
         for (int e = 0; e < DIM; ++e) t += f[m * DIM + e] * u[e];
         ut[m] = t;
@@ -503,7 +504,7 @@ __device__ __forceinline__ void jac_point(const RecRef rc, const double* pic, in
                 const int s = (kx - li[0] + RR) + SW * (ky - li[1] + RR) +
                               (DIM == 3 ? SW * SW * (kz - li[2] + RR) : 0);
                 const int kk = kx + WB * (ky + WB * kz);
-                double val;
+                C val;
                 if constexpr (DIM == 2) {
                     val = ut[0] * dw[0][kx] * w[1][ky] + ut[1] * w[0][kx] * dw[1][ky] + alpha * w[0][kx] * w[1][ky];
                 } else {
@@ -516,8 +517,8 @@ __device__ __forceinline__ void jac_point(const RecRef rc, const double* pic, in
 }
 
 // All points of bucket n - l (LI = window index of n), then the next window index.
-template <int DIM, int SHAPE, int LI>
-__device__ __forceinline__ void jac_bucket(const Dev* __restrict__ d, const int* n, int ca, int cc, double* acc) {
+template <int DIM, int SHAPE, int LI, typename C>
+__device__ __forceinline__ void jac_bucket(const Dev* __restrict__ d, const int* n, int ca, int cc, C* acc) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int NN = DIM == 2 ? WB * WB : WB * WB * WB;
     if constexpr (LI < NN) {
@@ -525,17 +526,17 @@ __device__ __forceinline__ void jac_bucket(const Dev* __restrict__ d, const int*
         int64_t cid;
         int p0, p1;
         if (bucket_of<DIM, WB, LI>(d, n, &cid, &p0, &p1)) {
-            double pic[NN];
+            C pic[NN];
 #pragma unroll
-            for (int k = 0; k < NN; ++k) pic[k] = 0.0;
+            for (int k = 0; k < NN; ++k) pic[k] = C(0);
             if (!SHAPE && ca == DIM && cc == DIM && p1 > p0) {
 #pragma unroll
-                for (int k = 0; k < NN; ++k) pic[k] = d->cellpi[cid * NN + k];
+                for (int k = 0; k < NN; ++k) pic[k] = (C)d->cellpi[cid * NN + k];
             }
-            const bool kc = d->phi0 > 0.0;
-            for (int p = p0; p < p1; ++p) jac_point<DIM, SHAPE, LI>(RecRef(d->rec, p, L::N), pic, ca, cc, kc, acc);
+            const bool kc = d->phi0 > C(0);
+            for (int p = p0; p < p1; ++p) jac_point<DIM, SHAPE, LI, C>(RecRef(d->rec, p, L::N), pic, ca, cc, kc, acc);
         }
-        jac_bucket<DIM, SHAPE, LI + 1>(d, n, ca, cc, acc);
+        jac_bucket<DIM, SHAPE, LI + 1, C>(d, n, ca, cc, acc);
     }
 }
 
@@ -544,11 +545,11 @@ __device__ __forceinline__ void jac_bucket(const Dev* __restrict__ d, const int*
 // node read the same point record at the same time and a wavefront's record loads touch a few
 // cache lines instead of one per lane.  The node's block row over the fixed stencil is
 // accumulated in registers and written once, with the rows and columns of constrained dofs
-// replaced by identity rows.  The 2D FP32 form is held to 128 registers (4 waves per SIMD, a
-// few words spilled: 9% faster); the FP64 and 3D forms run faster unconstrained at 3 waves.
+// replaced by identity rows.  The point terms are formed and accumulated in T: the FP32 Jacobian
+// of the mixed path (records, residual and Newton update stay FP64) needs about two thirds of
+// the registers of the FP64 one and runs at 4-5 waves per SIMD instead of 3.
 template <int DIM, int SHAPE, typename T>
-__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(DIM == 2 && sizeof(T) == 4 ? 4 : 1, 8)))
-k_jacobian(Batch B) {
+__global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
     const int q = batch_find(B, blockIdx.x);
     const Dev* __restrict__ d = B.d[q];
     const int64_t lb = blockIdx.x - B.pfx[q];
@@ -570,10 +571,10 @@ k_jacobian(Batch B) {
     n[2] = DIM == 3 ? (int)(lb / ((int64_t)ntx * d->nn[1])) : 0;
     if (n[0] >= d->nn[0]) return;
     const int64_t row = n[0] + (int64_t)d->nn[0] * (n[1] + (int64_t)d->nn[1] * n[2]);
-    double acc[S];
+    T acc[S];   // accumulated, like the point terms, in the Jacobian's own precision
 #pragma unroll
-    for (int s = 0; s < S; ++s) acc[s] = 0.0;
-    jac_bucket<DIM, SHAPE, 0>(d, n, ca, cc, acc);
+    for (int s = 0; s < S; ++s) acc[s] = T(0);
+    jac_bucket<DIM, SHAPE, 0, T>(d, n, ca, cc, acc);
     const int64_t pni = pad_index(d, n[0], n[1], n[2]);
     const bool fr = d->dfree[pni * BS + ca] != 0;
     T* J = (T*)d->J;
