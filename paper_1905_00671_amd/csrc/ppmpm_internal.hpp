@@ -183,7 +183,8 @@ __device__ __forceinline__ int batch_find(const Batch& B, int blk) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// record layout (quadrature-point data written once per Newton iteration)
+// record layout (quadrature-point data written once per Newton iteration): the fields the
+// residual gather reads come first, so that one visit touches three cache lines instead of four
 // ------------------------------------------------------------------------------------------------
 template <int DIM, int WB>
 struct RecLayout {
@@ -191,21 +192,21 @@ struct RecLayout {
     static constexpr int DW_ = W_ + DIM * WB;          // 1D gradients [DIM][WB]
     static constexpr int S0_ = DW_ + DIM * WB;         // GIMP constant basis [DIM][WB]
     static constexpr int FI_ = S0_ + DIM * WB;         // dF^{-1} [DIM*DIM]
-    static constexpr int AB_ = FI_ + DIM * DIM;        // tangent Abar [DIM^4]
+    static constexpr int SG_ = FI_ + DIM * DIM;        // -V0 tau' + dv p 1 [DIM*DIM]
+    static constexpr int BF_ = SG_ + DIM * DIM;        // m (g - a) [DIM]
+    static constexpr int DT_ = BF_ + DIM;              // dv theta
+    static constexpr int ST_ = DT_ + 1;                // tau V_n (pdot - Pi pdot)
+    static constexpr int DK_ = ST_ + 1;                // dv kappa
+    static constexpr int QW_ = DK_ + 1;                // w = grad p - rho_f (g - a) [DIM]
+    static constexpr int AB_ = QW_ + DIM;              // tangent Abar [DIM^4]
     static constexpr int DV_ = AB_ + DIM * DIM * DIM * DIM;   // dv
     static constexpr int CM_ = DV_ + 1;                // m / (beta dt^2)
     static constexpr int BV_ = CM_ + 1;                // volumetric coupling coefficient
     static constexpr int LV_ = BV_ + 1;                // dv * velocity gradient [DIM*DIM]
-    static constexpr int DK_ = LV_ + DIM * DIM;        // dv kappa
-    static constexpr int GP_ = DK_ + 1;                // grad p [DIM]
-    static constexpr int QW_ = GP_ + DIM;              // w = grad p - rho_f (g - a) [DIM]
-    static constexpr int EE_ = QW_ + DIM;              // dv kappa rho_f / (beta dt^2)
+    static constexpr int GP_ = LV_ + DIM * DIM;        // grad p [DIM]
+    static constexpr int EE_ = GP_ + DIM;              // dv kappa rho_f / (beta dt^2)
     static constexpr int TC_ = EE_ + 1;                // tau c_t V_n
-    static constexpr int SG_ = TC_ + 1;                // -V0 tau' + dv p 1 [DIM*DIM]
-    static constexpr int BF_ = SG_ + DIM * DIM;        // m (g - a) [DIM]
-    static constexpr int DT_ = BF_ + DIM;              // dv theta
-    static constexpr int ST_ = DT_ + 1;                // tau V_n (pdot - Pi pdot)
-    static constexpr int KJ_ = ST_ + 1;                // dv J dkappa/dJ (Kozeny-Carman; else 0)
+    static constexpr int KJ_ = TC_ + 1;                // dv J dkappa/dJ (Kozeny-Carman; else 0)
     static constexpr int N = KJ_ + 1;
 };
 
