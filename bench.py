@@ -270,7 +270,7 @@ def main():
     args = ap.parse_args()
     WORKLOAD = args.workload
     if args.gpus != 1:
-        print(f"bench.py measures one MI355X: --gpus {args.gpus} is not supported (this build runs the hot path "
+        print(f"bench.py measures one MI355X: --gpus {args.gpus} is not supported (the library runs the hot path "
               f"on a single GPU; the multi-GPU decomposition is a design only).", file=sys.stderr)
         sys.exit(2)
     import torch
