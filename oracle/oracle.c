@@ -36,6 +36,7 @@ typedef struct {
     double rho_f;
     double g[3];
     double phi0;     /* initial porosity of the Kozeny-Carman law (Sec. 2.2); <= 0: kappa constant */
+    double alpha_vis; /* damping parameter of the Kelvin-type viscous stress (Sec. 2.2); dynamic only */
 } or_mat;
 
 /* Porosity below which the Kozeny-Carman mobility is held constant (the law degenerates at
@@ -403,6 +404,19 @@ void or_mobility(double kappa0, double phi0, double J, double* k, double* dk) {
     *dk = held ? 0.0 : dk_dphi * (1.0 - phi0) / (J * J);
 }
 
+/* Kelvin-type viscous effective stress (Sec. 2.2): sigma'_vis = alpha_vis c : sym(l) with l the
+ * velocity gradient in the current configuration (d x d, row-major).  Reading: c is the isotropic
+ * elasticity tensor of the skeleton, lambda 1 (x) 1 + 2 G I, i.e. the spatial tangent of the
+ * inviscid law at the undeformed state (so that the damping term can be linearized exactly).
+ * Only the in-plane block is formed in plane strain. */
+void or_viscous_stress(const or_mat* mt, int d, const double* l, double* s) {
+    double tr = 0.0;
+    for (int a = 0; a < d; a++) tr += l[a * d + a];
+    for (int a = 0; a < d; a++)
+        for (int b = 0; b < d; b++)
+            s[a * d + b] = mt->alpha_vis * (mt->G * (l[a * d + b] + l[b * d + a]) + (a == b ? mt->lam * tr : 0.0));
+}
+
 /* Local residual r[nn*(d+1)] and local Jacobian Jl[(nn*(d+1))^2] (row-major, may be NULL) of
  * one material point.  Terms (Sec. 3.1-3.4, 4.2):
  *   R_mom_i  = -(V_n/J_n) tau' gradS_i + dv p^h gradS_i + m S_i (g - a^h)          (eq. residual-momentum)
@@ -479,6 +493,10 @@ int or_particle(const or_grid* g, const or_mat* mt, const or_opt* op, const doub
     }
     double w[3];
     for (int a = 0; a < d; a++) w[a] = gp[a] - mt->rho_f * (mt->g[a] - ah[a]);
+    /* viscous stress of the Newmark velocity field (dynamic problems only, eq. quasi-static-condition) */
+    int vis = op->dynamic && mt->alpha_vis != 0.0;
+    double svis[9] = {0};
+    if (vis) or_viscous_stress(mt, d, l, svis);
     double ct = op->dynamic ? ga / (be * dt) : 1.0 / dt;
     double pstab = 0;
     if (op->tau != 0.0) {
@@ -495,7 +513,9 @@ int or_particle(const or_grid* g, const or_mat* mt, const or_opt* op, const doub
         for (int a = 0; a < d; a++) {
             double s = 0;
             for (int b = 0; b < d; b++) s += tau[a * 3 + b] * gS[k * d + b];
-            r[k * nd1 + a] = -V0 * s + dv * ph * gS[k * d + a] + mp * S[k] * (mt->g[a] - ah[a]);
+            double sv = 0;
+            for (int b = 0; b < d; b++) sv += svis[a * d + b] * gS[k * d + b];
+            r[k * nd1 + a] = -V0 * s + dv * ph * gS[k * d + a] + mp * S[k] * (mt->g[a] - ah[a]) - dv * sv;
         }
         double dw = 0;
         for (int a = 0; a < d; a++) dw += gS[k * d + a] * w[a];
@@ -526,6 +546,15 @@ int or_particle(const or_grid* g, const or_mat* mt, const or_opt* op, const doub
             }
             double dw[3];
             for (int a = 0; a < d; a++) dw[a] = dgp[a] + mt->rho_f * dah[a];
+            /* derivative of the viscous stress: dl = (gamma/(beta dt) e_c - l e_c) (x) gradS_kb */
+            double dsvis[9] = {0};
+            if (vis) {
+                double dl[9];
+                for (int x = 0; x < d; x++)
+                    for (int y = 0; y < d; y++)
+                        dl[x * d + y] = ((x == c ? ga / (be * dt) : 0.0) - l[x * d + c]) * gS[kb * d + y];
+                or_viscous_stress(mt, d, dl, dsvis);
+            }
             for (int k = 0; k < nn; k++) {
                 double dgS[3];
                 for (int y = 0; y < d; y++) dgS[y] = -gS[kb * d + y] * gS[k * d + c];
@@ -536,6 +565,15 @@ int or_particle(const or_grid* g, const or_mat* mt, const or_opt* op, const doub
                         s2 += tau[a * 3 + b] * dgS[b];
                     }
                     double v = -V0 * (s1 + s2) + ddv * ph * gS[k * d + a] + dv * ph * dgS[a] - mp * S[k] * dah[a];
+                    if (vis) {
+                        double t1 = 0, t2 = 0, t3 = 0;
+                        for (int b = 0; b < d; b++) {
+                            t1 += svis[a * d + b] * gS[k * d + b];
+                            t2 += dsvis[a * d + b] * gS[k * d + b];
+                            t3 += svis[a * d + b] * dgS[b];
+                        }
+                        v -= ddv * t1 + dv * t2 + dv * t3;
+                    }
                     Jl[(k * nd1 + a) * nl + col] = v;
                 }
                 double gw = 0, dgw = 0, gdw = 0;

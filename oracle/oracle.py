@@ -49,7 +49,7 @@ class _Grid(ctypes.Structure):
 class _Mat(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("lam", ctypes.c_double), ("G", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("rho_f", ctypes.c_double),
-                ("g", ctypes.c_double * 3), ("phi0", ctypes.c_double)]
+                ("g", ctypes.c_double * 3), ("phi0", ctypes.c_double), ("alpha_vis", ctypes.c_double)]
 
 
 class _Opt(ctypes.Structure):
@@ -78,6 +78,7 @@ def lib():
         _lib.or_particle.restype = i
         _lib.or_particle.argtypes = [vp, vp, vp, vp, vp, vp, d, d, i, vp, vp, vp, vp]
         _lib.or_mobility.argtypes = [d, d, d, vp, vp]
+        _lib.or_viscous_stress.argtypes = [vp, i, vp, vp]
         _lib.or_assemble.restype = l
         _lib.or_assemble.argtypes = [vp, vp, vp, l, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, l, vp, vp]
         _lib.or_g2p.restype = l
@@ -121,7 +122,8 @@ def stab_parameter(kind: int, scale: float, E: float, nu: float, kappa: float, h
     if kind == 2:
         return scale * max(0.0, (1.0 / M) * (1.0 - 3.0 * c) * (1.0 + math.tanh(2.0 - 12.0 * c)))
     if kind == 3:
-        return scale * max(2.0 * kappa / cv - (beta / gamma) * 12.0 * kappa * dt / (h * h), 0.0)
+        # 2 kappa / c_v = 2 / M (c_v = M kappa), which also holds in the limit kappa -> 0
+        return scale * max(2.0 / M - (beta / gamma) * 12.0 * kappa * dt / (h * h), 0.0)
     raise ValueError(kind)
 
 
@@ -161,7 +163,7 @@ class OracleProblem:
         # initial porosity of the Kozeny-Carman law when the material asks for it, else 0
         kc = material.phi0 if getattr(material, "kozeny_carman", False) else 0.0
         self._m = _Mat(material.model, lam, G, self.kappa, material.rho_f,
-                       (ctypes.c_double * 3)(*gv[:3]), kc)
+                       (ctypes.c_double * 3)(*gv[:3]), kc, float(getattr(material, "alpha_vis", 0.0)))
         self.history = []
         self.rtol = options.newton_rtol
         self.newton_max = options.newton_max
@@ -354,6 +356,16 @@ def basis(grid, shape, xp, lp=None):
     S = np.zeros(64); G = np.zeros(64 * 3); S0 = np.zeros(64)
     n = lib().or_basis(_a(g), shape, _p(xp), _p(lp), _p(nodes), _p(S), _p(G), _p(S0))
     return nodes[:n].copy(), S[:n].copy(), G[: n * grid.dim].reshape(n, grid.dim).copy(), S0[:n].copy()
+
+
+def viscous_stress(lam, G, alpha_vis, L):
+    """Kelvin-type viscous stress of ``or_viscous_stress`` for the velocity gradient L (d x d)."""
+    L = np.ascontiguousarray(L, np.float64)
+    d = L.shape[0]
+    m = _Mat(1, lam, G, 0.0, 0.0, (ctypes.c_double * 3)(0.0, 0.0, 0.0), 0.0, alpha_vis)
+    out = np.zeros(d * d)
+    lib().or_viscous_stress(_a(m), d, _p(L), _p(out))
+    return out.reshape(d, d)
 
 
 def kirchhoff(model, lam, G, F):

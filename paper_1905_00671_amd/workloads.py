@@ -78,6 +78,7 @@ class Material:
     phi0: float = 0.33
     g: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     kozeny_carman: bool = False     # k(phi) from phi0 and the volume ratio (eq. kozeny-carman)
+    alpha_vis: float = 0.0          # Kelvin-type damping parameter (s), dynamic problems only
 
     @property
     def rho0(self) -> float:

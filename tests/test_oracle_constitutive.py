@@ -80,3 +80,25 @@ def test_neo_hookean_closed_form():
     J = np.linalg.det(F)
     tau = O.kirchhoff(1, LAM, G, F)
     assert np.abs(tau[:2, :2] - (G * (b - np.eye(2)) + LAM * np.log(J) * np.eye(2))).max() < 1e-6
+
+
+@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_viscous_stress_uses_the_small_strain_tangent(model, dim):
+    """Sec. 2.2, Kelvin-type damping sigma'_vis = alpha_vis c : sym(l): with c read as the spatial
+    tangent of the inviscid law at the undeformed state, sigma'_vis / alpha_vis must equal the
+    derivative of the effective Cauchy stress along F = 1 + eps l at eps = 0 (central differences
+    of or_kirchhoff; both hyperelastic laws share this small-strain tangent)."""
+    if model == 0 and dim == 3:
+        pytest.skip("Hencky is plane strain only")
+    rng = np.random.default_rng(3 + dim + 10 * model)
+    lam, G, alpha = 5.769e6, 3.846e6, 0.04
+    for _ in range(3):
+        L = rng.random((dim, dim)) - 0.5
+        eps = 1e-6
+        sp = O.kirchhoff(model, lam, G, np.eye(dim) + eps * L)[:dim, :dim] / np.linalg.det(np.eye(dim) + eps * L)
+        sm = O.kirchhoff(model, lam, G, np.eye(dim) - eps * L)[:dim, :dim] / np.linalg.det(np.eye(dim) - eps * L)
+        fd = (sp - sm) / (2 * eps)
+        sv = O.viscous_stress(lam, G, alpha, L)
+        assert np.abs(sv / alpha - fd).max() <= 1e-6 * np.abs(fd).max()
+        assert np.allclose(sv, sv.T)

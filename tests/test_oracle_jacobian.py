@@ -8,7 +8,7 @@ from oracle import oracle as O
 from paper_1905_00671_amd import workloads as W
 
 
-def _problem(dim, shape, dynamic, model, tau_kind, seed, g=(0.0, 0.0, 0.0), kozeny_carman=False):
+def _problem(dim, shape, dynamic, model, tau_kind, seed, g=(0.0, 0.0, 0.0), kozeny_carman=False, alpha_vis=0.0):
     rng = np.random.default_rng(seed)
     if dim == 2:
         grid = W.Grid(2, (4, 4), 0.5, (0.0, 0.0, 0.0))
@@ -16,7 +16,7 @@ def _problem(dim, shape, dynamic, model, tau_kind, seed, g=(0.0, 0.0, 0.0), koze
     else:
         grid = W.Grid(3, (3, 3, 3), 0.5, (0.0, 0.0, 0.0))
         lo, hi = (1, 1, 1), (2, 2, 2)
-    mat = W.Material(model=model, k=1e-9, g=g, kozeny_carman=kozeny_carman)
+    mat = W.Material(model=model, k=1e-9, g=g, kozeny_carman=kozeny_carman, alpha_vis=alpha_vis)
     opt = W.Options(shape=shape, dynamic=dynamic, beta=0.3025, gamma=0.6, tau_kind=tau_kind)
     parts = W.fill_particles(grid, lo, hi, mat.rho0, jitter=0.8, rng=rng)
     pr = O.OracleProblem(grid, mat, opt, parts)
@@ -47,10 +47,18 @@ CASES = [
 KC_CASES = [(2, 1, 0, 1, 1, True), (2, 0, 1, 0, 1, True), (3, 0, 0, 1, 1, True)]
 
 
-@pytest.mark.parametrize("dim,shape,dynamic,model,tau_kind,kc", [c + (False,) for c in CASES] + KC_CASES)
-def test_jacobian_matches_central_differences(dim, shape, dynamic, model, tau_kind, kc):
+# Kelvin-type viscous damping (Sec. 2.2, the sigma'_vis term of eq. residual-momentum), Newmark:
+# its exact linearization (velocity through eq. newmark-linearization, and the geometric terms)
+VIS_CASES = [(2, 1, 1, 1, 1, False, 0.04), (2, 0, 1, 0, 1, False, 0.04), (3, 0, 1, 1, 1, False, 0.04),
+             (2, 1, 1, 1, 1, True, 0.04)]
+
+
+@pytest.mark.parametrize("dim,shape,dynamic,model,tau_kind,kc,alpha_vis",
+                         [c + (False, 0.0) for c in CASES] + [c + (0.0,) for c in KC_CASES] + VIS_CASES)
+def test_jacobian_matches_central_differences(dim, shape, dynamic, model, tau_kind, kc, alpha_vis):
     pr, nodal, U, P, rng = _problem(dim, shape, dynamic, model, tau_kind, seed=dim * 100 + shape * 10 + dynamic,
-                                    g=(0.3, -9.81, 0.0) if dim == 2 else (0.0, 0.2, -9.81), kozeny_carman=kc)
+                                    g=(0.3, -9.81, 0.0) if dim == 2 else (0.0, 0.2, -9.81), kozeny_carman=kc,
+                                    alpha_vis=alpha_vis)
     if kc:
         # volume changes of several percent, so that the mobility varies from point to point
         U = U * 20.0

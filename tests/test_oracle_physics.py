@@ -308,3 +308,36 @@ def test_kozeny_carman_mobility_values():
     k1, d1 = O.mobility(1.0, 0.3, 0.7)
     k2, d2 = O.mobility(1.0, 0.3, 0.6)
     assert d1 == 0.0 and d2 == 0.0 and k1 == k2
+
+
+@pytest.mark.parametrize("shape", [W.LINEAR, W.GIMP])
+def test_viscous_damping_dissipates(shape):
+    """The Kelvin-type viscous term (Sec. 2.2) only dissipates: with zero nodal kinematics at t_n
+    the Newmark velocity is proportional to U (eq. newmark), and the viscous part of the momentum
+    residual does negative work, sum_i U_i . R_vis,i < 0, for any increment; it vanishes for a
+    rigid translation (l = 0)."""
+    r = np.random.default_rng(12)
+    res = {}
+    Us = None
+    for alpha in (0.0, 0.05):
+        w = W.jittered_box(5, 5, h=0.25, shape=shape, dynamic=1, seed=6, jitter=0.5, empty=1)
+        w.material.alpha_vis = alpha
+        pr = O.from_workload(w)
+        nodal = pr.p2g()
+        nn, d = w.grid.nnode, 2
+        nodal["vn"] = np.zeros(nn * d)
+        nodal["an"] = np.zeros(nn * d)
+        act = nodal["active"]
+        if Us is None:
+            Us = [1e-4 * (r.random((nn, d)) - 0.5) * act[:, None] for _ in range(4)]
+            Us.append(np.tile([3e-4, -2e-4], (nn, 1)) * act[:, None])          # rigid translation
+        res[alpha] = [pr.assemble(u, nodal["Pn"], nodal, 1e-3, want_J=False)[0].reshape(nn, d + 1)[:, :d]
+                      for u in Us]
+    for k, u in enumerate(Us):
+        Rv = res[0.05][k] - res[0.0][k]
+        work = float(np.sum(Rv * u))
+        scale = float(np.abs(Rv).max() * np.abs(u).max()) + 1e-300
+        if k < 4:
+            assert work < 0.0 and np.abs(Rv).max() > 0.0
+        else:
+            assert np.abs(Rv).max() <= 1e-9 * np.abs(res[0.0][k]).max(), k
