@@ -115,13 +115,20 @@ static void gimp_1d(double a, double b, double xi, double h, double* S, double* 
     *dS = (hat(b - xi, h) - hat(a - xi, h)) / len;
 }
 
+/* Overlap (relative to h) below which a node's support and a particle domain only touch: the
+ * intersection of the definition (eq. gimp-basis) then has measure zero and the node carries no
+ * weight.  Without the threshold, the rounding of the interval ends (cell sizes that are not
+ * powers of two) would decide whether such a node gets a mass of ~1e-27 and becomes active. */
+#define OR_GIMP_TOUCH 1e-10
+
 /* 1D constant basis of the GIMP-compatible projection (Sec. 4.4): one half of the share of the
- * particle domain lying inside the support [xi - h, xi + h] of the node. */
+ * particle domain lying inside the support [xi - h, xi + h] of the node; 0 (and the node is not
+ * in the point's basis) when the two only touch. */
 static double gimp_s0_1d(double a, double b, double xi, double h) {
     double lo = a > xi - h ? a : xi - h;
     double hi = b < xi + h ? b : xi + h;
     double ov = hi - lo;
-    return ov > 0.0 ? 0.5 * ov / (b - a) : 0.0;
+    return ov > OR_GIMP_TOUCH * h ? 0.5 * ov / (b - a) : 0.0;
 }
 
 static int cell_of(const or_grid* g, int d, double x) {
