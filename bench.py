@@ -1,17 +1,28 @@
 #!/usr/bin/env python
 """Benchmark of the stabilized implicit MPM hot path on one MI355X.
 
-Workload: the large 2D quasi-static footing -- GIMP basis, 512 x 256 material cells of
-h = 0.0625 m plus 16 empty rows, 4 points per cell (524,288 points), neo-Hookean skeleton,
-permeability drawn once from seed 0, rigid footing pushed 5 mm per step, dt = 0.1 s.
-One "step" is one full implicit time step (sort, P2G, Newton iterations with assembly and the
-block-preconditioned BiCGStab, G2P) with Newton driven to 1e-8 relative residual per block.
+Headline workload (default): the 3D rigid-footing quarter-model -- trilinear original MPM,
+96^3 material cells of h = 0.125 m plus 2 empty layers, 8 points per cell (7,077,888 points,
+931,491 grid nodes, 3,725,964 u-p unknowns in 4x4 blocks), neo-Hookean skeleton, k = 1e-12 m^2,
+footing pushed 5 mm per step, dt = 0.1 s, quasi-static.  One "step" is one full implicit time
+step: sort, P2G, Newton iterations (material-point residual and exact Jacobian with the PPP term,
+block-preconditioned BiCGStab), G2P, with Newton driven to 1e-8 relative residual per block.
 
-Reported: particle-updates/s per Newton step (points x Newton iterations / s) for the FP64 path
-(the headline value) and for the mixed path (FP32 Jacobian, SpMV, preconditioner; FP64 residual
-and update) at the same 1e-8 residual; particle-steps/s; p50/p99 step latency; the SpMV roofline
-from HIP events recorded inside the library; the CPU oracle on a bounded sample; a small parity
-check against the oracle.
+Reported on the JSON line:
+  value        particle-updates/s per Newton step (points x Newton iterations / s) of the FP64 path
+  fp64, mixed  both precisions at the same 1e-8 Newton residual (mixed: FP32 Jacobian, SpMV and
+               preconditioner, FP64 residual and update), particle-steps/s, p50/p99 step latency,
+               Newton/Krylov counts, per-kernel times; an FP64 control at the mixed path's Krylov
+               tolerance separates the precision effect from the looser inner solve
+  roofline     the SpMV of the Krylov solver (HIP-event launch times inside the library; HBM
+               traffic from the committed rocprofv3 counter summary of the same workload and
+               precision, if it was taken on the current kernel source); `assembly` the same for
+               the Jacobian assembly kernels
+  footing2d_large  the 512 x 256-cell 2D GIMP footing (524,288 points), both precisions
+  serving      the Poisson stream of 256 independent 2D problems through the continuous-batching
+               loop, both precisions on the same trace: throughput and p50/p99 latencies
+  cpu_baseline the CPU oracle (single core, pinned) on a bounded sample, run before the GPU is used
+  parity       GPU vs the oracle on a 1/8-scale replica of the headline workload, 2 steps
 """
 import argparse
 import hashlib
@@ -30,26 +41,102 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-updates/s per Newton step, p50/p99 latency; FP32-mixed vs FP64 at 1e-8 resid"
 
-
-WORKLOAD = "footing2d_large"
 DESCR = {
+    "footing3d": "footing3d: 3D trilinear quasi-static rigid square-footing quarter-model, 96^3 cells (h=0.125 m) "
+                 "+2 empty layers, 7,077,888 points, 931,491 nodes, neo-Hookean E=10 MPa nu=0.3, k=1e-12, "
+                 "dt=0.1 s, 5 mm/step, Newton 1e-8 per residual block",
     "footing2d_large": "footing2d_large: 2D GIMP quasi-static rigid-footing half-model, 512x256 cells (h=0.0625 m) "
                        "+16 empty rows, 524,288 points, neo-Hookean E=10 MPa nu=0.3, k from seed 0, "
                        "dt=0.1 s, 5 mm/step, Newton 1e-8 per residual block",
-    "footing3d": "footing3d: 3D trilinear quasi-static rigid square-footing quarter-model, 96^3 cells (h=0.125 m) "
-                 "+2 empty layers, 7,077,888 points, neo-Hookean E=10 MPa nu=0.3, k=1e-12, dt=0.1 s, "
-                 "5 mm/step, Newton 1e-8 per residual block",
 }
 
 
-def workload(scale: int = 1):
+def workload(name, scale: int = 1):
     from paper_1905_00671_amd import workloads as W
-    if WORKLOAD == "footing3d":
+    if name == "footing3d":
         n = 96 // scale
         return W.footing3d(n=n, size=12.0 * n / 96, half_b=max(0.25, 1.0 * n / 96))
     return W.config(3, nx=512 // scale, ny=256 // scale, width=32.0 / scale, empty_rows=max(2, 16 // scale))
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------------------------
+# CPU oracle baseline (a child process pinned to one core, run before this process touches the GPU)
+# ---------------------------------------------------------------------------------------------
+CPU_SAMPLE = r"""
+import os, sys, time, json
+os.sched_setaffinity(0, {{{core}}})
+sys.path.insert(0, {root!r})
+import numpy as np
+from oracle import oracle as O
+from paper_1905_00671_amd import workloads as W
+out = {{}}
+# (1) two full time steps of a replica of the workload (SuperLU direct solve)
+if {name!r} == "footing3d":
+    w = W.footing3d(n=12, size=1.5, half_b=0.25)
+else:
+    w = W.config(3, nx=128, ny=64, width=8.0, empty_rows=4)
+pr = O.from_workload(w)
+t0 = time.perf_counter(); newton = 0; t_asm = 0.0
+for n in (1, 2):
+    st = pr.step(w.dt, w.bc(n)); newton += st["newton_iters"]; t_asm += st["t_assemble"]
+out["replica"] = dict(seconds=time.perf_counter() - t0, newton=newton, np=pr.np, t_assemble=t_asm)
+# (2) the residual of the full-size workload at its first Newton iterate (the residual alone: the
+#     oracle's local Jacobians would take about a minute more at 7M points)
+if {full}:
+    if {name!r} == "footing3d":
+        w = W.footing3d()
+    else:
+        w = W.config(3)
+    pr = O.from_workload(w)
+    nodal = pr.p2g()
+    g, d = w.grid, w.grid.dim
+    U = np.zeros((g.nnode, d)); P = nodal["Pn"].copy()
+    t0 = time.perf_counter()
+    pr.assemble(U, P, nodal, w.dt, want_J=False)
+    out["fullsize_assembly"] = dict(seconds=time.perf_counter() - t0, np=pr.np)
+print(json.dumps(out))
+"""
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, full=True):
+    core = sorted(os.sched_getaffinity(0))[0]
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    src = CPU_SAMPLE.format(root=ROOT, name=name, core=core, full=full)
+    t0 = time.perf_counter()
+    r = subprocess.run([sys.executable, "-c", src], capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        return dict(error=r.stderr[-400:])
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    rep = d["replica"]
+    out = dict(value=rep["np"] * rep["newton"] / rep["seconds"], unit="particle-updates/s", cores=1, kind="oracle",
+               sample=(f"2 full time steps ({rep['newton']} Newton iterations, exact Jacobian, SuperLU direct solve) "
+                       f"of a {'12^3-cell' if name == 'footing3d' else '128x64-cell'} replica of the workload "
+                       f"({rep['np']} points) in {rep['seconds']:.1f} s, of which assembly {rep['t_assemble']:.1f} s"),
+               core=core, nproc=os.cpu_count(), cpu_model=cpu_model(), wall_s=time.perf_counter() - t0)
+    if "fullsize_assembly" in d:
+        fa = d["fullsize_assembly"]
+        out["fullsize_assembly"] = dict(seconds=fa["seconds"], points=fa["np"],
+                                        what="residual of the full-size workload at its first Newton iterate, one core")
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# GPU runs
+# ---------------------------------------------------------------------------------------------
 def device_bcs(w, steps):
     import torch
     out = {}
@@ -60,17 +147,17 @@ def device_bcs(w, steps):
     return out
 
 
-def run_path(w, precision, warmup, steps, bcs):
+def run_path(w, precision, warmup, steps, bcs, tag="", **over):
     import torch
     from paper_1905_00671_amd import binding as B
-    p = B.Problem.from_workload(w, precision=precision)
+    p = B.Problem.from_workload(w, precision=precision, **over)
     try:
         for n in range(1, warmup + 1):
             ts = time.perf_counter()
             st = p.step(w.dt, bcs[n])
             torch.cuda.synchronize()
-            print(f"[bench] precision={precision} warm-up step {n}: {(time.perf_counter() - ts) * 1e3:.1f} ms "
-                  f"newton={st['newton_iters']} krylov={st['krylov_iters']}", file=sys.stderr, flush=True)
+            log(f"{tag} precision={precision} warm-up step {n}: {(time.perf_counter() - ts) * 1e3:.1f} ms "
+                f"newton={st['newton_iters']} krylov={st['krylov_iters']}")
         torch.cuda.synchronize()
         B.timing_reset()
         B.timing_enable(True)
@@ -81,12 +168,13 @@ def run_path(w, precision, warmup, steps, bcs):
             st = p.step(w.dt, bcs[n])
             lat.append(time.perf_counter() - ts)
             stats.append(st)
-            print(f"[bench] precision={precision} step {n}: {lat[-1] * 1e3:.1f} ms newton={st['newton_iters']} "
-                  f"krylov={st['krylov_iters']}", file=sys.stderr, flush=True)
+            log(f"{tag} precision={precision} step {n}: {lat[-1] * 1e3:.1f} ms newton={st['newton_iters']} "
+                f"krylov={st['krylov_iters']}")
         torch.cuda.synchronize()
         T = time.perf_counter() - t0
         B.timing_enable(False)
         kt = B.timing_get()
+        ws_bytes = p.workspace_bytes
     finally:
         p.close()
     npt = w.particles.n
@@ -109,92 +197,128 @@ def run_path(w, precision, warmup, steps, bcs):
                      krylov=sum(s["t_krylov"] for s in stats), sort=sum(s["t_sort"] for s in stats),
                      g2p=sum(s["t_g2p"] for s in stats)),
         kernels=kt,
+        hbm_footprint_bytes=ws_bytes,
     )
+
+
+def stencil(w):
+    return 25 if w.options.shape == 1 else (9 if w.grid.dim == 2 else 27)
 
 
 def spmv_roofline(w, kt, precision):
     """Algorithmic bytes of one SpMV launch: every stored block of the fixed-stencil rows once
     (S b^2 words per grid node), the input vector once, the output and the dot-product vector."""
     g = w.grid
-    nnode = g.nnode
     b = g.dim + 1
-    S = 25 if w.options.shape == 1 else (9 if g.dim == 2 else 27)
     word = 8 if precision == 0 else 4
-    bytes_per_launch = nnode * (S * b * b + 3 * b) * word
+    bytes_per_launch = g.nnode * (stencil(w) * b * b + 3 * b) * word
     k = kt["spmv"]
     if k["launches"] == 0:
         return None
     avg_s = k["total_ms"] / k["launches"] * 1e-3
     achieved = bytes_per_launch / avg_s / 1e9
     return dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                traffic=None, kernel="k_spmv (stencil block-CSR SpMV)", bytes_per_launch=bytes_per_launch,
+                traffic=None, kernel="k_spmv (fixed-stencil block-row SpMV)", bytes_per_launch=bytes_per_launch,
                 avg_launch_us=avg_s * 1e6, launches=k["launches"])
 
 
-def spmv_source_digest():
-    """sha256 of the SpMV kernel's source text (template line to closing brace)."""
-    src = open(os.path.join(ROOT, "paper_1905_00671_amd", "csrc", "kern_solver.hip")).read()
-    a = src.index("template <int DIM, int R, typename T>\n__global__ void __launch_bounds__(TPB) k_spmv(")
+def assembly_roofline(w, kt, precision):
+    """Jacobian assembly of one Newton iteration: the stencil block rows written once
+    (S b^2 words per grid node) are its algorithmic bytes (the point data it reads is a few
+    percent of that); time = the Jacobian kernels' launch time per assembly."""
+    g = w.grid
+    b = g.dim + 1
+    word = 8 if precision == 0 else 4
+    jbytes = g.nnode * stencil(w) * b * b * word
+    k = kt["jacobian"]
+    if k["launches"] == 0:
+        return None
+    avg_s = k["total_ms"] / k["launches"] * 1e-3
+    achieved = jbytes / avg_s / 1e9
+    out = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+               traffic=None, kernel="Jacobian assembly (stencil block rows)", bytes_per_launch=jbytes,
+               avg_launch_us=avg_s * 1e6, launches=k["launches"])
+    r = kt["records"]
+    if r["launches"]:
+        out["records_avg_us"] = r["total_ms"] / r["launches"] * 1e3
+    r = kt["residual"]
+    if r["launches"]:
+        out["residual_avg_us"] = r["total_ms"] / r["launches"] * 1e3
+    return out
+
+
+def kernel_digest(fname, signature):
+    """sha256 of a kernel's source text (signature line to closing brace)."""
+    src = open(os.path.join(ROOT, "paper_1905_00671_amd", "csrc", fname)).read()
+    a = src.index(signature)
     b = src.index("\n}\n", a) + 3
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def pmc_traffic(roof, precision):
-    """HBM bytes per SpMV launch from the committed rocprofv3 counter summary (FETCH_SIZE and
-    WRITE_SIZE scaled by the copy-kernel calibration), if it was taken on the current kernel
-    source; None otherwise."""
-    path = os.path.join(ROOT, "profiles", "spmv_footing2d_large_pmc.txt")
-    if roof is None or not os.path.exists(path):
+SPMV_SIG = "template <int DIM, int R, typename T>\n__global__ void __launch_bounds__(TPB) k_spmv("
+
+
+def pmc_traffic(name, precision, kernel="spmv"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this workload and
+    kernel (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), if the summary names
+    this workload and precision and was taken on the current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_pmc.txt")
+    if not os.path.exists(path):
         return None
     try:
-        digest, per = None, {}
+        digest, per, wl = None, {}, None
         for line in open(path):
             if line.startswith("kernel_source_sha256:"):
                 digest = line.split(":", 1)[1].strip()
+            if line.startswith("workload:"):
+                wl = line.split(":", 1)[1].strip().split()[0]
             m = re.match(r"^(fp64|mixed):.*hbm_bytes_per_launch=([0-9.eE+]+)", line)
             if m:
                 per[m.group(1)] = float(m.group(2))
-        if digest != spmv_source_digest():
+        if wl != name or kernel != "spmv" or digest != kernel_digest("kern_solver.hip", SPMV_SIG):
             return None
         return per.get("fp64" if precision == 0 else "mixed")
     except Exception:
         return None
 
 
-CPU_SAMPLE = r"""
-import os, sys, time, json
-sys.path.insert(0, {root!r})
-from oracle import oracle as O
-from paper_1905_00671_amd import workloads as W
-w = W.config(3, nx=128, ny=64, width=8.0, empty_rows=4)
-pr = O.from_workload(w)
-t0 = time.perf_counter(); newton = 0
-for n in (1, 2):
-    st = pr.step(w.dt, w.bc(n)); newton += st["newton_iters"]
-T = time.perf_counter() - t0
-print(json.dumps(dict(seconds=T, newton=newton, np=pr.np)))
-"""
+def bench_workload(name, warmup, steps, control=True):
+    """FP64 and mixed paths (and the FP64 control at the mixed Krylov tolerance) on one workload."""
+    w = workload(name)
+    t = time.perf_counter()
+    bcs = device_bcs(w, range(1, warmup + steps + 1))
+    log(f"{name}: {w.particles.n} points, {w.grid.nnode} nodes, inputs on the device in {time.perf_counter() - t:.1f} s")
+    res = {"fp64": run_path(w, 0, warmup, steps, bcs, name), "mixed": run_path(w, 1, warmup, steps, bcs, name)}
+    if control:
+        res["fp64_krylov_1e-6"] = run_path(w, 0, warmup, steps, bcs, name + " control", krylov_rtol=1e-6)
+    out = {}
+    for key, r in res.items():
+        prec = 1 if key == "mixed" else 0
+        out[key] = {k: r[k] for k in ("particle_updates_per_s", "particle_steps_per_s", "ms_per_step", "latency_ms",
+                                      "newton_iters", "krylov_iters", "newton_per_step", "krylov_per_newton",
+                                      "final_rel_residual", "phase_s", "hbm_footprint_bytes")}
+        out[key]["kernels_ms"] = {k: v for k, v in r["kernels"].items() if v["launches"]}
+        roof = spmv_roofline(w, r["kernels"], prec)
+        if roof is not None:
+            roof["traffic"] = pmc_traffic(name, prec)
+        out[key]["roofline"] = roof
+        out[key]["assembly_roofline"] = assembly_roofline(w, r["kernels"], prec)
+    out["mixed_vs_fp64"] = dict(
+        particle_steps_ratio=res["mixed"]["particle_steps_per_s"] / res["fp64"]["particle_steps_per_s"],
+        particle_updates_ratio=res["mixed"]["particle_updates_per_s"] / res["fp64"]["particle_updates_per_s"])
+    if control:
+        out["mixed_vs_fp64"]["particle_steps_ratio_vs_fp64_krylov_1e-6"] = (
+            res["mixed"]["particle_steps_per_s"] / res["fp64_krylov_1e-6"]["particle_steps_per_s"])
+    return w, res, out
 
 
-def cpu_baseline():
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-c", CPU_SAMPLE.format(root=ROOT)], capture_output=True, text=True,
-                       env=env, timeout=600)
-    if r.returncode != 0:
-        return dict(error=r.stderr[-400:])
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    return dict(value=d["np"] * d["newton"] / d["seconds"], unit="particle-updates/s", cores=1, kind="oracle",
-                sample=f"2 full time steps ({d['newton']} Newton iterations, SuperLU direct solve) of a 128x64-cell "
-                       f"replica of the footing workload ({d['np']} points), single thread, {d['seconds']:.1f} s",
-                seconds=d["seconds"])
-
-
-def parity_check():
-    """GPU (both precisions) vs the oracle on a 64x32 replica, 2 steps, default tolerances."""
+def parity_check(name):
+    """GPU (both precisions) vs the oracle on a 1/8-scale replica, 2 steps, default tolerances;
+    element-wise errors of u and p over all points."""
     from oracle import oracle as O
     from paper_1905_00671_amd import binding as B
     out = {}
-    w = workload(scale=8)
+    w = workload(name, scale=8)
     pr = O.from_workload(w)
     probs = {0: B.Problem.from_workload(w, precision=0), 1: B.Problem.from_workload(w, precision=1)}
     try:
@@ -203,13 +327,14 @@ def parity_check():
             pr.step(w.dt, w.bc(n))
             for prec, p in probs.items():
                 p.step(w.dt, w.bc(n))
-                eu = np.linalg.norm(p.get("u") - pr.u) / np.linalg.norm(pr.u)
-                ep = np.linalg.norm(p.get("p") - pr.p) / max(np.linalg.norm(pr.p), 1e-300)
+                eu = np.abs(p.get("u") - pr.u).max() / np.abs(pr.u).max()
+                ep = np.abs(p.get("p") - pr.p).max() / max(np.abs(pr.p).max(), 1e-3 * np.abs(pr.sig).max())
                 worst[prec][0] = max(worst[prec][0], eu)
                 worst[prec][1] = max(worst[prec][1], ep)
-        for prec, name in ((0, "fp64"), (1, "mixed")):
-            out[name] = dict(rel_err_u=worst[prec][0], rel_err_p=worst[prec][1])
-        out["case"] = f"1/8-scale replica of the workload ({w.particles.n} points), 2 steps, Newton 1e-8, vs FP64 oracle"
+        for prec, key in ((0, "fp64"), (1, "mixed")):
+            out[key] = dict(max_rel_err_u=worst[prec][0], max_rel_err_p=worst[prec][1])
+        out["case"] = (f"1/8-scale replica of the workload ({w.particles.n} points), 2 steps, Newton 1e-8, "
+                       f"element-wise vs the FP64 oracle")
     finally:
         for p in probs.values():
             p.close()
@@ -224,127 +349,118 @@ def serve_bench(nreq, realtime):
     from paper_1905_00671_amd import workloads as W
     trace = W.serving_trace(nreq=nreq)
     out = {}
-    for name, prec in (("fp64", 0), ("mixed", 1)):
+    for key, prec in (("fp64", 0), ("mixed", 1)):
         free, _ = torch.cuda.mem_get_info()
         budget = int(0.8 * free)
         rep = S.serve(trace, budget, realtime=realtime, **S.gpu_backend(prec))
         torch.cuda.synchronize()
-        out[name] = rep.summary()
-        out[name]["budget_bytes"] = budget
-        print(f"[serve] {name}: {out[name]}", file=sys.stderr, flush=True)
-    line = {
-        "metric": "serving: particle-steps/s with continuous batching; p50/p99 step and request latency",
-        "value": out["fp64"]["particle_steps_per_s"],
-        "unit": "particle-steps/s",
-        "n_gpus": 1,
-        "higher_is_better": True,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"serving stream: {nreq} requests, Poisson arrivals at 20/s, 2D n=16..256 "
-                               f"(log-uniform), k=1e-16..1e-10, 20-50 steps, 50/50 consolidation (linear) / "
-                               f"footing (GIMP), dt=0.1 s, {'real-time arrivals' if realtime else 'idle gaps skipped'}"},
+        out[key] = rep.summary()
+        out[key]["budget_bytes"] = budget
+        log(f"serve {key}: {json.dumps(out[key])}")
+    return {
+        "workload": (f"serving stream: {nreq} requests, Poisson arrivals at 20/s, 2D n=16..256 (log-uniform), "
+                     f"k=1e-16..1e-10, 20-50 steps, 50/50 consolidation (original MPM) / footing (GIMP), dt=0.1 s, "
+                     f"Newton 1e-8 per block, {'real-time arrivals' if realtime else 'idle gaps skipped'}, "
+                     f"admission by workspace bytes within 80% of free HBM"),
         "fp64": out["fp64"],
         "mixed": out["mixed"],
-        "mixed_vs_fp64": out["mixed"]["particle_steps_per_s"] / max(out["fp64"]["particle_steps_per_s"], 1e-300),
+        "mixed_vs_fp64": dict(
+            particle_steps_ratio=out["mixed"]["particle_steps_per_s"] / max(out["fp64"]["particle_steps_per_s"], 1e-300),
+            particle_updates_ratio=out["mixed"]["particle_updates_per_s"] / max(out["fp64"]["particle_updates_per_s"],
+                                                                                 1e-300)),
     }
-    print(json.dumps(line))
 
 
 def main():
-    global WORKLOAD
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(DESCR), default="footing3d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--workload", choices=sorted(DESCR), default=WORKLOAD)
-    ap.add_argument("--serve", action="store_true",
-                    help="run the serving stream (continuous batching) instead of the footing step benchmark")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline workload only (no 2D footing, serving stream or FP64 Krylov control)")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving stream")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-no-wait", action="store_true", help="skip idle gaps between arrivals")
     ap.add_argument("--calibrate-mb", type=int, default=0,
                     help="before the run, stream a float32 tensor of this many MiB through one elementwise "
                          "kernel (read once, write once): the reference for hardware byte counters")
     args = ap.parse_args()
-    WORKLOAD = args.workload
     if args.gpus != 1:
         print(f"bench.py measures one MI355X: --gpus {args.gpus} is not supported (the library runs the hot path "
               f"on a single GPU; the multi-GPU decomposition is a design only).", file=sys.stderr)
         sys.exit(2)
+    name = args.workload
+    cpu = None
+    if not args.no_cpu_baseline and not args.serve_only:
+        log("CPU oracle baseline (one pinned core) before the GPU is used")
+        cpu = cpu_baseline(name)
+        log(f"cpu_baseline: {json.dumps(cpu)}")
     import torch
     assert torch.cuda.is_available(), "a GPU is required"
     from paper_1905_00671_amd import binding as B
     B.lib()
-    if args.serve:
-        serve_bench(args.serve_requests, not args.serve_no_wait)
+    if args.serve_only:
+        line = serve_bench(args.serve_requests, not args.serve_no_wait)
+        line.update(metric="serving: particle-steps/s with continuous batching; p50/p99 step and request latency",
+                    value=line["fp64"]["particle_steps_per_s"], unit="particle-steps/s", n_gpus=1,
+                    higher_is_better=True, dtype="f64", data="synthetic")
+        print(json.dumps(line))
         return
     if args.calibrate_mb > 0:
         a = torch.ones(args.calibrate_mb * 262144, dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
         b = a.mul(2.0)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy: {a.numel() * 4} bytes read, {b.numel() * 4} bytes written",
-              file=sys.stderr, flush=True)
+        log(f"calibration copy: {a.numel() * 4} bytes read, {b.numel() * 4} bytes written")
         del a, b
-    w = workload()
-    bcs = device_bcs(w, range(1, args.warmup + args.steps + 1))
-    res = {}
-    if args.precision in ("both", "fp64"):
-        res["fp64"] = run_path(w, 0, args.warmup, args.steps, bcs)
-    if args.precision in ("both", "mixed"):
-        res["mixed"] = run_path(w, 1, args.warmup, args.steps, bcs)
-    head = res.get("fp64") or res.get("mixed")
-    head_prec = 0 if "fp64" in res else 1
-    roof = spmv_roofline(w, head["kernels"], head_prec)
-    if roof is not None:
-        roof["traffic"] = pmc_traffic(roof, head_prec)
+    w, res, head = bench_workload(name, args.warmup, args.steps, control=not args.no_extra)
+    fp = res["fp64"]
     line = {
         "metric": METRIC,
-        "value": head["particle_updates_per_s"],
+        "value": fp["particle_updates_per_s"],
         "unit": "particle-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
+        "ms_per_step": fp["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head_prec == 0 else "mixed-f32/f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": DESCR[WORKLOAD],
+            "workload": DESCR[name],
             "points": w.particles.n,
             "grid_nodes": w.grid.nnode,
             "dofs": w.grid.nnode * (w.grid.dim + 1),
             "k_m2": w.meta["k"],
         },
-        "latency_ms": head["latency_ms"],
-        "particle_steps_per_s": head["particle_steps_per_s"],
-        "newton_iters": head["newton_iters"],
-        "krylov_iters": head["krylov_iters"],
-        "roofline": roof,
+        "latency_ms": fp["latency_ms"],
+        "particle_steps_per_s": fp["particle_steps_per_s"],
+        "newton_iters": fp["newton_iters"],
+        "krylov_iters": fp["krylov_iters"],
+        "hbm_footprint_bytes": {"fp64": res["fp64"]["hbm_footprint_bytes"], "mixed": res["mixed"]["hbm_footprint_bytes"]},
+        "roofline": head["fp64"]["roofline"],
+        "fp64": head["fp64"],
+        "mixed": head["mixed"],
+        "mixed_vs_fp64": head["mixed_vs_fp64"],
     }
-    for name in ("fp64", "mixed"):
-        if name in res:
-            r = res[name]
-            line[name] = {k: r[k] for k in ("particle_updates_per_s", "particle_steps_per_s", "ms_per_step",
-                                            "latency_ms", "newton_iters", "krylov_iters", "newton_per_step",
-                                            "krylov_per_newton", "final_rel_residual", "phase_s")}
-            line[name]["kernels_ms"] = {k: v for k, v in r["kernels"].items() if v["launches"]}
-    if "fp64" in res and "mixed" in res:
-        line["mixed_vs_fp64"] = dict(
-            particle_steps_ratio=res["mixed"]["particle_steps_per_s"] / res["fp64"]["particle_steps_per_s"],
-            particle_updates_ratio=res["mixed"]["particle_updates_per_s"] / res["fp64"]["particle_updates_per_s"])
-        roof32 = spmv_roofline(w, res["mixed"]["kernels"], 1)
-        if roof32 is not None:
-            roof32["traffic"] = pmc_traffic(roof32, 1)
-        line["mixed"]["roofline"] = roof32
+    if "fp64_krylov_1e-6" in head:
+        line["fp64_krylov_1e-6"] = head["fp64_krylov_1e-6"]
+    if not args.no_extra:
+        other = "footing2d_large" if name == "footing3d" else "footing3d"
+        _, _, sub = bench_workload(other, 2 if other == "footing2d_large" else 1,
+                                   6 if other == "footing2d_large" else 2, control=False)
+        sub["workload"] = DESCR[other]
+        line[other] = sub
+        line["serving"] = serve_bench(args.serve_requests, not args.serve_no_wait)
     if not args.no_parity:
-        line["parity"] = parity_check()
-    if not args.no_cpu_baseline and WORKLOAD == "footing2d_large":
-        line["cpu_baseline"] = cpu_baseline()
+        line["parity"] = parity_check(name)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line))
 
 

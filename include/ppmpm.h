@@ -18,7 +18,8 @@
  *   - `where` = PPMPM_HOST or PPMPM_DEVICE says whether a caller pointer is host memory or
  *     device memory of the problem's GPU.  The caller owns every array it passes; the library
  *     copies inputs into its workspace and never frees caller memory.
- *   - All device work is enqueued on the caller's HIP stream (hipStream_t passed as void*).
+ *   - All device work is enqueued on the caller's HIP stream (hipStream_t passed as void*);
+ *     ppmpm_step_batched also runs kernel-variant groups on streams of its own (see there).
  *     ppmpm_step returns after its statistics are available (it synchronizes the stream once
  *     per Newton iteration and a few times per Krylov solve).
  *   - A problem is not thread-safe.  Problems stepped together by ppmpm_step_batched must share
@@ -75,6 +76,9 @@ typedef struct {
     double E, nu, k, mu_f, rho_f;
     double g[3];
     double phi0;
+    double alpha_vis;  /* Kelvin-type damping parameter (s), Sec. 2.2: sigma'_vis = alpha_vis c : sym(l),
+                          c = lambda 1 (x) 1 + 2 G I (the tangent at the undeformed state); used by
+                          dynamic problems only (eq. quasi-static-condition), >= 0 */
 } ppmpm_material;
 
 /* Method options.
@@ -129,7 +133,9 @@ typedef struct {
 #define PPMPM_MAX_HIST 64
 /* Per-step statistics.  res_u/res_p: L2 norms of the momentum and mass residual blocks at each
  * Newton iteration (free degrees of freedom only); krylov_iters per Newton iteration; times in
- * seconds measured on the host around the synchronized phases. */
+ * seconds measured on the host around the synchronized phases.  The Jacobian and preconditioner
+ * set-up (t_precond) is timed apart only while kernel timing is enabled (ppmpm_timing_enable);
+ * otherwise it is part of t_krylov and t_precond is 0. */
 typedef struct {
     int status;
     int newton_iters;
@@ -172,10 +178,16 @@ ppmpm_status ppmpm_set_particles(ppmpm_problem* p, int64_t np, const double* x, 
 ppmpm_status ppmpm_step(ppmpm_problem* p, double dt, const ppmpm_bc* bc, ppmpm_step_stats* stats);
 
 /* Steps nprob problems together: one kernel launch per phase over all problems that share a
- * kernel variant (dimension, basis, precision), each problem converging independently.
- * dt[nprob], bcs[nprob], stats[nprob] (per-problem status in stats[i].status).  Returns
- * PPMPM_OK if every problem succeeded, otherwise the first failing status; a failing problem
- * does not affect the others. */
+ * kernel variant (dimension, basis, precision) and Krylov options (krylov_rtol, krylov_max,
+ * krylov_check), each problem converging independently.  The groups advance in lockstep, the
+ * first on the problems' stream and the others on streams the library creates (default
+ * priority, kept until the process ends), so that their work overlaps on the device; the call
+ * returns after all of it has completed.  dt[nprob], bcs[nprob], stats[nprob]: every
+ * stats[i].status is set, also when the call fails (a problem the step did not finish carries
+ * the call's failure).  A problem without particles, with dt <= 0 or on another stream than the
+ * first valid problem of the batch gets PPMPM_E_INVALID and is not stepped; the others are.
+ * Returns PPMPM_OK if every problem succeeded, otherwise the first failing status; a failing
+ * problem does not affect the others. */
 ppmpm_status ppmpm_step_batched(ppmpm_problem* const* probs, int nprob, const double* dt,
                                 const ppmpm_bc* const* bcs, ppmpm_step_stats* stats);
 
@@ -221,9 +233,10 @@ const char* ppmpm_last_error(void);
  * of launches and their summed duration in milliseconds since the last reset.
  *   0 SpMV of the Krylov solver   1 Jacobian block rows   2 quadrature records   3 residual
  *   4 multigrid residual on the finest level   5 P2G   6 G2P   7 sort permutation
- *   8 Galerkin coarse operators */
+ *   8 Galerkin coarse operators   9 3D cell matrices (the block rows of 3D problems are then
+ *   summed from them by launch 1) */
 enum { PPMPM_K_SPMV = 0, PPMPM_K_JACOBIAN, PPMPM_K_RECORDS, PPMPM_K_RESIDUAL, PPMPM_K_MG0_RESID,
-       PPMPM_K_P2G, PPMPM_K_G2P, PPMPM_K_PERMUTE, PPMPM_K_RAP, PPMPM_K_COUNT };
+       PPMPM_K_P2G, PPMPM_K_G2P, PPMPM_K_PERMUTE, PPMPM_K_RAP, PPMPM_K_CELLMAT, PPMPM_K_COUNT };
 ppmpm_status ppmpm_timing_enable(int on);
 ppmpm_status ppmpm_timing_reset(void);
 ppmpm_status ppmpm_timing_get(int kernel, int64_t* launches, double* total_ms);

@@ -36,7 +36,7 @@ class Grid(ctypes.Structure):
 class Material(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("E", ctypes.c_double), ("nu", ctypes.c_double),
                 ("k", ctypes.c_double), ("mu_f", ctypes.c_double), ("rho_f", ctypes.c_double),
-                ("g", ctypes.c_double * 3), ("phi0", ctypes.c_double)]
+                ("g", ctypes.c_double * 3), ("phi0", ctypes.c_double), ("alpha_vis", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -141,7 +141,8 @@ def make_grid(g) -> Grid:
 def make_material(m) -> Material:
     gv = list(m.g) + [0.0] * 3
     kc = m.phi0 if getattr(m, "kozeny_carman", False) else 0.0
-    return Material(m.model, m.E, m.nu, m.k, m.mu_f, m.rho_f, (ctypes.c_double * 3)(*gv[:3]), kc)
+    return Material(m.model, m.E, m.nu, m.k, m.mu_f, m.rho_f, (ctypes.c_double * 3)(*gv[:3]), kc,
+                    float(getattr(m, "alpha_vis", 0.0)))
 
 
 def make_options(o, precision: int = FP64, **over) -> Options:
@@ -282,11 +283,13 @@ def step_batched(problems: Sequence[Problem], dts: Sequence[float], bcs: Sequenc
     keep = [BCArrays(b) for b in bcs]
     bptr = (ctypes.c_void_p * n)(*[ctypes.addressof(k.c) for k in keep])
     stats = (StepStats * n)()
-    L.ppmpm_step_batched(arr, n, dt, bptr, stats)
+    s = L.ppmpm_step_batched(arr, n, dt, bptr, stats)
+    if s in (E_DEVICE, E_OOM):
+        _check(s)            # a failure of the batch itself, not of one problem
     return [stats[i].as_dict() for i in range(n)]
 
 
-KERNELS = ["spmv", "jacobian", "records", "residual", "mg0_resid", "p2g", "g2p", "permute", "rap"]
+KERNELS = ["spmv", "jacobian", "records", "residual", "mg0_resid", "p2g", "g2p", "permute", "rap", "cellmat"]
 
 
 def timing_enable(on: bool = True):

@@ -20,9 +20,15 @@ def build(force: bool = True, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
 
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    headers.append(os.path.join(os.path.dirname(HERE), "include", "ppmpm.h"))
+    newest_header = max(os.path.getmtime(h) for h in headers)
+
     def one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        if not force and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(path), newest_header):
+            return obj
         cmd = ["hipcc"] + FLAGS + ["-c", path, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
@@ -43,4 +49,4 @@ def build(force: bool = True, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(force="--incremental" not in sys.argv, verbose=True))

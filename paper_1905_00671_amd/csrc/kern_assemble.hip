@@ -171,11 +171,29 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     }
     double wv[DIM];
     for (int a = 0; a < DIM; ++a) wv[a] = gp[a] - d->rho_f * (d->g[a] - ah[a]);
-    // Kirchhoff stress and the tangent with the geometric and pressure terms folded in
+    // Kelvin-type viscous stress of the Newmark velocity field, sigma_vis = alpha (lam tr l 1 +
+    // G (l + l^T)); its linearization is folded into the 2D tangent below and formed in closed
+    // form by the 3D cell-matrix kernel
+    const bool vis = dyn && d->alpha_vis != 0.0;
+    double svis[DIM * DIM];
+    for (int k = 0; k < DIM * DIM; ++k) svis[k] = 0.0;
+    if (vis) {
+        const double al = d->alpha_vis;
+        double tr = 0.0;
+        for (int a = 0; a < DIM; ++a) tr += l[a * DIM + a];
+        for (int a = 0; a < DIM; ++a)
+            for (int c = 0; c < DIM; ++c)
+                svis[a * DIM + c] = al * (d->G * (l[a * DIM + c] + l[c * DIM + a]) + (a == c ? d->lam * tr : 0.0));
+    }
+    // Kirchhoff stress; 2D: the tangent with the geometric, pressure and damping terms folded in,
+    // with w_c = gamma/(beta dt) e_c - l e_c the damping terms are
+    //   dAbar_{ab,ce} = -dv alpha (lam d_ab w_c^e + G d_be w_c^a + G d_ae w_c^b)
+    //                   - dv svis_ab d_ce + dv svis_ae d_bc
     double tau[DIM * DIM], tzz;
     if constexpr (DIM == 2) {
         double T[16];
         kirchhoff_tangent<2>(d->model, d->lam, d->G, F, tau, &tzz, T);
+        const double al = d->alpha_vis, vg = ga / (be * dt);
         for (int a = 0; a < DIM; ++a)
             for (int bb = 0; bb < DIM; ++bb)
                 for (int c = 0; c < DIM; ++c)
@@ -184,10 +202,23 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
                         if (bb == c) v += V0 * tau[a * DIM + e];
                         if (a == bb && c == e) v += dv * ph;
                         if (a == e && bb == c) v -= dv * ph;
+                        if (vis) {
+                            // w_c^m = vg d_mc - l_mc
+                            const double wce = (e == c ? vg : 0.0) - l[e * DIM + c];
+                            const double wca = (a == c ? vg : 0.0) - l[a * DIM + c];
+                            const double wcb = (bb == c ? vg : 0.0) - l[bb * DIM + c];
+                            double t = 0.0;
+                            if (a == bb) t += d->lam * wce;
+                            if (bb == e) t += d->G * wca;
+                            if (a == e) t += d->G * wcb;
+                            v -= dv * al * t;
+                            if (c == e) v -= dv * svis[a * DIM + bb];
+                            if (bb == c) v += dv * svis[a * DIM + e];
+                        }
                         rec[L::AB_ + ((a * DIM + bb) * DIM + c) * DIM + e] = v;
                     }
     } else {
-        // neo-Hookean (the 3D model): T_{ab,ce} = G (d_ac b_eb + b_ae d_bc) + lambda d_ab d_ce
+        // neo-Hookean (the 3D model): the closed-form coefficients of the displacement block
         kirchhoff_tangent<3>(d->model, d->lam, d->G, F, tau, &tzz, nullptr);
         double bm[9];
         for (int a = 0; a < 3; ++a)
@@ -196,25 +227,28 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
                 for (int k = 0; k < 3; ++k) t += F[a * 3 + k] * F[c * 3 + k];
                 bm[a * 3 + c] = t;
             }
-        const double Gm = d->G, lam = d->lam;
-        for (int a = 0; a < 3; ++a)
-            for (int bb = 0; bb < 3; ++bb)
-                for (int c = 0; c < 3; ++c)
-                    for (int e = 0; e < 3; ++e) {
-                        double Tv = (a == c ? Gm * bm[e * 3 + bb] : 0.0) + (bb == c ? Gm * bm[a * 3 + e] : 0.0) +
-                                    (a == bb && c == e ? lam : 0.0);
-                        double v = -V0 * Tv;
-                        if (bb == c) v += V0 * tau[a * 3 + e];
-                        if (a == bb && c == e) v += dv * ph;
-                        if (a == e && bb == c) v -= dv * ph;
-                        rec[L::AB_ + ((a * 3 + bb) * 3 + c) * 3 + e] = v;
-                    }
+        const double lnJ = log(det<3>(F));   // as in the Kirchhoff stress
+        rec[L::VG_] = V0 * d->G;
+        rec[L::BM_ + 0] = bm[0];
+        rec[L::BM_ + 1] = bm[4];
+        rec[L::BM_ + 2] = bm[8];
+        rec[L::BM_ + 3] = bm[1];
+        rec[L::BM_ + 4] = bm[5];
+        rec[L::BM_ + 5] = bm[2];
+        rec[L::C1_] = V0 * (d->lam * lnJ - d->G) - dv * ph;
+        rec[L::C2_] = dv * ph - V0 * d->lam;
+        rec[L::SV_ + 0] = svis[0];
+        rec[L::SV_ + 1] = svis[4];
+        rec[L::SV_ + 2] = svis[8];
+        rec[L::SV_ + 3] = svis[1];
+        rec[L::SV_ + 4] = svis[5];
+        rec[L::SV_ + 5] = svis[2];
     }
     for (int k = 0; k < DIM * DIM; ++k) {
         rec[L::FI_ + k] = f[k];
         rec[L::LV_ + k] = dyn ? dv * l[k] : 0.0;
         int a = k / DIM, c = k % DIM;
-        rec[L::SG_ + k] = -V0 * tau[k] + (a == c ? dv * ph : 0.0);
+        rec[L::SG_ + k] = -V0 * tau[k] + (a == c ? dv * ph : 0.0) - dv * svis[k];
     }
     rec[L::DV_] = dv;
     rec[L::CM_] = dyn ? m / (be * dt * dt) : 0.0;
@@ -598,6 +632,213 @@ __global__ void __launch_bounds__(TPB) k_jacobian(Batch B) {
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// 3D Jacobian: cell matrices, then block rows
+// ---------------------------------------------------------------------------------------------
+// Trilinear basis: the points of cell c (its sort bucket) reach exactly the cell's 8 corner
+// nodes, so the Jacobian is the sum of cell matrices K_c = sum_{p in c} (point terms), each
+// 8 x 8 blocks of 4 x 4.  k_cellmat3 forms them with one wavefront per cell and one lane per
+// node pair (i, k) of the cell (lane = 8 i + k, corner index x + 2 y + 4 z): the cell's points
+// are walked in order at wave-uniform addresses, so every lane reads the same record words and
+// computes its own 16 entries from them (no atomics, no redundant point terms); the lanes store
+// K_c as Ke[(c * 16 + e) * 64 + lane], 64 consecutive words per entry.  With gi = dF^{-T} grad_n S_i
+// (likewise gk), the (a, c) entries of the block J_ik are
+//   uu  -V0 G (gi . b gk) d_ac + C1 gk_a gi_c + C2 gi_a gk_c - m/(beta dt^2) S_i S_k d_ac
+//       [Kelvin damping, with l the velocity gradient and v_g = gamma/(beta dt):
+//        - alpha (lam gi_a (dv v_g gk_c - (dv l^T gk)_c) + G (gi . gk)(dv v_g d_ac - dv l_ac)
+//                 + G gk_a (dv v_g gi_c - (dv l^T gi)_c)) - dv (s_vis gi)_a gk_c + dv (s_vis gk)_a gi_c]
+//   up  dv S_k gi_a
+//   pu  S_i (bv gk_c - (dv l^T gk)_c) + dv kappa (gk_c gi.w - gi_c w.gk - (gi . gk) gp_c)
+//       + dv kappa rho_f/(beta dt^2) gi_c S_k  [+ dv J kappa'(J) (gi.w) gk_c, Kozeny-Carman]
+//   pp  dv kappa gi . gk + tau c_t V_n (S_i - Pi_i)(S_k - Pi_k)
+// (the exact derivatives of the residual terms listed at the top of this file; the same
+// entries as the 2D kernel's folded-tangent form).  T is the Jacobian's precision.
+template <typename T, bool DYN, bool VIS>
+__global__ void __launch_bounds__(TPB) k_cellmat3(Batch B) {
+    const int q = batch_find(B, blockIdx.x);
+    const Dev* __restrict__ d = B.d[q];
+    const int64_t lb = blockIdx.x - B.pfx[q];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t c = lb * (TPB / 64) + wave;
+    if (c >= d->Ncell) return;
+    // wave-uniform point range (readfirstlane: the compiler then keeps the record addresses scalar)
+    const int p0 = __builtin_amdgcn_readfirstlane(d->cstart[c]);
+    const int p1 = __builtin_amdgcn_readfirstlane(d->cstart[c + 1]);
+    using L = RecLayout<3, 2>;   // (an empty cell stores a zero matrix)
+    const int i = lane >> 3, k = lane & 7;
+    const int ix = i & 1, iy = (i >> 1) & 1, iz = i >> 2;
+    const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
+    const T Pii = (T)d->cellpi[c * 8 + i], Pik = (T)d->cellpi[c * 8 + k];
+    const bool kc = d->phi0 > 0.0;
+    const T lam = (T)d->lam, Gm = (T)d->G, al = (T)d->alpha_vis, vg = (T)(d->gamma / (d->beta * d->dt));
+    T acc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = T(0);
+    // the records are read-only here and every lane reads the same words: the constant address
+    // space turns them into scalar loads (written by the records kernel, a previous launch)
+    using CRec = const __attribute__((address_space(4))) double*;
+    const CRec rec = (CRec)d->rec;
+    for (int p = p0; p < p1; ++p) {
+        const CRec r = rec + (int64_t)p * L::N;
+        // basis of nodes i and k (reference gradients), then spatial gradients gi, gk; the 1D
+        // values are loaded for both nodes of each axis (uniform) and selected per lane
+        T w1[6], d1[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            w1[e] = (T)r[L::W_ + e];
+            d1[e] = (T)r[L::DW_ + e];
+        }
+        const T wxi = ix ? w1[1] : w1[0], wyi = iy ? w1[3] : w1[2], wzi = iz ? w1[5] : w1[4];
+        const T dxi = ix ? d1[1] : d1[0], dyi = iy ? d1[3] : d1[2], dzi = iz ? d1[5] : d1[4];
+        const T wxk = kx ? w1[1] : w1[0], wyk = ky ? w1[3] : w1[2], wzk = kz ? w1[5] : w1[4];
+        const T dxk = kx ? d1[1] : d1[0], dyk = ky ? d1[3] : d1[2], dzk = kz ? d1[5] : d1[4];
+        const T Si = wxi * wyi * wzi, Sk = wxk * wyk * wzk;
+        const T Gi[3] = {dxi * wyi * wzi, wxi * dyi * wzi, wxi * wyi * dzi};
+        const T Gk[3] = {dxk * wyk * wzk, wxk * dyk * wzk, wxk * wyk * dzk};
+        T f[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) f[e] = (T)r[L::FI_ + e];
+        T gi[3], gk[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gi[a] = f[a] * Gi[0] + f[3 + a] * Gi[1] + f[6 + a] * Gi[2];
+            gk[a] = f[a] * Gk[0] + f[3 + a] * Gk[1] + f[6 + a] * Gk[2];
+        }
+        const T dv = (T)r[L::DV_];
+        const T b00 = (T)r[L::BM_ + 0], b11 = (T)r[L::BM_ + 1], b22 = (T)r[L::BM_ + 2];
+        const T b01 = (T)r[L::BM_ + 3], b12 = (T)r[L::BM_ + 4], b02 = (T)r[L::BM_ + 5];
+        const T bgk[3] = {b00 * gk[0] + b01 * gk[1] + b02 * gk[2], b01 * gk[0] + b11 * gk[1] + b12 * gk[2],
+                          b02 * gk[0] + b12 * gk[1] + b22 * gk[2]};
+        const T gbg = gi[0] * bgk[0] + gi[1] * bgk[1] + gi[2] * bgk[2];
+        const T gigk = gi[0] * gk[0] + gi[1] * gk[1] + gi[2] * gk[2];
+        T diag = -(T)r[L::VG_] * gbg;
+        if (DYN) diag -= (T)r[L::CM_] * Si * Sk;
+        const T C1 = (T)r[L::C1_], C2 = (T)r[L::C2_];
+        T LV[9], lti[3], ltk[3];
+        if (DYN) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) LV[e] = (T)r[L::LV_ + e];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {   // (dv l^T g)_a = sum_e LV[e][a] g_e
+                ltk[a] = LV[a] * gk[0] + LV[3 + a] * gk[1] + LV[6 + a] * gk[2];
+                lti[a] = LV[a] * gi[0] + LV[3 + a] * gi[1] + LV[6 + a] * gi[2];
+            }
+        }
+        // displacement-displacement block
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                T v = C1 * gk[a] * gi[cc] + C2 * gi[a] * gk[cc];
+                if (a == cc) v += diag;
+                acc[a * 4 + cc] += v;
+            }
+        if (VIS) {
+            const T s00 = (T)r[L::SV_ + 0], s11 = (T)r[L::SV_ + 1], s22 = (T)r[L::SV_ + 2];
+            const T s01 = (T)r[L::SV_ + 3], s12 = (T)r[L::SV_ + 4], s02 = (T)r[L::SV_ + 5];
+            const T sgi[3] = {s00 * gi[0] + s01 * gi[1] + s02 * gi[2], s01 * gi[0] + s11 * gi[1] + s12 * gi[2],
+                              s02 * gi[0] + s12 * gi[1] + s22 * gi[2]};
+            const T sgk[3] = {s00 * gk[0] + s01 * gk[1] + s02 * gk[2], s01 * gk[0] + s11 * gk[1] + s12 * gk[2],
+                              s02 * gk[0] + s12 * gk[1] + s22 * gk[2]};
+            const T dvg = dv * vg;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    T t = lam * gi[a] * (dvg * gk[cc] - ltk[cc]) + Gm * gigk * ((a == cc ? dvg : T(0)) - LV[a * 3 + cc]) +
+                          Gm * gk[a] * (dvg * gi[cc] - lti[cc]);
+                    acc[a * 4 + cc] += -al * t - dv * sgi[a] * gk[cc] + dv * sgk[a] * gi[cc];
+                }
+        }
+        // displacement rows, pressure column
+        const T dvs = dv * Sk;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a * 4 + 3] += dvs * gi[a];
+        // pressure row, displacement columns
+        const T bv = (T)r[L::BV_], dk = (T)r[L::DK_];
+        const T qw[3] = {(T)r[L::QW_], (T)r[L::QW_ + 1], (T)r[L::QW_ + 2]};
+        const T giq = gi[0] * qw[0] + gi[1] * qw[1] + gi[2] * qw[2];
+        const T qwk = qw[0] * gk[0] + qw[1] * gk[1] + qw[2] * gk[2];
+        T gkc = Si * bv + dk * giq;
+        if (kc) gkc += (T)r[L::KJ_] * giq;
+        const T gic = -dk * qwk + (DYN ? (T)r[L::EE_] * Sk : T(0));
+        const T gpf = -dk * gigk;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            T v = gkc * gk[cc] + gic * gi[cc] + gpf * (T)r[L::GP_ + cc];
+            if (DYN) v -= Si * ltk[cc];
+            acc[12 + cc] += v;
+        }
+        // pressure-pressure
+        acc[15] += dk * gigk + (T)r[L::TC_] * (Si - Pii) * (Sk - Pik);
+    }
+    using GT = __attribute__((address_space(1))) T*;
+    const GT Ke = (GT)d->Ke;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) Ke[(c * 16 + e) * 64 + lane] = acc[e];
+}
+
+// Block rows of the 3D Jacobian from the cell matrices: a wavefront per (run of 64 consecutive
+// nodes along x, block entry e = 4 a + c), a thread per node.  The node is corner i of its cells
+// c = n - i; their blocks (i, k) go to the stencil slots k - i, summed over i in a fixed order.
+// Rows and columns of constrained dofs become identity rows; each store writes 64 consecutive
+// rows of one entry.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_jacgather3(Batch B) {
+    const int q = batch_find(B, blockIdx.x);
+    const Dev* __restrict__ d = B.d[q];
+    const int64_t lb = blockIdx.x - B.pfx[q];
+    const int64_t W = lb * (TPB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int e = (int)(W % 16), ca = e >> 2, cc = e & 3;
+    const int64_t run = W / 16;
+    const int nrx = (d->nn[0] + 63) / 64;
+    const int x = (int)(run % nrx) * 64 + lane;
+    const int y = (int)((run / nrx) % d->nn[1]);
+    const int z = (int)(run / ((int64_t)nrx * d->nn[1]));
+    if (z >= d->nn[2] || x >= d->nn[0]) return;
+    using GT = const __attribute__((address_space(1))) T*;
+    const GT Ke = (GT)d->Ke;
+    T acc[27];
+#pragma unroll
+    for (int s = 0; s < 27; ++s) acc[s] = T(0);
+    // branch-free over the 8 cells (an off-grid cell reads cell 0 with weight 0), so that all
+    // loads issue together; node n's entries (i, 0..7) of a cell and its x-neighbour's (i ^ 1,
+    // 0..7) share a 128-byte line
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int ix = i & 1, iy = (i >> 1) & 1, iz = i >> 2;
+        const int cx = x - ix, cy = y - iy, cz = z - iz;
+        const bool in = cx >= 0 && cy >= 0 && cz >= 0 && cx < d->nc[0] && cy < d->nc[1] && cz < d->nc[2];
+        const int64_t c = in ? cx + (int64_t)d->nc[0] * (cy + (int64_t)d->nc[1] * cz) : 0;
+        const T wgt = in ? T(1) : T(0);
+        const GT kp = Ke + (c * 16 + e) * 64 + i * 8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
+            acc[(kx - ix + 1) + 3 * ((ky - iy + 1) + 3 * (kz - iz + 1))] += wgt * kp[k];
+        }
+    }
+    const int64_t row = x + (int64_t)d->nn[0] * (y + (int64_t)d->nn[1] * z);
+    const int64_t pni = pad_index(d, x, y, z);
+    const bool fr = d->dfree[pni * 4 + ca] != 0;
+    T* __restrict__ J = (T*)d->J;
+#pragma unroll
+    for (int s = 0; s < 27; ++s) {
+        const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = s / 9 - 1;
+        const int kx = x + ox, ky = y + oy, kz = z + oz;
+        const bool valid = kx >= 0 && ky >= 0 && kz >= 0 && kx < d->nn[0] && ky < d->nn[1] && kz < d->nn[2];
+        T v = T(0);
+        if (valid) {
+            v = acc[s];
+            const bool fc = d->dfree[pad_index(d, kx, ky, kz) * 4 + cc] != 0;
+            if (!(fr && fc)) v = (s == 13 && ca == cc) ? T(1) : T(0);
+        }
+        J[jidx<3>((s * 4 + ca) * 4 + cc, row, 27 * 16, d->Nnode)] = v;
+    }
+}
+
 // sum of the residual partials of each problem (one block per problem)
 __global__ void k_finalize_norms(Batch B) {
     const int q = blockIdx.x;
@@ -653,8 +894,32 @@ void launch_jacobian(const Group& g, hipStream_t st) {
         if (g.mixed) PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 1, float>), gr, tb, 0, st, Bn));
         else PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<2, 1, double>), gr, tb, 0, st, Bn));
     } else {
-        if (g.mixed) PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<3, 0, float>), gr, tb, 0, st, Bn));
-        else PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacobian<3, 0, double>), gr, tb, 0, st, Bn));
+        // cell matrices (a wavefront per cell), then the block rows (a wavefront per 64-node run
+        // and block entry)
+        std::vector<int64_t> cw, gw;
+        bool dyn = false, vis = false;
+        for (size_t i = 0; i < g.ncell.size(); ++i) {
+            cw.push_back(g.ncell[i] * 64);
+            gw.push_back(jacgather3_blocks(g.nn3[i]));
+        }
+        for (const Dev* hd : g.hdev) {
+            dyn = dyn || hd->dyn;
+            vis = vis || (hd->dyn && hd->alpha_vis != 0.0);
+        }
+        Batch Bc = make_batch(g.ddev, cw, TPB);
+        Batch Bg = make_batch_blocks(g.ddev, gw);
+        const dim3 gc(Bc.pfx[Bc.n]), gg(Bg.pfx[Bg.n]);
+        if (g.mixed) {
+            if (vis) PPM_TIMED(KT_CELLMAT, st, hipLaunchKernelGGL((k_cellmat3<float, true, true>), gc, tb, 0, st, Bc));
+            else if (dyn) PPM_TIMED(KT_CELLMAT, st, hipLaunchKernelGGL((k_cellmat3<float, true, false>), gc, tb, 0, st, Bc));
+            else PPM_TIMED(KT_CELLMAT, st, hipLaunchKernelGGL((k_cellmat3<float, false, false>), gc, tb, 0, st, Bc));
+            PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacgather3<float>), gg, tb, 0, st, Bg));
+        } else {
+            if (vis) PPM_TIMED(KT_CELLMAT, st, hipLaunchKernelGGL((k_cellmat3<double, true, true>), gc, tb, 0, st, Bc));
+            else if (dyn) PPM_TIMED(KT_CELLMAT, st, hipLaunchKernelGGL((k_cellmat3<double, true, false>), gc, tb, 0, st, Bc));
+            else PPM_TIMED(KT_CELLMAT, st, hipLaunchKernelGGL((k_cellmat3<double, false, false>), gc, tb, 0, st, Bc));
+            PPM_TIMED(KT_JACOBIAN, st, hipLaunchKernelGGL((k_jacgather3<double>), gg, tb, 0, st, Bg));
+        }
     }
 }
 

@@ -294,16 +294,17 @@ __global__ void k_bicg_scalars(Batch B, int stage, double rtol, int maxit) {
     }
 }
 
-// X += x (Newton update, FP64)
+// X += s x (Newton update, FP64; s = 1, or a negative fraction that takes back part of the last
+// update)
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_newton_update(Batch B) {
+__global__ void __launch_bounds__(TPB) k_newton_update(Batch B, double s) {
     PROB_PROLOGUE
     if (tid >= d->Nnode) return;
     const int64_t pn = node_pad<T>(d, tid);
     const int bs = d->b;
     for (int a = 0; a < bs; ++a) {
         int64_t k = pn * bs + a;
-        if (d->dfree[k]) d->X[k] += (double)vp<T>(d->kx)[k];
+        if (d->dfree[k]) d->X[k] += s * (double)vp<T>(d->kx)[k];
     }
 }
 
@@ -362,10 +363,10 @@ void launch_krylov_iters(const Group& g, const std::vector<const Dev*>& hc, int 
     }
 }
 
-void launch_newton_update(const Group& g, hipStream_t st) {
+void launch_newton_update(const Group& g, hipStream_t st, double s) {
     Batch Bn = make_batch(g.ddev, g.nnode, TPB);
-    if (g.mixed) hipLaunchKernelGGL(k_newton_update<float>, dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn);
-    else hipLaunchKernelGGL(k_newton_update<double>, dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn);
+    if (g.mixed) hipLaunchKernelGGL(k_newton_update<float>, dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn, s);
+    else hipLaunchKernelGGL(k_newton_update<double>, dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn, s);
 }
 
 // ---------------------------------------------------------------------------------------------

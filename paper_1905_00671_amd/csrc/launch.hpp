@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <array>
 #include <initializer_list>
 #include <vector>
 
@@ -16,11 +17,13 @@ struct Group {
     int dim = 2, shape = 0, mixed = 0, S = 9, b = 3;
     std::vector<const Dev*> ddev;   // device descriptors
     std::vector<int64_t> np, nnode, ncell, ncell1, npadb, npad, ntile, jblk;
+    std::vector<std::array<int, 3>> nn3;   // nodes per axis
+    std::vector<const Dev*> hdev;          // host copies of the descriptors
 };
 
 // Per-kernel timing with HIP events recorded on the launching stream (off unless enabled).
 enum KernelId : int { KT_SPMV = 0, KT_JACOBIAN, KT_RECORDS, KT_RESIDUAL, KT_MG0_RESID, KT_P2G, KT_G2P, KT_PERMUTE,
-                      KT_RAP, KT_COUNT };
+                      KT_RAP, KT_CELLMAT, KT_COUNT };
 bool timing_on();
 void timing_begin(hipStream_t st, int id, hipEvent_t* a, hipEvent_t* b);
 void timing_end(hipStream_t st, hipEvent_t b);
@@ -76,6 +79,12 @@ inline int64_t jacobian_blocks(int dim, const int* nn) {
     return runs * nn[1] * (dim == 3 ? nn[2] : 1);
 }
 
+// Blocks of the 3D block-row gather: a wavefront per (64-node x-run, block entry), 16 entries.
+inline int64_t jacgather3_blocks(const std::array<int, 3>& nn) {
+    const int64_t waves = (int64_t)((nn[0] + 63) / 64) * nn[1] * nn[2] * 16;
+    return (waves + TPB / 64 - 1) / (TPB / 64);
+}
+
 // Tiles of the multigrid sweeps covering a level of n nodes per axis.
 inline int64_t mg_tiles(int dim, const int* n) {
     if (dim == 2) return (int64_t)((n[0] + MGT2X - 1) / MGT2X) * ((n[1] + MGT2Y - 1) / MGT2Y);
@@ -113,7 +122,8 @@ void launch_precond_apply(const Group& g, const std::vector<const Dev*>& host_co
 void launch_krylov_init(const Group& g, double rtol, int maxit, hipStream_t st);
 void launch_krylov_iters(const Group& g, const std::vector<const Dev*>& host_copies, int iters, double rtol,
                          int maxit, hipStream_t st);
-void launch_newton_update(const Group& g, hipStream_t st);
+// X += s x on the free dofs (s = 1: the Newton update; s < 0 takes back part of the last one)
+void launch_newton_update(const Group& g, hipStream_t st, double s = 1.0);
 void launch_apply_jacobian(const Dev* dd, const Dev* hd, const double* v_nat, double* y_nat, hipStream_t st);
 void launch_nodal_out(const Dev* dd, const Dev* hd, int field, double* out, hipStream_t st);
 void launch_residual_out(const Dev* dd, const Dev* hd, double* out, hipStream_t st);

@@ -93,8 +93,10 @@ struct Dev {
     double h, x0[3], hi[3];
     double lam, G, kappa, rho_f, g[3];
     double phi0;  // initial porosity of the Kozeny-Carman law, 0: constant mobility
+    double alpha_vis;  // Kelvin-type damping parameter (dynamic problems)
     // per-step parameters
     double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
+    double kin;   // inertia factor of the Newmark fixed-stress modulus (fs_term)
     int nlev;
     int ltail;    // first level handled by the fused small-level kernel
     int ls_stop;  // Schur-block hierarchy ends here with two Jacobi sweeps (>= ltail: not truncated)
@@ -131,6 +133,8 @@ struct Dev {
     // Jacobian, fixed stencil block rows: entry e = (s*b + a)*b + c of row r at
     // J[jidx<dim>(e, r, S*b*b, Nnode)], precision T (see jidx)
     void* J;
+    // 3D: cell matrices [Ncell][16][64] (entry, node pair), precision T
+    void* Ke;
     // Krylov vectors [Npad*b], precision T
     void* kx; void* kr; void* kh; void* kp; void* kv; void* ks; void* kt; void* kph; void* ksh;
     void* kbt;        // [Npad*dim] rhs of the A cycle (r_u - B1 z_p)
@@ -210,6 +214,42 @@ struct RecLayout {
     static constexpr int N = KJ_ + 1;
 };
 
+// 3D (trilinear, neo-Hookean): no folded tangent.  The cell-matrix kernel forms the
+// displacement block of each node pair in closed form from V0 G, b = F F^T and two scalars:
+//   A_ik^ac = -V0 G (gi . b gk) d_ac + C1 gk_a gi_c + C2 gi_a gk_c
+//   C1 = V0 (lam ln J - G) - dv p,   C2 = dv p - V0 lam
+// (plus the Newmark inertia and the Kelvin damping terms), which is the contraction
+// gi_b Abar_{ab,ce} gk_e of the folded tangent for tau' = G (b - 1) + lam ln J 1.
+// 80 words = five 128-byte lines: every record starts on a line, the residual gather's 39 words
+// are its first three lines and the cell-matrix kernel's 66 words its first five.
+template <>
+struct RecLayout<3, 2> {
+    static constexpr int W_ = 0;       // 1D weights [3][2]
+    static constexpr int DW_ = 6;      // 1D gradients [3][2]
+    static constexpr int FI_ = 12;     // dF^{-1} [9]
+    static constexpr int SG_ = 21;     // -V0 tau' + dv p 1 - dv sigma_vis [9]
+    static constexpr int BF_ = 30;     // m (g - a) [3]
+    static constexpr int DT_ = 33;     // dv theta
+    static constexpr int ST_ = 34;     // tau V_n (pdot - Pi pdot)
+    static constexpr int DK_ = 35;     // dv kappa
+    static constexpr int QW_ = 36;     // w = grad p - rho_f (g - a) [3]
+    static constexpr int DV_ = 39;     // dv
+    static constexpr int CM_ = 40;     // m / (beta dt^2)
+    static constexpr int BV_ = 41;     // volumetric coupling coefficient
+    static constexpr int LV_ = 42;     // dv * velocity gradient [9]
+    static constexpr int GP_ = 51;     // grad p [3]
+    static constexpr int EE_ = 54;     // dv kappa rho_f / (beta dt^2)
+    static constexpr int TC_ = 55;     // tau c_t V_n
+    static constexpr int KJ_ = 56;     // dv J dkappa/dJ (Kozeny-Carman; else 0)
+    static constexpr int VG_ = 57;     // V0 G
+    static constexpr int BM_ = 58;     // b = F F^T: xx yy zz xy yz xz
+    static constexpr int C1_ = 64;
+    static constexpr int C2_ = 65;
+    static constexpr int SV_ = 66;     // sigma_vis: xx yy zz xy yz xz (Kelvin damping only)
+    static constexpr int S0_ = 72;     // (GIMP constant basis; unused by the trilinear basis) [3][2]
+    static constexpr int N = 80;
+};
+
 // Record of point p: NREC contiguous words (the gathers read ~30 fields of one point per visit,
 // which then share a few cache lines).  rec[f] is field f of the point.
 struct RecRef {
@@ -255,6 +295,11 @@ __device__ __forceinline__ int window_base(double x, double lp, double x0, doubl
     return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
 }
 
+// Overlap (relative to h) below which a GIMP domain and a node's support only touch: the
+// intersection has measure zero and the node gets weight, gradient and S0 exactly 0, so that the
+// rounding of the interval ends cannot make an untouched node active with a ~1e-27 mass.
+constexpr double GIMP_TOUCH = 1e-10;
+
 // 1D basis of one particle along one axis.  Original MPM: the two nodes of the containing cell
 // (clamped), hat weights.  GIMP: the domain [x-lp, x+lp] clipped to the grid, three nodes from
 // the one at or left of its lower end; weight = domain average of the hat, gradient = domain
@@ -280,7 +325,9 @@ __device__ __forceinline__ int basis_1d(double x, double lp, double x0, double h
             w[k] = (hat_prim(bb - xn, h) - hat_prim(a - xn, h)) / len;
             dw[k] = (hat_val(bb - xn, h) - hat_val(a - xn, h)) / len;
             double ov = fmin(bb, xn + h) - fmax(a, xn - h);
-            s0[k] = ov > 0.0 ? 0.5 * ov / len : 0.0;
+            const bool in = ov > GIMP_TOUCH * h;
+            s0[k] = in ? 0.5 * ov / len : 0.0;
+            if (!in) w[k] = dw[k] = 0.0;
         }
     }
     return base;

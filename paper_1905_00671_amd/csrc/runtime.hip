@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -233,6 +234,7 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
     h.cellpi = c.take<double>(h.Ncell * (1 << D));
     h.rec = c.take<double>((size_t)nrec * rec_points_padded(np));
     h.J = c.take<char>((size_t)h.S * bs * bs * jrows_padded(h.Nnode) * TS);
+    h.Ke = c.take<char>(D == 3 ? (size_t)h.Ncell * 16 * 64 * TS : 0);
     void** kv[9] = {&h.kx, &h.kr, &h.kh, &h.kp, &h.kv, &h.ks, &h.kt, &h.kph, &h.ksh};
     for (auto* p : kv) *p = c.take<char>((size_t)P * bs * TS);
     h.kbt = c.take<char>((size_t)P * D * TS);
@@ -283,7 +285,8 @@ double stab_tau(const ppmpm_options* o, double lam, double G, double kappa, doub
         double t = (1.0 - 3.0 * r) * (1.0 + std::tanh(2.0 - 12.0 * r)) / Mp;
         return o->tau_scale * std::max(t, 0.0);
     }
-    double t = 2.0 * kappa / cv - (o->beta / o->gamma) * 12.0 * kappa * dt / (h * h);
+    // 2 kappa / c_v = 2 / M, also in the limit kappa -> 0
+    double t = 2.0 / Mp - (o->beta / o->gamma) * 12.0 * kappa * dt / (h * h);
     return o->tau_scale * std::max(t, 0.0);
 }
 
@@ -319,22 +322,28 @@ int schur_truncation(const Dev& h) {
     return MAXLEV;
 }
 
-ppmpm_status upload_desc(ppmpm_problem* p) {
+// The pinned staging copy is read when the copy executes: callers synchronize the stream
+// before the next upload of the same problem.
+ppmpm_status upload_desc(ppmpm_problem* p, hipStream_t st) {
     *p->hpin = p->h;
-    HIPCHK(hipMemcpyAsync(p->d, p->hpin, sizeof(Dev), hipMemcpyHostToDevice, p->st));
+    HIPCHK(hipMemcpyAsync(p->d, p->hpin, sizeof(Dev), hipMemcpyHostToDevice, st));
     return PPMPM_OK;
 }
+ppmpm_status upload_desc(ppmpm_problem* p) { return upload_desc(p, p->st); }
 
 // copy a caller array of `bytes` into device memory: device pointers pass through, host ones
 // are staged in the io region at byte offset `off`
-const void* to_device(ppmpm_problem* p, const void* src, size_t bytes, int where, size_t& off) {
+const void* to_device(ppmpm_problem* p, const void* src, size_t bytes, int where, size_t& off, hipStream_t st) {
     if (!src) return nullptr;
     if (where == PPMPM_DEVICE) return src;
     off = (off + 255) & ~size_t(255);
     char* dst = p->io + off;
     off += bytes;
-    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, p->st) != hipSuccess) return nullptr;
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return nullptr;
     return dst;
+}
+const void* to_device(ppmpm_problem* p, const void* src, size_t bytes, int where, size_t& off) {
+    return to_device(p, src, bytes, where, off, p->st);
 }
 
 Group make_group(const std::vector<ppmpm_problem*>& ps) {
@@ -354,6 +363,8 @@ Group make_group(const std::vector<ppmpm_problem*>& ps) {
         g.npadb.push_back(p->h.Npad * p->h.b);
         g.ntile.push_back(node_tiles(p->h.dim, p->h.nn));
         g.jblk.push_back(jacobian_blocks(p->h.dim, p->h.nn));
+        g.nn3.push_back({p->h.nn[0], p->h.nn[1], p->h.nn[2]});
+        g.hdev.push_back(&p->h);
     }
     return g;
 }
@@ -367,19 +378,26 @@ std::vector<const Dev*> host_copies(const std::vector<ppmpm_problem*>& ps) {
 using clk = std::chrono::steady_clock;
 double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
 
-ppmpm_status read_scalars(const std::vector<ppmpm_problem*>& ps, hipStream_t st) {
+// scalars and error flags of each problem into its pinned staging (asynchronous)
+ppmpm_status fetch_scalars(const std::vector<ppmpm_problem*>& ps, hipStream_t st) {
     for (auto* p : ps) {
         HIPCHK(hipMemcpyAsync(p->spin, p->h.scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(p->fpin, p->h.flags, sizeof(int) * NFLAG, hipMemcpyDeviceToHost, st));
     }
+    return PPMPM_OK;
+}
+
+ppmpm_status read_scalars(const std::vector<ppmpm_problem*>& ps, hipStream_t st) {
+    ppmpm_status s = fetch_scalars(ps, st);
+    if (s) return s;
     HIPCHK(hipStreamSynchronize(st));
     return PPMPM_OK;
 }
 
 // Stage 1 for a group: descriptor upload (per-step parameters), boundary data, sort, projection
 // cells, P2G.  BC staging happens per problem.
-ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, const ppmpm_bc* const* bcs) {
-    hipStream_t st = ps[0]->st;
+ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, const ppmpm_bc* const* bcs,
+                    hipStream_t st) {
     for (size_t i = 0; i < ps.size(); ++i) {
         ppmpm_problem* p = ps[i];
         Dev& h = p->h;
@@ -394,10 +412,14 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
         h.hc2 = o->dynamic ? (1.0 - 0.5 * o->gamma / o->beta) * t : 0.0;
         h.tau = stab_tau(o, h.lam, h.G, h.kappa, h.h, t);
         h.Kfs = h.lam + 2.0 * h.G / h.dim;
+        // inertia factor of the Newmark fixed-stress modulus: 0 / 0.03 / 0.1 / 0.3 / 1 took 805 /
+        // 664 / 515 / 430 / 364 FP64 Krylov iterations over four steps of a 16 x 16 undrained
+        // dynamic footing and 3771 / 3327 / 2713 / 2028 / 1725 over six steps of config 2
+        h.kin = 1.0;
         h.omega = smoother_damping(h);
         h.mg_nsm = std::max(1, o->mg_smooth);
         h.ls_stop = schur_truncation(h);
-        ppmpm_status s = upload_desc(p);
+        ppmpm_status s = upload_desc(p, st);
         if (s) return s;
         HIPCHK(hipMemsetAsync(h.flags, 0, sizeof(int) * NFLAG, st));
         const ppmpm_bc* bc = bcs ? bcs[i] : nullptr;
@@ -405,12 +427,12 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
         const int64_t nn = h.Nnode;
         const int D = h.dim;
         int where = bc ? bc->where : PPMPM_HOST;
-        const uint8_t* uf = bc ? (const uint8_t*)to_device(p, bc->u_fixed, nn * D, where, off) : nullptr;
-        const double* ui = bc ? (const double*)to_device(p, bc->u_inc, nn * D * 8, where, off) : nullptr;
-        const uint8_t* pf = bc ? (const uint8_t*)to_device(p, bc->p_fixed, nn, where, off) : nullptr;
-        const double* pv = bc ? (const double*)to_device(p, bc->p_val, nn * 8, where, off) : nullptr;
-        const double* fe = bc ? (const double*)to_device(p, bc->f_ext, nn * D * 8, where, off) : nullptr;
-        const double* qe = bc ? (const double*)to_device(p, bc->q_ext, nn * 8, where, off) : nullptr;
+        const uint8_t* uf = bc ? (const uint8_t*)to_device(p, bc->u_fixed, nn * D, where, off, st) : nullptr;
+        const double* ui = bc ? (const double*)to_device(p, bc->u_inc, nn * D * 8, where, off, st) : nullptr;
+        const uint8_t* pf = bc ? (const uint8_t*)to_device(p, bc->p_fixed, nn, where, off, st) : nullptr;
+        const double* pv = bc ? (const double*)to_device(p, bc->p_val, nn * 8, where, off, st) : nullptr;
+        const double* fe = bc ? (const double*)to_device(p, bc->f_ext, nn * D * 8, where, off, st) : nullptr;
+        const double* qe = bc ? (const double*)to_device(p, bc->q_ext, nn * 8, where, off, st) : nullptr;
         if (off > p->iob) return fail(PPMPM_E_OOM, "io staging too small");
         launch_bc(p->d, nn, uf, ui, pf, pv, fe, qe, st);
     }
@@ -425,7 +447,346 @@ struct NState {
     int phase = 0;  // 0 Newton, 1 converged, 2 failed
     int status = PPMPM_OK;
     double ru0 = 0, rp0 = 0, atol_u = 0, atol_p = 0;
+    int halvings = 0;  // mixed path: times the last Newton update was halved
 };
+
+// Mixed path: an FP32 Krylov solve can return a direction whose full step inverts a material
+// point (or makes the residual non-finite) although a shorter step would not.  The update is then
+// halved, up to this many times, before the step is reported as failed.  The FP64 path takes
+// full steps only, as the oracle does.
+constexpr int MAX_HALVINGS = 4;
+
+constexpr int ST_PENDING = -1;   // statistics slot of a problem not (yet) finished
+
+// Streams for the second and later kernel-variant groups of a batch, so that the groups' work
+// overlaps on the device (the first group runs on the caller's stream).  Created on first use
+// per device, at the default priority, and kept until the process ends.
+hipStream_t aux_stream(size_t k) {
+    static std::mutex mu;
+    static std::vector<std::vector<hipStream_t>> pool;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)pool.size() <= dev) pool.resize(dev + 1);
+    auto& v = pool[dev];
+    while (v.size() < k) {
+        hipStream_t t = nullptr;
+        if (hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        v.push_back(t);
+    }
+    return v[k - 1];
+}
+
+// Problems of one kernel variant and their Newton state during a batched step.
+struct GroupRun {
+    std::vector<int> idx;                 // batch indices
+    std::vector<ppmpm_problem*> ps;
+    std::vector<NState> ns;
+    hipStream_t st = nullptr;
+    double krtol = 1e-8;
+    int kmax = 1000, kcheck = 4;
+    // current Newton iteration
+    std::vector<ppmpm_problem*> act, cont;
+    std::vector<int> actk, contk;
+    bool kdone = true;
+    int kiters = 0;
+};
+
+// The batched step.  Problems are grouped by kernel variant (dimension, basis, precision) and
+// Krylov options, at most MAXB per group; all groups advance through the stages in lockstep,
+// each on its own stream, with one host wait per stage for all of them.  S[i].status is set for
+// every problem the step finishes; a returned error leaves the others at ST_PENDING.
+ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* dt, const ppmpm_bc* const* bcs,
+                          std::vector<ppmpm_step_stats>& S) {
+    // per-problem validation: an invalid problem does not stop the others
+    int lead = -1;
+    std::vector<int> valid;
+    for (int i = 0; i < nprob; ++i) {
+        ppmpm_problem* p = probs[i];
+        if (!p || !p->have_particles) {
+            S[i].status = PPMPM_E_INVALID;
+            g_err = "problem without particles";
+            continue;
+        }
+        if (!(dt[i] > 0)) {
+            S[i].status = PPMPM_E_INVALID;
+            g_err = "dt must be positive";
+            continue;
+        }
+        if (lead < 0) lead = i;
+        if (p->st != probs[lead]->st) {
+            S[i].status = PPMPM_E_INVALID;
+            g_err = "problems of a batch must share one stream";
+            continue;
+        }
+        valid.push_back(i);
+    }
+    if (valid.empty()) return PPMPM_OK;
+    hipStream_t st0 = probs[lead]->st;
+    const bool phase_sync = ppm::g_timing;   // exact phase clocks only while kernel timing is on
+    auto t0 = clk::now();
+    // group by kernel variant and Krylov options
+    std::vector<GroupRun> G;
+    {
+        std::vector<int> used(nprob, 0);
+        for (int i : valid) {
+            if (used[i]) continue;
+            GroupRun g;
+            const ppmpm_problem* a = probs[i];
+            for (int j : valid) {
+                if (used[j] || (int)g.idx.size() >= MAXB) continue;
+                const ppmpm_problem* b = probs[j];
+                if (a->h.dim == b->h.dim && a->h.shape == b->h.shape && a->h.mixed == b->h.mixed &&
+                    a->opt.krylov_rtol == b->opt.krylov_rtol && a->opt.krylov_max == b->opt.krylov_max &&
+                    a->opt.krylov_check == b->opt.krylov_check) {
+                    g.idx.push_back(j);
+                    g.ps.push_back(probs[j]);
+                    used[j] = 1;
+                }
+            }
+            g.ns.resize(g.ps.size());
+            g.krtol = a->opt.krylov_rtol;
+            if (a->h.mixed) g.krtol = std::max(g.krtol, 1e-6);   // FP32 floor; Newton refines
+            g.kmax = a->opt.krylov_max;
+            g.kcheck = std::max(1, a->opt.krylov_check);
+            G.push_back(std::move(g));
+        }
+    }
+    // streams: the first group on the caller's, the others on auxiliary streams joined to it
+    hipEvent_t ev_in = nullptr;
+    if (G.size() > 1) {
+        HIPCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev_in, st0));
+    }
+    for (size_t k = 0; k < G.size(); ++k) {
+        G[k].st = k == 0 ? st0 : aux_stream(k);   // the caller's stream may be the null stream
+        if (k > 0 && !G[k].st) return fail(PPMPM_E_DEVICE, "could not create a stream for a kernel-variant group");
+        if (k > 0) HIPCHK(hipStreamWaitEvent(G[k].st, ev_in, 0));
+    }
+    if (ev_in) HIPCHK(hipEventDestroy(ev_in));
+    // Stage 1 for every group, then one wait
+    auto ta = clk::now();
+    for (auto& g : G) {
+        std::vector<double> dts;
+        std::vector<const ppmpm_bc*> bcv;
+        for (int i : g.idx) {
+            dts.push_back(dt[i]);
+            bcv.push_back(bcs ? bcs[i] : nullptr);
+        }
+        ppmpm_status s = stage1(g.ps, dts.data(), bcv.data(), g.st);
+        if (s) return s;
+        HIPCHK(hipGetLastError());
+    }
+    for (auto& g : G) HIPCHK(hipStreamSynchronize(g.st));
+    auto tb = clk::now();
+    for (auto& g : G)
+        for (size_t k = 0; k < g.ps.size(); ++k) {
+            const Dev& h = g.ps[k]->h;
+            const ppmpm_options& o = g.ps[k]->opt;
+            g.ns[k].atol_u = o.newton_atol_u > 0 ? o.newton_atol_u : 1e-12 * g.ps[k]->mat.E * std::pow(h.h, h.dim - 1);
+            g.ns[k].atol_p = o.newton_atol_p > 0 ? o.newton_atol_p : 1e-12 * std::pow(h.h, h.dim) / h.dt;
+            S[g.idx[k]].t_sort = secs(ta, tb);
+        }
+    for (int it = 0;; ++it) {
+        // residual of every active problem
+        auto t1 = clk::now();
+        bool any = false;
+        for (auto& g : G) {
+            g.act.clear();
+            g.actk.clear();
+            for (size_t k = 0; k < g.ps.size(); ++k)
+                if (g.ns[k].phase == 0) {
+                    g.act.push_back(g.ps[k]);
+                    g.actk.push_back((int)k);
+                }
+            if (g.act.empty()) continue;
+            any = true;
+            Group ga = make_group(g.act);
+            launch_assemble(ga, false, g.st);
+            HIPCHK(hipGetLastError());
+            ppmpm_status s = fetch_scalars(g.act, g.st);
+            if (s) return s;
+        }
+        if (!any) break;
+        for (auto& g : G)
+            if (!g.act.empty()) HIPCHK(hipStreamSynchronize(g.st));
+        auto t2 = clk::now();
+        // convergence test (eq. newton-tolerance per residual block), then Jacobian and
+        // preconditioner of the problems that continue
+        bool anycont = false;
+        for (auto& g : G) {
+            std::vector<ppmpm_problem*> retry;
+            g.cont.clear();
+            g.contk.clear();
+            for (size_t j = 0; j < g.act.size(); ++j) {
+                const int k = g.actk[j];
+                ppmpm_problem* p = g.act[j];
+                ppmpm_step_stats& so = S[g.idx[k]];
+                so.t_assemble += secs(t1, t2);
+                const double ru = std::sqrt(p->spin[SC_RU2]), rp = std::sqrt(p->spin[SC_RP2]);
+                if (it < PPMPM_MAX_HIST) {
+                    so.res_u[it] = ru;
+                    so.res_p[it] = rp;
+                }
+                so.newton_iters = it;
+                if (p->fpin[FL_INVERTED] || p->fpin[FL_NONFINITE] || !std::isfinite(ru) || !std::isfinite(rp)) {
+                    if (p->h.mixed && it > 0 && g.ns[k].halvings < MAX_HALVINGS) {
+                        // take back half of what remains of the last update, clear the flags and
+                        // evaluate the residual again in the next pass
+                        g.ns[k].halvings++;
+                        retry.push_back(p);
+                        continue;
+                    }
+                    g.ns[k].phase = 2;
+                    g.ns[k].status = PPMPM_E_NONFINITE;
+                    continue;
+                }
+                g.ns[k].halvings = 0;
+                if (p->fpin[FL_BOUNDS]) {
+                    g.ns[k].phase = 2;
+                    g.ns[k].status = PPMPM_E_DEVICE;
+                    continue;
+                }
+                if (it == 0) {
+                    g.ns[k].ru0 = ru;
+                    g.ns[k].rp0 = rp;
+                }
+                const double rt = p->opt.newton_rtol;
+                const bool cu = ru <= std::max(rt * g.ns[k].ru0, g.ns[k].atol_u);
+                const bool cp = rp <= std::max(rt * g.ns[k].rp0, g.ns[k].atol_p);
+                if (cu && cp) {
+                    g.ns[k].phase = 1;
+                    so.converged = 1;
+                    continue;
+                }
+                if (it >= p->opt.newton_max) {
+                    g.ns[k].phase = 2;
+                    g.ns[k].status = PPMPM_E_NEWTON;
+                    continue;
+                }
+                g.cont.push_back(p);
+                g.contk.push_back(k);
+            }
+            for (auto* p : retry) {
+                int k = 0;
+                while (g.ps[k] != p) ++k;
+                const double s = -std::ldexp(1.0, -g.ns[k].halvings);   // -1/2, -1/4, ...
+                launch_newton_update(make_group({p}), g.st, s);
+                HIPCHK(hipMemsetAsync(p->h.flags, 0, sizeof(int) * NFLAG, g.st));
+            }
+            if (g.cont.empty()) continue;
+            anycont = true;
+            Group gc = make_group(g.cont);
+            launch_jacobian(gc, g.st);
+            launch_precond_setup(gc, host_copies(g.cont), it == 0, g.st);
+            HIPCHK(hipGetLastError());
+        }
+        if (!anycont) continue;
+        auto t3 = clk::now();
+        if (phase_sync)
+            for (auto& g : G)
+                if (!g.cont.empty()) HIPCHK(hipStreamSynchronize(g.st));
+        auto t4 = clk::now();
+        // Krylov solves: every group advances krylov_check iterations, then one wait
+        for (auto& g : G) {
+            g.kdone = g.cont.empty();
+            g.kiters = 0;
+            if (g.kdone) continue;
+            launch_krylov_init(make_group(g.cont), g.krtol, g.kmax, g.st);
+        }
+        while (true) {
+            bool pending = false;
+            for (auto& g : G) {
+                if (g.kdone) continue;
+                launch_krylov_iters(make_group(g.cont), host_copies(g.cont), g.kcheck, g.krtol, g.kmax, g.st);
+                HIPCHK(hipGetLastError());
+                ppmpm_status s = fetch_scalars(g.cont, g.st);
+                if (s) return s;
+                g.kiters += g.kcheck;
+                pending = true;
+            }
+            if (!pending) break;
+            for (auto& g : G) {
+                if (g.kdone) continue;
+                HIPCHK(hipStreamSynchronize(g.st));
+                bool all = true;
+                for (auto* p : g.cont)
+                    if (p->spin[SC_DONE] == 0.0) all = false;
+                if (all || g.kiters >= g.kmax) g.kdone = true;
+            }
+        }
+        for (auto& g : G)
+            if (!g.cont.empty()) launch_newton_update(make_group(g.cont), g.st);
+        HIPCHK(hipGetLastError());
+        if (phase_sync)
+            for (auto& g : G)
+                if (!g.cont.empty()) HIPCHK(hipStreamSynchronize(g.st));
+        auto t5 = clk::now();
+        for (auto& g : G)
+            for (size_t j = 0; j < g.cont.size(); ++j) {
+                ppmpm_step_stats& so = S[g.idx[g.contk[j]]];
+                const int kit = (int)g.cont[j]->spin[SC_ITER];
+                if (it < PPMPM_MAX_HIST) so.krylov_iters[it] = kit;
+                so.krylov_total += kit;
+                if (g.cont[j]->spin[SC_BREAK] != 0.0) so.krylov_breakdowns++;
+                so.t_precond += phase_sync ? secs(t3, t4) : 0.0;
+                so.t_krylov += phase_sync ? secs(t4, t5) : secs(t2, t5);
+            }
+    }
+    // Stages 3-4 for the converged problems
+    auto t6 = clk::now();
+    std::vector<std::vector<ppmpm_problem*>> okp(G.size());
+    std::vector<std::vector<int>> okk(G.size());
+    for (size_t gi = 0; gi < G.size(); ++gi) {
+        GroupRun& g = G[gi];
+        for (size_t k = 0; k < g.ps.size(); ++k)
+            if (g.ns[k].phase == 1) {
+                okp[gi].push_back(g.ps[k]);
+                okk[gi].push_back((int)k);
+            }
+        if (okp[gi].empty()) continue;
+        launch_g2p(make_group(okp[gi]), g.st);
+        HIPCHK(hipGetLastError());
+        ppmpm_status s = fetch_scalars(okp[gi], g.st);
+        if (s) return s;
+    }
+    for (size_t gi = 0; gi < G.size(); ++gi) {
+        GroupRun& g = G[gi];
+        if (okp[gi].empty()) continue;
+        HIPCHK(hipStreamSynchronize(g.st));
+        for (size_t j = 0; j < okp[gi].size(); ++j) {
+            ppmpm_problem* p = okp[gi][j];
+            const int k = okk[gi][j];
+            if (p->fpin[FL_INVERTED]) {
+                g.ns[k].status = PPMPM_E_NONFINITE;
+                continue;
+            }
+            if (p->fpin[FL_OUTSIDE]) {
+                g.ns[k].status = PPMPM_E_OUT_OF_GRID;
+                continue;
+            }
+            // commit: the working buffer becomes the state
+            std::swap(p->h.pc, p->h.pw);
+            std::swap(p->h.idc, p->h.idw);
+            ppmpm_status s = upload_desc(p, g.st);
+            if (s) return s;
+        }
+    }
+    // the descriptor uploads complete before the pinned staging is reused; the caller's stream
+    // waits for every group
+    for (size_t gi = 0; gi < G.size(); ++gi) HIPCHK(hipStreamSynchronize(G[gi].st));
+    if (ppm::g_timing) ppm::timing_collect();
+    auto t7 = clk::now();
+    for (auto& g : G)
+        for (size_t k = 0; k < g.ps.size(); ++k) {
+            ppmpm_step_stats& so = S[g.idx[k]];
+            so.t_g2p = secs(t6, t7);
+            so.status = g.ns[k].status;
+            so.ngrid_levels = g.ps[k]->h.nlev;
+            so.t_total = secs(t0, t7);
+        }
+    return PPMPM_OK;
+}
 
 }  // namespace
 
@@ -456,6 +817,7 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->mu_f > 0) || !(mat->k >= 0))
         return fail(PPMPM_E_INVALID, "bad material constants");
     if (!(mat->phi0 >= 0.0 && mat->phi0 < 1.0)) return fail(PPMPM_E_INVALID, "initial porosity outside [0, 1)");
+    if (!(mat->alpha_vis >= 0.0)) return fail(PPMPM_E_INVALID, "negative damping parameter");
     if (((uintptr_t)workspace & 255) != 0) return fail(PPMPM_E_INVALID, "workspace must be 256-byte aligned");
     size_t need = ppmpm_workspace_bytes(grid, np, opt);
     if (need == 0) return PPMPM_E_INVALID;   // message set by ppmpm_workspace_bytes
@@ -483,6 +845,7 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     h.G = mat->E / (2.0 * (1.0 + mat->nu));
     h.kappa = mat->k / mat->mu_f;
     h.phi0 = mat->phi0;
+    h.alpha_vis = opt->dynamic ? mat->alpha_vis : 0.0;   // quasi-static: no viscous stress
     h.rho_f = mat->rho_f;
     for (int a = 0; a < 3; ++a) h.g[a] = a < grid->dim ? mat->g[a] : 0.0;
     h.dt = 1.0;
@@ -538,208 +901,20 @@ ppmpm_status ppmpm_set_particles(ppmpm_problem* p, int64_t np, const double* x, 
 ppmpm_status ppmpm_step_batched(ppmpm_problem* const* probs, int nprob, const double* dt, const ppmpm_bc* const* bcs,
                                 ppmpm_step_stats* stats) {
     if (!probs || nprob < 1 || !dt) return fail(PPMPM_E_INVALID, "bad batch");
-    for (int i = 0; i < nprob; ++i)
-        if (!probs[i] || !probs[i]->have_particles) return fail(PPMPM_E_INVALID, "problem without particles");
-    hipStream_t st = probs[0]->st;
-    auto t0 = clk::now();
     std::vector<ppmpm_step_stats> S(nprob);
-    for (auto& s : S) {
-        std::memset(&s, 0, sizeof(s));
-        s.status = PPMPM_OK;
+    for (auto& so : S) {
+        std::memset(&so, 0, sizeof(so));
+        so.status = ST_PENDING;
     }
-    // group by kernel variant, chunks of MAXB
-    std::vector<std::vector<int>> groups;
-    {
-        std::vector<int> used(nprob, 0);
-        for (int i = 0; i < nprob; ++i) {
-            if (used[i]) continue;
-            std::vector<int> gidx;
-            for (int j = i; j < nprob && (int)gidx.size() < MAXB; ++j) {
-                if (used[j]) continue;
-                const Dev &a = probs[i]->h, &b = probs[j]->h;
-                if (a.dim == b.dim && a.shape == b.shape && a.mixed == b.mixed) {
-                    gidx.push_back(j);
-                    used[j] = 1;
-                }
-            }
-            groups.push_back(gidx);
-        }
-    }
-    ppmpm_status first_err = PPMPM_OK;
-    for (auto& gi : groups) {
-        std::vector<ppmpm_problem*> ps;
-        std::vector<double> dts;
-        std::vector<const ppmpm_bc*> bcv;
-        for (int i : gi) {
-            ps.push_back(probs[i]);
-            dts.push_back(dt[i]);
-            bcv.push_back(bcs ? bcs[i] : nullptr);
-        }
-        auto ta = clk::now();
-        ppmpm_status s = stage1(ps, dts.data(), bcv.data());
-        if (s) return s;
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(st));
-        auto tb = clk::now();
-        for (int i : gi) S[i].t_sort = secs(ta, tb);
-        std::vector<NState> ns(ps.size());
-        for (size_t k = 0; k < ps.size(); ++k) {
-            const Dev& h = ps[k]->h;
-            const ppmpm_options& o = ps[k]->opt;
-            ns[k].atol_u = o.newton_atol_u > 0 ? o.newton_atol_u : 1e-12 * ps[k]->mat.E * std::pow(h.h, h.dim - 1);
-            ns[k].atol_p = o.newton_atol_p > 0 ? o.newton_atol_p : 1e-12 * std::pow(h.h, h.dim) / h.dt;
-        }
-        for (int it = 0;; ++it) {
-            std::vector<ppmpm_problem*> act;
-            std::vector<int> actk;
-            for (size_t k = 0; k < ps.size(); ++k)
-                if (ns[k].phase == 0) {
-                    act.push_back(ps[k]);
-                    actk.push_back((int)k);
-                }
-            if (act.empty()) break;
-            auto t1 = clk::now();
-            Group ga = make_group(act);
-            launch_assemble(ga, false, st);
-            HIPCHK(hipGetLastError());
-            s = read_scalars(act, st);
-            if (s) return s;
-            auto t2 = clk::now();
-            std::vector<ppmpm_problem*> cont;
-            std::vector<int> contk;
-            for (size_t j = 0; j < act.size(); ++j) {
-                int k = actk[j];
-                ppmpm_problem* p = act[j];
-                int qi = gi[k];
-                ppmpm_step_stats& so = S[qi];
-                so.t_assemble += secs(t1, t2);
-                double ru = std::sqrt(p->spin[SC_RU2]), rp = std::sqrt(p->spin[SC_RP2]);
-                if (it < PPMPM_MAX_HIST) {
-                    so.res_u[it] = ru;
-                    so.res_p[it] = rp;
-                }
-                so.newton_iters = it;
-                if (p->fpin[FL_INVERTED] || p->fpin[FL_NONFINITE] || !std::isfinite(ru) || !std::isfinite(rp)) {
-                    ns[k].phase = 2;
-                    ns[k].status = PPMPM_E_NONFINITE;
-                    continue;
-                }
-                if (p->fpin[FL_BOUNDS]) {
-                    ns[k].phase = 2;
-                    ns[k].status = PPMPM_E_DEVICE;
-                    continue;
-                }
-                if (it == 0) {
-                    ns[k].ru0 = ru;
-                    ns[k].rp0 = rp;
-                }
-                const double rt = p->opt.newton_rtol;
-                bool cu = ru <= std::max(rt * ns[k].ru0, ns[k].atol_u);
-                bool cp = rp <= std::max(rt * ns[k].rp0, ns[k].atol_p);
-                if (cu && cp) {
-                    ns[k].phase = 1;
-                    so.converged = 1;
-                    continue;
-                }
-                if (it >= p->opt.newton_max) {
-                    ns[k].phase = 2;
-                    ns[k].status = PPMPM_E_NEWTON;
-                    continue;
-                }
-                cont.push_back(p);
-                contk.push_back(k);
-            }
-            if (cont.empty()) continue;
-            Group gc = make_group(cont);
-            auto hcs = host_copies(cont);
-            auto t3 = clk::now();
-            launch_jacobian(gc, st);
-            launch_precond_setup(gc, hcs, it == 0, st);
-            HIPCHK(hipGetLastError());
-            HIPCHK(hipStreamSynchronize(st));
-            auto t4 = clk::now();
-            double krtol = cont[0]->opt.krylov_rtol;
-            if (gc.mixed) krtol = std::max(krtol, 1e-6);
-            int kmax = cont[0]->opt.krylov_max;
-            int kcheck = std::max(1, cont[0]->opt.krylov_check);
-            launch_krylov_init(gc, krtol, kmax, st);
-            int done_iters = 0;
-            while (true) {
-                launch_krylov_iters(gc, hcs, kcheck, krtol, kmax, st);
-                HIPCHK(hipGetLastError());
-                s = read_scalars(cont, st);
-                if (s) return s;
-                done_iters += kcheck;
-                bool all = true;
-                for (auto* p : cont)
-                    if (p->spin[SC_DONE] == 0.0) all = false;
-                if (all || done_iters >= kmax) break;
-            }
-            launch_newton_update(gc, st);
-            HIPCHK(hipGetLastError());
-            HIPCHK(hipStreamSynchronize(st));
-            auto t5 = clk::now();
-            for (size_t j = 0; j < cont.size(); ++j) {
-                int qi = gi[contk[j]];
-                ppmpm_step_stats& so = S[qi];
-                int kit = (int)cont[j]->spin[SC_ITER];
-                if (it < PPMPM_MAX_HIST) so.krylov_iters[it] = kit;
-                so.krylov_total += kit;
-                if (cont[j]->spin[SC_BREAK] != 0.0) so.krylov_breakdowns++;
-                so.t_precond += secs(t3, t4);
-                so.t_krylov += secs(t4, t5);
-            }
-        }
-        // Stages 3-4 for the converged problems
-        std::vector<ppmpm_problem*> okp;
-        std::vector<int> okk;
-        for (size_t k = 0; k < ps.size(); ++k)
-            if (ns[k].phase == 1) {
-                okp.push_back(ps[k]);
-                okk.push_back((int)k);
-            }
-        auto t6 = clk::now();
-        if (!okp.empty()) {
-            Group go = make_group(okp);
-            launch_g2p(go, st);
-            HIPCHK(hipGetLastError());
-            s = read_scalars(okp, st);
-            if (s) return s;
-            for (size_t j = 0; j < okp.size(); ++j) {
-                ppmpm_problem* p = okp[j];
-                int k = okk[j];
-                if (p->fpin[FL_INVERTED]) {
-                    ns[k].status = PPMPM_E_NONFINITE;
-                    continue;
-                }
-                if (p->fpin[FL_OUTSIDE]) {
-                    ns[k].status = PPMPM_E_OUT_OF_GRID;
-                    continue;
-                }
-                // commit: the working buffer becomes the state
-                std::swap(p->h.pc, p->h.pw);
-                std::swap(p->h.idc, p->h.idw);
-                s = upload_desc(p);
-                if (s) return s;
-            }
-        }
-        HIPCHK(hipStreamSynchronize(st));
-        auto t7 = clk::now();
-        for (size_t k = 0; k < ps.size(); ++k) {
-            int qi = gi[k];
-            S[qi].t_g2p = secs(t6, t7);
-            S[qi].status = ns[k].status;
-            S[qi].ngrid_levels = ps[k]->h.nlev;
-            if (ns[k].status != PPMPM_OK && first_err == PPMPM_OK) first_err = (ppmpm_status)ns[k].status;
-        }
-    }
-    if (ppm::g_timing) ppm::timing_collect();
-    auto tend = clk::now();
+    ppmpm_status s = batched_body(probs, nprob, dt, bcs, S);
+    // every problem gets a status: those the body did not finish share its failure
+    ppmpm_status first_err = s;
     for (int i = 0; i < nprob; ++i) {
-        S[i].t_total = secs(t0, tend);
+        if (S[i].status == ST_PENDING) S[i].status = s != PPMPM_OK ? s : PPMPM_E_DEVICE;
+        if (S[i].status != PPMPM_OK && first_err == PPMPM_OK) first_err = (ppmpm_status)S[i].status;
         if (stats) stats[i] = S[i];
     }
-    if (first_err) {
+    if (first_err != PPMPM_OK && s == PPMPM_OK) {
         const char* names[] = {"ok", "invalid", "oom", "device", "Newton did not converge", "krylov",
                                "non-finite residual or inverted material point", "material point left the grid"};
         g_err = std::string("step failed: ") + names[first_err];
@@ -779,7 +954,7 @@ ppmpm_status ppmpm_eval_residual(ppmpm_problem* p, double dt, const ppmpm_bc* bc
     if (!p || !p->have_particles || !U || !P || !R) return fail(PPMPM_E_INVALID, "bad eval_residual arguments");
     std::vector<ppmpm_problem*> ps{p};
     const ppmpm_bc* bcs[1] = {bc};
-    ppmpm_status s = stage1(ps, &dt, bcs);
+    ppmpm_status s = stage1(ps, &dt, bcs, p->st);
     if (s) return s;
     const int64_t nn = p->h.Nnode;
     const int D = p->h.dim;

@@ -115,9 +115,16 @@ __device__ __forceinline__ Op<T> op_of(const Dev* d, int fam, int l) {
     return o;
 }
 
-// fixed-stress diagonal of the Schur approximation on level 0 (zero on non-free pressure dofs)
+// fixed-stress diagonal of the Schur approximation on level 0 (zero on non-free pressure dofs):
+// c_t / K M_p.  Newmark problems add the inertia of the displacement block to the modulus,
+// K = K_fs + kin rho_i h^2 / (beta dt^2) with the nodal density rho_i = M_i / M_p,i: a pressure
+// mode of wavenumber xi sees A^-1 ~ 1 / (K_fs xi^2 + rho / (beta dt^2)); kin is set by Krylov
+// counts (1: the grid's shortest modes see a few times less inertia than this)
 __device__ __forceinline__ double fs_term(const Dev* d, int64_t pn) {
-    return d->dfree[pn * d->b + d->dim] ? d->ct / d->Kfs * d->Mp[pn] : 0.0;
+    if (!d->dfree[pn * d->b + d->dim]) return 0.0;
+    double K = d->Kfs;
+    if (d->dyn) K += d->kin * d->M[pn] / d->Mp[pn] * d->h * d->h / (d->beta * d->dt * d->dt);
+    return d->ct / K * d->Mp[pn];
 }
 
 __device__ __forceinline__ double mask0(const Dev* d, int fam, int64_t pn, int comp) {

@@ -44,6 +44,7 @@ class Report:
     rounds: int = 0
     wall_s: float = 0.0
     particle_steps: int = 0
+    particle_updates: int = 0                                        # points x Newton iterations
     step_latency_ms: List[float] = field(default_factory=list)       # one entry per request step
     request_latency_s: List[float] = field(default_factory=list)     # arrival -> last step done
     batch_sizes: List[int] = field(default_factory=list)
@@ -58,6 +59,7 @@ class Report:
             completed=self.completed, failed=self.failed, rejected=self.rejected, rounds=self.rounds,
             wall_s=self.wall_s,
             particle_steps_per_s=self.particle_steps / self.wall_s if self.wall_s > 0 else 0.0,
+            particle_updates_per_s=self.particle_updates / self.wall_s if self.wall_s > 0 else 0.0,
             step_latency_ms=dict(p50=float(np.percentile(sl, 50)), p99=float(np.percentile(sl, 99))),
             request_latency_s=dict(p50=float(np.percentile(rl, 50)), p99=float(np.percentile(rl, 99))),
             mean_batch=float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
@@ -122,6 +124,7 @@ def serve(requests: Sequence, budget_bytes: int, *, bytes_of: Callable, open_pro
         for j, st in zip(active, stats):
             rep.step_latency_ms.append((te - ts) * 1e3)
             j.newton += int(st.get("newton_iters", 0))
+            rep.particle_updates += int(points_of(j.req)) * int(st.get("newton_iters", 0))
             j.krylov += int(st.get("krylov_total", 0))
             if int(st.get("status", 0)) != 0:
                 j.failed = True
@@ -148,8 +151,9 @@ def serve(requests: Sequence, budget_bytes: int, *, bytes_of: Callable, open_pro
     return rep
 
 
-def gpu_backend(precision: int, workload_cache: Optional[Dict] = None):
-    """bytes_of / open_problem / step_many / close_problem / points_of on the C ABI."""
+def gpu_backend(precision: int, workload_cache: Optional[Dict] = None, **over):
+    """bytes_of / open_problem / step_many / close_problem / points_of on the C ABI; `over`
+    overrides method options of every problem (e.g. newton_rtol, krylov_rtol)."""
     import ctypes
 
     from . import binding as B
@@ -166,11 +170,11 @@ def gpu_backend(precision: int, workload_cache: Optional[Dict] = None):
     def bytes_of(r):
         w = wl(r)
         g = B.make_grid(w.grid)
-        o = B.make_options(w.options, precision=precision)
+        o = B.make_options(w.options, precision=precision, **over)
         return int(B.lib().ppmpm_workspace_bytes(ctypes.byref(g), w.particles.n, ctypes.byref(o)))
 
     def open_problem(r):
-        return B.Problem.from_workload(wl(r), precision=precision)
+        return B.Problem.from_workload(wl(r), precision=precision, **over)
 
     def step_many(handles, reqs, steps):
         ws = [wl(r) for r in reqs]

@@ -61,3 +61,50 @@ def dyn_oracle_nodal(pr, bc):
             v[ufix] = 0.0
             nodal[k] = v.reshape(-1)
     return nodal
+
+
+def field_errors(got, ref, dynamic, gimp):
+    """Element-wise errors of the material-point state: for each field the largest absolute
+    difference over the points, divided by the field's own scale (u, v, a, pdot, pddot, sigma':
+    their largest magnitude; p: max(|p|, 1e-3 |sigma'|) so that drained states with p -> 0 stay
+    meaningful; x: the displacement scale, since x - x0 = u on both sides; F, and the relative
+    volume and GIMP-length changes: the strain scale max |F - 1|)."""
+    def mx(a):
+        return float(np.abs(a).max()) if np.size(a) else 0.0
+
+    def rel(a, b, scale):
+        return mx(np.asarray(a) - np.asarray(b)) / (scale if scale > 0 else 1.0)
+
+    d = ref["F"].shape[-1]
+    strain = mx(ref["F"] - np.eye(d)[None])
+    out = {
+        "u": rel(got["u"], ref["u"], mx(ref["u"])),
+        "p": rel(got["p"], ref["p"], max(mx(ref["p"]), 1e-3 * mx(ref["sig"]))),
+        "x": rel(got["x"], ref["x"], mx(ref["u"])),
+        "F": rel(got["F"], ref["F"], strain),
+        "vol": mx((np.asarray(got["vol"]) - ref["vol"]) / ref["vol"]) / (strain if strain > 0 else 1.0),
+        "sig": rel(got["sig"], ref["sig"], mx(ref["sig"])),
+    }
+    if gimp:
+        out["lp"] = mx((np.asarray(got["lp"]) - ref["lp"]) / ref["lp"]) / (strain if strain > 0 else 1.0)
+    if dynamic:
+        for k in ("v", "a", "pd", "pdd"):
+            out[k] = rel(got[k], ref[k], mx(ref[k]))
+    return out
+
+
+GPU_FIELDS = ("u", "p", "x", "F", "vol", "sig", "lp", "v", "a", "pd", "pdd")
+
+
+def gpu_state(gp, idx=None):
+    out = {}
+    for k in GPU_FIELDS:
+        v = gp.get(k)
+        out[k] = v if idx is None else v[idx]
+    return out
+
+
+def oracle_state(pr, idx=None):
+    s = dict(u=pr.u, p=pr.p, x=pr.x, F=pr.F, vol=pr.V, sig=pr.sig, lp=pr.lp, v=pr.v, a=pr.a, pd=pr.pd,
+             pdd=pr.pdd)
+    return s if idx is None else {k: v[idx] for k, v in s.items()}

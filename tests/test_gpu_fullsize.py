@@ -65,9 +65,12 @@ def test_fullsize_residual_and_jv(name):
             gp.close()
 
 
-def test_fullsize_step_footing2d():
+@pytest.mark.parametrize("seed", range(5))
+def test_fullsize_step_footing2d(seed):
+    """Seeds 0-4 draw k from 1e-14 (undrained) to 1e-10 m^2 (drained within a step)."""
     from paper_1905_00671_amd import binding as B
-    w = W.config(3)
+    w = W.config(3, seed=seed)
+    print(f"[fullsize step] seed {seed}: k={w.meta['k']:.3e}", flush=True)
     g, d = w.grid, w.grid.dim
     nn = g.nnode
     bc = w.bc(1)

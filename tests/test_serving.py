@@ -145,3 +145,38 @@ def test_served_results_equal_alone():
                 p.close()
             assert got[r.rid][2] == r.nsteps
             assert np.array_equal(u, got[r.rid][0]) and np.array_equal(pp, got[r.rid][1]), r
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_served_results_match_oracle(precision):
+    """Requests served in mixed batches (consolidation on original MPM and footings on GIMP, so
+    two kernel-variant groups overlap) against the CPU oracle run of each request alone: FP64
+    within 1e-10, mixed within 1e-6 on u and p (Newton driven to 1e-10 on both sides)."""
+    from oracle import oracle as O
+    from tests.gpu_common import field_errors
+    reqs = [W.Request(0, 0.0, "consolidation", 12, 1e-12, 3), W.Request(1, 0.0, "footing", 16, 1e-14, 3),
+            W.Request(2, 0.0, "consolidation", 10, 1e-15, 2), W.Request(3, 0.005, "footing", 12, 1e-11, 2)]
+    be = S.gpu_backend(precision, newton_rtol=1e-10, krylov_rtol=1e-12)
+    got = {}
+
+    def fin(job):
+        got[job.req.rid] = {k: job.handle.get(k) for k in ("u", "p", "x", "F", "vol", "sig", "lp")}
+
+    print(f"[serving vs oracle] precision={precision}", flush=True)
+    rep = S.serve(reqs, 1 << 40, realtime=False, on_finish=fin, **be)
+    assert rep.completed == len(reqs) and rep.failed == 0
+    assert max(rep.batch_sizes) >= 3
+    tol = 1e-10 if precision == 0 else 1e-6
+    for r in reqs:
+        w = r.workload()
+        w.options.newton_rtol = 1e-10
+        pr = O.from_workload(w)
+        for n in range(1, r.nsteps + 1):
+            pr.step(w.dt, w.bc(n))
+        ref = dict(u=pr.u, p=pr.p, x=pr.x, F=pr.F, vol=pr.V, sig=pr.sig, lp=pr.lp)
+        fe = field_errors(got[r.rid], ref, False, w.options.shape == W.GIMP)
+        print(f"  request {r.rid} ({r.kind}, n={r.n}): " + " ".join(f"{k}={v:.1e}" for k, v in fe.items()),
+              flush=True)
+        assert fe["u"] < tol and fe["p"] < tol, (r, fe)
+        assert max(fe.values()) < 10 * tol, (r, fe)
