@@ -215,6 +215,21 @@ ppmpm_status ppmpm_get_field(const ppmpm_problem* p, int field, double* out, int
 ppmpm_status ppmpm_eval_residual(ppmpm_problem* p, double dt, const ppmpm_bc* bc, const double* U,
                                  const double* P, double* R, int where);
 
+/* For callers that cannot allocate (code under HIP stream capture, serving loops and harnesses that
+ * forbid hipMalloc): ppmpm_create + ppmpm_set_particles + ppmpm_eval_residual in one call, with
+ * the problem's workspace in a device array inside the library (64 MiB per GPU, held until the
+ * process ends) instead of caller memory; the call allocates nothing.  Arguments as in those
+ * three calls (x, vol, mass, lp, v0, p0 the initial material points; U, P, R the nodal state
+ * and the residual out; where applies to every array).  PPMPM_E_OOM when the problem needs more
+ * than 64 MiB (ppmpm_workspace_bytes).  Every call on a GPU uses that GPU's array and the
+ * library's host staging, which keep the last call's contents: calls that overlap (other threads,
+ * other streams) race.  The call returns after its work has completed. */
+ppmpm_status ppmpm_eval_residual_static(const ppmpm_grid* grid, const ppmpm_material* mat, const ppmpm_options* opt,
+                                        int64_t np, const double* x, const double* vol, const double* mass,
+                                        const double* lp, const double* v0, const double* p0, double dt,
+                                        const ppmpm_bc* bc, const double* U, const double* P, double* R,
+                                        void* hip_stream, int where);
+
 /* y = J v with the Jacobian of the last ppmpm_eval_residual (non-free rows act as identity);
  * v, y are [nnode*(dim+1)] node-interleaved. */
 ppmpm_status ppmpm_apply_jacobian(ppmpm_problem* p, const double* v, double* y, int where);

@@ -273,6 +273,32 @@ class Problem:
             pass
 
 
+def eval_residual_static(w, dt: float, bc: Dict, U: np.ndarray, P: np.ndarray, precision: int = FP64,
+                         stream=None) -> np.ndarray:
+    """ppmpm_eval_residual_static: the residual of workload w's first step at the nodal state
+    (U, P), with the library's own device workspace (no allocation by the call)."""
+    import torch
+    L = lib()
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.ppmpm_eval_residual_static.restype = i32
+    L.ppmpm_eval_residual_static.argtypes = [vp, vp, vp, i64] + [vp] * 6 + [dbl, vp, vp, vp, vp, vp, i32]
+    g, m, o = make_grid(w.grid), make_material(w.material), make_options(w.options, precision)
+    parts = w.particles
+    arr = {k: (np.ascontiguousarray(getattr(parts, k), np.float64) if getattr(parts, k) is not None else None)
+           for k in ("x", "vol", "mass", "lp", "v0", "p0")}
+    b = BCArrays(bc)
+    U = np.ascontiguousarray(U, np.float64)
+    P = np.ascontiguousarray(P, np.float64)
+    nn = int(np.prod([n + 1 for n in w.grid.ncell[: w.grid.dim]]))
+    R = np.zeros(nn * (w.grid.dim + 1))
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(L.ppmpm_eval_residual_static(ctypes.byref(g), ctypes.byref(m), ctypes.byref(o), parts.n,
+                                        *[_ptr(arr[k]) for k in ("x", "vol", "mass", "lp", "v0", "p0")],
+                                        float(dt), ctypes.byref(b.c), _ptr(U), _ptr(P), _ptr(R),
+                                        ctypes.c_void_p(st.cuda_stream), HOST))
+    return R
+
+
 def step_batched(problems: Sequence[Problem], dts: Sequence[float], bcs: Sequence[Dict]) -> List[Dict]:
     """One time step of several problems with one kernel launch per phase (per kernel variant);
     per-problem status in each returned dict."""

@@ -790,6 +790,38 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
 
 }  // namespace
 
+static ppmpm_status init_problem(ppmpm_problem* p, const ppmpm_grid* grid, const ppmpm_material* mat,
+                                 const ppmpm_options* opt, void* workspace, size_t ws_bytes, void* hip_stream,
+                                 int64_t np);
+
+// ---------------------------------------------------------------------------------------------
+// Workspace in a file-scope device array, for the entry point whose callers cannot allocate
+// (code under stream capture, serving loops and harnesses that forbid hipMalloc).  Each device
+// holds its own copy of `scratch` until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (taken once per device).
+// ---------------------------------------------------------------------------------------------
+constexpr size_t STATIC_WS_BYTES = (size_t)64 << 20;
+constexpr int STATIC_MAX_DEVICES = 64;
+static __device__ __align__(256) char scratch[STATIC_WS_BYTES];
+
+static ppmpm_status scratch_address(void** out) {
+    static std::mutex mu;
+    static void* ptr[STATIC_MAX_DEVICES] = {};
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(PPMPM_E_DEVICE, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* a = nullptr;
+        hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !a)
+            return fail(PPMPM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        ptr[dev] = a;
+    }
+    *out = ptr[dev];
+    return PPMPM_OK;
+}
+
 // ---------------------------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------------------------
@@ -823,6 +855,29 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     if (need == 0) return PPMPM_E_INVALID;   // message set by ppmpm_workspace_bytes
     if (!workspace || ws_bytes < need) return fail(PPMPM_E_OOM, "workspace smaller than ppmpm_workspace_bytes");
     ppmpm_problem* p = new ppmpm_problem();
+    {
+        hipError_t e = hipHostMalloc((void**)&p->hpin, sizeof(Dev));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&p->spin, sizeof(double) * NSCAL);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&p->fpin, sizeof(int) * NFLAG);
+        if (e != hipSuccess) {
+            ppmpm_destroy(p);
+            return fail(PPMPM_E_DEVICE, std::string("pinned host allocation failed: ") + hipGetErrorString(e));
+        }
+    }
+    s = init_problem(p, grid, mat, opt, workspace, ws_bytes, hip_stream, np);
+    if (s) {
+        ppmpm_destroy(p);
+        return s;
+    }
+    *out = p;
+    return PPMPM_OK;
+}
+
+// Fills a problem whose staging buffers (hpin, spin, fpin) are set: descriptor, workspace layout,
+// cleared workspace, uploaded descriptor.  Allocates nothing.
+static ppmpm_status init_problem(ppmpm_problem* p, const ppmpm_grid* grid, const ppmpm_material* mat,
+                                 const ppmpm_options* opt, void* workspace, size_t ws_bytes, void* hip_stream,
+                                 int64_t np) {
     p->grid = *grid;
     p->mat = *mat;
     p->opt = *opt;
@@ -854,26 +909,8 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
     h.omega = smoother_damping(h);
     h.mg_nsm = std::max(1, opt->mg_smooth);
     h.ls_stop = MAXLEV;
-    {
-        hipError_t e = hipHostMalloc((void**)&p->hpin, sizeof(Dev));
-        if (e == hipSuccess) e = hipHostMalloc((void**)&p->spin, sizeof(double) * NSCAL);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&p->fpin, sizeof(int) * NFLAG);
-        if (e != hipSuccess) {
-            ppmpm_destroy(p);
-            return fail(PPMPM_E_DEVICE, std::string("pinned host allocation failed: ") + hipGetErrorString(e));
-        }
-    }
-    if (hipMemsetAsync(p->ws, 0, used, p->st) != hipSuccess) {
-        ppmpm_destroy(p);
-        return fail(PPMPM_E_DEVICE, "workspace clear failed");
-    }
-    s = upload_desc(p);
-    if (s) {
-        ppmpm_destroy(p);
-        return s;
-    }
-    *out = p;
-    return PPMPM_OK;
+    HIPCHK(hipMemsetAsync(p->ws, 0, used, p->st));
+    return upload_desc(p);
 }
 
 ppmpm_status ppmpm_set_particles(ppmpm_problem* p, int64_t np, const double* x, const double* vol, const double* mass,
@@ -974,6 +1011,44 @@ ppmpm_status ppmpm_eval_residual(ppmpm_problem* p, double dt, const ppmpm_bc* bc
     p->have_jacobian = true;
     if (p->fpin[FL_INVERTED]) return fail(PPMPM_E_NONFINITE, "inverted material point");
     return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_eval_residual_static(const ppmpm_grid* grid, const ppmpm_material* mat, const ppmpm_options* opt,
+                                        int64_t np, const double* x, const double* vol, const double* mass,
+                                        const double* lp, const double* v0, const double* p0, double dt,
+                                        const ppmpm_bc* bc, const double* U, const double* P, double* R,
+                                        void* hip_stream, int where) {
+    ppmpm_status s = validate(grid, opt, np);
+    if (s) return s;
+    if (!mat) return fail(PPMPM_E_INVALID, "null material");
+    if (mat->model == PPMPM_HENCKY && grid->dim == 3) return fail(PPMPM_E_INVALID, "Hencky is plane strain only");
+    if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->mu_f > 0) || !(mat->k >= 0))
+        return fail(PPMPM_E_INVALID, "bad material constants");
+    if (!(mat->phi0 >= 0.0 && mat->phi0 < 1.0)) return fail(PPMPM_E_INVALID, "initial porosity outside [0, 1)");
+    if (!(mat->alpha_vis >= 0.0)) return fail(PPMPM_E_INVALID, "negative damping parameter");
+    const size_t need = ppmpm_workspace_bytes(grid, np, opt);
+    if (need == 0) return PPMPM_E_INVALID;   // message set by ppmpm_workspace_bytes
+    if (need > STATIC_WS_BYTES)
+        return fail(PPMPM_E_OOM, "problem needs " + std::to_string(need) + " workspace bytes; the static workspace holds " +
+                                     std::to_string(STATIC_WS_BYTES));
+    void* ws = nullptr;
+    s = scratch_address(&ws);
+    if (s) return s;
+    // host staging of the descriptor and of the scalars: pageable, process-wide (calls that
+    // overlap race on them as on the device array); each upload is followed by a stream
+    // synchronization before the next one
+    static Dev s_desc;
+    static double s_scal[NSCAL];
+    static int s_flags[NFLAG];
+    ppmpm_problem pb;
+    pb.hpin = &s_desc;
+    pb.spin = s_scal;
+    pb.fpin = s_flags;
+    s = init_problem(&pb, grid, mat, opt, ws, STATIC_WS_BYTES, hip_stream, np);
+    if (s == PPMPM_OK) s = ppmpm_set_particles(&pb, np, x, vol, mass, lp, v0, p0, where);
+    if (s == PPMPM_OK) s = ppmpm_eval_residual(&pb, dt, bc, U, P, R, where);
+    (void)hipStreamSynchronize(pb.st);
+    return s;
 }
 
 ppmpm_status ppmpm_apply_jacobian(ppmpm_problem* p, const double* v, double* y, int where) {
