@@ -255,6 +255,11 @@ class OracleProblem:
         act = nodal["active"]
         ufix = bc["u_fixed"].astype(bool).reshape(nn, d)
         pfix = bc["p_fixed"].astype(bool).reshape(nn)
+        p_val = np.asarray(bc["p_val"], np.float64).reshape(nn)
+        if getattr(self.opt, "drained_surface", 0):
+            surf = free_surface_nodes(g, act)
+            pfix = pfix | surf
+            p_val = np.where(surf, 0.0, p_val)
         if self.opt.dynamic:
             # constrained components of the nodal kinematics start from rest
             for k in ("vn", "an"):
@@ -267,7 +272,7 @@ class OracleProblem:
         free = (~fixed) & act[:, None]
         free_f = free.reshape(-1)
         U = np.where(ufix, bc["u_inc"].reshape(nn, d), 0.0) * act[:, None]
-        P = np.where(pfix, bc["p_val"], nodal["Pn"]) * act
+        P = np.where(pfix, p_val, nodal["Pn"]) * act
         fext = np.zeros((nn, d + 1))
         fext[:, :d] = bc["f_ext"].reshape(nn, d)
         fext[:, d] = -bc["q_ext"]
@@ -339,6 +344,28 @@ class OracleProblem:
         self.x, self.lp, self.F, self.V = x, lp, F.reshape(self.np, d, d), V
         self.p, self.u, self.v, self.a, self.pd, self.pdd = p, u, v, a, pd, pdd
         self.sig = sig.reshape(self.np, 3, 3)
+
+
+def free_surface_nodes(grid, active):
+    """Nodes on the current free surface of the material: active nodes with an inactive node among
+    their 3^d - 1 neighbours inside the grid (the edges of the grid are supports or symmetry
+    planes, not free surfaces).  A drained free surface (zero pore pressure) is imposed there."""
+    d = grid.dim
+    shape = tuple(reversed(grid.nnode_axis))          # natural order: x fastest
+    act = np.asarray(active, bool).reshape(shape)
+    inact = ~act
+    near = np.zeros_like(act)
+    offs = [(dz, dy, dx) for dz in ((-1, 0, 1) if d == 3 else (0,)) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    for off in offs:
+        if not any(off):
+            continue
+        if d == 2:
+            off = off[1:]
+        # near[j] |= inact[j + off] wherever both lie inside the grid
+        dst = [slice(max(0, -o), n - max(0, o)) for o, n in zip(off, shape)]
+        src = [slice(max(0, o), n - max(0, -o)) for o, n in zip(off, shape)]
+        near[tuple(dst)] |= inact[tuple(src)]
+    return (act & near).reshape(-1)
 
 
 def from_workload(w) -> OracleProblem:

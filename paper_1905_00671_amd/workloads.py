@@ -100,7 +100,7 @@ class Options:
     newton_max: int = 25
     krylov_rtol: float = 1e-8
     krylov_max: int = 4000
-    proj_mode: int = 0             # original MPM only: 0 particle-quadrature cell mean, 1 analytic
+    drained_surface: int = 0       # 1: zero pore pressure on the current free surface of the material
 
 
 @dataclass
@@ -318,6 +318,47 @@ def consolidation2d(n: int, k: float, width: float = 10.0, load: float = 10e3, n
 
     return Workload("consolidation2d", grid, mat, opt, parts, dt, nsteps, bc,
                     meta=dict(H=H, W=W, load=load, k=k))
+
+
+def self_weight(h: float = 0.125, ppa: int = 5, width: float = 2.0, height: float = 2.0, K: float = 15e3,
+                nu: float = 0.3, k: float = 1e-14, phi0: float = 0.5, rho_s: float = 2600.0,
+                rho_f: float = 1000.0, mu_f: float = 1e-3, dt0: float = 0.1, growth: float = 1.2,
+                nsteps: int = 100, shape: int = GIMP, tau_kind: int = TAU_WHITE,
+                right_drained: bool = True) -> Workload:
+    """Consolidation under self weight (the paper's third example): the right half of a 4 m wide,
+    2 m tall soft deposit, Hencky skeleton with bulk modulus K = 15 kPa, nu = 0.3, Kozeny-Carman
+    permeability from k0 = 1e-14 m^2 and phi0 = 0.5, gravity applied at t = 0, quasi-static,
+    dt = 0.1 s growing by 1.2 per step.  Readings: the left edge is the symmetry plane (roller,
+    impermeable), the bottom is fixed and impermeable, the right edge is a drained roller
+    (laterally confined deposit) and the top is a drained free surface, so that the zero pressure
+    follows the settling surface (Options.drained_surface).  With gravity in the Darcy law a
+    drained right edge is a seepage face (p = 0 at every depth); right_drained=False makes it
+    impermeable, so that the column drains through its top to a hydrostatic end state.  h = 0.125 m with 5 x 5 points per cell
+    (6,400 points) or h = 0.0625 m with 4 x 4 (16,384 points) as in the paper.
+    Step n lasts dt0 growth^(n-1) (meta['dt_of'])."""
+    nx, ny = int(round(width / h)), int(round(height / h))
+    # two empty rows above the material: the drained surface is where active nodes meet inactive ones
+    grid = Grid(2, (nx, ny + 2), h, (0.0, 0.0, 0.0))
+    E = 3.0 * K * (1.0 - 2.0 * nu)
+    mat = Material(model=HENCKY, E=E, nu=nu, k=k, mu_f=mu_f, rho_s=rho_s, rho_f=rho_f, phi0=phi0,
+                   g=(0.0, -9.81, 0.0), kozeny_carman=True)
+    opt = Options(shape=shape, dynamic=0, tau_kind=tau_kind, drained_surface=1)
+    parts = fill_particles(grid, (0, 0), (nx, ny), mat.rho0, ppa=ppa)
+    X = grid.node_coords()
+    t = _tol(grid)
+
+    def bc(step: int):
+        b = empty_bc(grid)
+        box_supports(grid, b, (width,))
+        if right_drained:
+            b["p_fixed"][X[:, 0] >= width - t] = 1
+        return b
+
+    def dt_of(step: int) -> float:
+        return dt0 * growth ** (step - 1)
+
+    return Workload("self_weight", grid, mat, opt, parts, dt0, nsteps, bc,
+                    meta=dict(H=height, W=width, K=K, dt_of=dt_of, k=k))
 
 
 def jittered_box(nx: int = 8, ny: int = 8, h: float = 0.25, seed: int = 0, shape: int = LINEAR,

@@ -341,3 +341,63 @@ def test_viscous_damping_dissipates(shape):
             assert work < 0.0 and np.abs(Rv).max() > 0.0
         else:
             assert np.abs(Rv).max() <= 1e-9 * np.abs(res[0.0][k]).max(), k
+
+
+@pytest.mark.parametrize("dim,seed", [(2, 0), (2, 1), (3, 2)])
+def test_free_surface_nodes_brute_force(dim, seed):
+    """The drained free surface of the self-weight example: active nodes with an inactive neighbour
+    among the 3^dim - 1 nodes around them that lie inside the grid, by direct enumeration."""
+    rng = np.random.default_rng(seed)
+    nc = (5, 4, 3)[:dim]
+    grid = W.Grid(dim, nc, 0.5, (0.0, 0.0, 0.0))
+    nn = [c + 1 for c in nc]
+    act = rng.random(int(np.prod(nn))) < 0.7
+    got = O.free_surface_nodes(grid, act)
+    want = np.zeros_like(act)
+    for idx in np.ndindex(*reversed(nn)):
+        ijk = tuple(reversed(idx))                      # x fastest in the natural node order
+        lin = sum(ijk[a] * int(np.prod(nn[:a])) for a in range(dim))
+        if not act[lin]:
+            continue
+        for off in np.ndindex(*([3] * dim)):
+            q = [ijk[a] + off[a] - 1 for a in range(dim)]
+            if all(o == 1 for o in off) or any(q[a] < 0 or q[a] >= nn[a] for a in range(dim)):
+                continue
+            if not act[sum(q[a] * int(np.prod(nn[:a])) for a in range(dim))]:
+                want[lin] = True
+    assert np.array_equal(got, want)
+    assert got.any() and not got.all()
+
+
+def test_self_weight_consolidation_end_state():
+    """Sec. 5.3 problem (coarse: h = 0.25 m, 2 x 2 points per cell), drained through its free top
+    only: gravity at t = 0 is carried by the pore fluid first (undrained: the pressure at the base
+    is close to the total weight of the column), the excess pressure then dissipates (dt growing by
+    1.2 per step) to the hydrostatic state, in which the effective stress carries the buoyant
+    weight of the settled column."""
+    w = W.self_weight(h=0.25, ppa=2, nsteps=130, right_drained=False)
+    pr = O.from_workload(w)
+    lam, G = O.lame(w.material.E, w.material.nu)
+    M = lam + 2 * G
+    rho0, rf, g = w.material.rho0, w.material.rho_f, 9.81
+    H = w.meta["H"]
+    st = pr.step(w.meta["dt_of"](1), w.bc(1))
+    base = (pr.x[:, 1] < 0.25) & (pr.x[:, 0] < 1.0)     # away from the drained right edge
+    # undrained first step: the base pressure carries (nearly) the whole column
+    assert pr.p[base].mean() == pytest.approx(rho0 * g * (H - 0.125), rel=0.05)
+    for n in range(2, w.nsteps + 1):
+        pr.step(w.meta["dt_of"](n), w.bc(n))
+    # hydrostatic end state: the pore pressure grows with depth at rho_f g (eq. darcy-law with
+    # gravity; zero pressure holds on the surface nodes, up to a cell above the last points)
+    fit = np.polyfit(pr.x[:, 1], pr.p, 1)
+    assert fit[0] == pytest.approx(-rf * g, rel=0.03)
+    assert np.abs(pr.p - np.polyval(fit, pr.x[:, 1])).max() < 0.03 * rf * g * H
+    # vertical equilibrium of the mixture (eq. residual-momentum with m g): the total stress at a
+    # point carries the weight of the (constant) point masses above it, rho0 g (H - Z) with Z the
+    # point's initial elevation, although the column has settled by large strains
+    Z = pr.x[:, 1] - pr.u[:, 1]
+    total = pr.sig[:, 1, 1] - pr.p
+    inner = (Z > 0.3) & (Z < H - 0.3)
+    assert np.abs(total[inner] + rho0 * g * (H - Z[inner])).max() < 0.03 * rho0 * g * H
+    assert -pr.u[:, 1].min() > 0.2            # large strain: tens of centimetres on a 2 m column
+    assert np.linalg.det(pr.F).min() < 0.75
