@@ -95,6 +95,11 @@ typedef struct {
  *   krylov_rtol      BiCGStab stops at ||r|| <= krylov_rtol ||R^k||; krylov_max caps iterations
  *   krylov_check     iterations between host checks of the convergence flag (>= 1)
  *   mg_smooth        pre/post smoothing sweeps of each multigrid V-cycle (>= 1)
+ *   drained_surface  1: zero pore pressure on the current free surface of the material (Sec. 5.3:
+ *                    a drained top that follows the settling material), imposed at the start
+ *                    of every step on the active nodes that have an inactive node among their
+ *                    3^dim - 1 neighbours inside the grid (the grid edges are supports or
+ *                    symmetry planes, not free surfaces); 0: boundary data only
  */
 typedef struct {
     int shape;
@@ -109,6 +114,7 @@ typedef struct {
     int krylov_max;
     int krylov_check;
     int mg_smooth;
+    int drained_surface;
 } ppmpm_options;
 
 /* Boundary data of one step on the grid nodes (natural order).

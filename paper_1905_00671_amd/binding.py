@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("newton_rtol", ctypes.c_double),
                 ("newton_atol_u", ctypes.c_double), ("newton_atol_p", ctypes.c_double),
                 ("newton_max", ctypes.c_int), ("krylov_rtol", ctypes.c_double),
-                ("krylov_max", ctypes.c_int), ("krylov_check", ctypes.c_int), ("mg_smooth", ctypes.c_int)]
+                ("krylov_max", ctypes.c_int), ("krylov_check", ctypes.c_int), ("mg_smooth", ctypes.c_int),
+                ("drained_surface", ctypes.c_int)]
 
 
 class BC(ctypes.Structure):
@@ -150,7 +151,7 @@ def make_options(o, precision: int = FP64, **over) -> Options:
                 tau_scale=o.tau_scale, precision=precision, newton_rtol=o.newton_rtol,
                 newton_atol_u=getattr(o, "newton_atol_u", 0.0), newton_atol_p=getattr(o, "newton_atol_p", 0.0),
                 newton_max=o.newton_max, krylov_rtol=o.krylov_rtol, krylov_max=o.krylov_max,
-                krylov_check=4, mg_smooth=1)
+                krylov_check=4, mg_smooth=1, drained_surface=int(getattr(o, "drained_surface", 0)))
     vals.update(over)
     return Options(**vals)
 

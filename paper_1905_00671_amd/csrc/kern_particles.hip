@@ -328,6 +328,34 @@ __global__ void k_p2g(Batch B) {
     }
 }
 
+// Drained free surface (Sec. 5.3): the pore pressure of an active node with an inactive node
+// among its 3^dim - 1 neighbours inside the grid is held at zero for the step.  Reads the nodal
+// masses of k_p2g, so it runs as a kernel of its own after it.
+template <int DIM>
+__global__ void k_drain_surface(Batch B) {
+    PROB_PROLOGUE
+    if (tid >= d->Nnode || !d->drain) return;
+    int n[3];
+    n[0] = (int)(tid % d->nn[0]);
+    n[1] = (int)((tid / d->nn[0]) % d->nn[1]);
+    n[2] = DIM == 3 ? (int)(tid / ((int64_t)d->nn[0] * d->nn[1])) : 0;
+    const int64_t pn = pad_index(d, n[0], n[1], n[2]);
+    if (!(d->M[pn] > 0.0)) return;
+    bool surf = false;
+    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int kx = n[0] + ox, ky = n[1] + oy, kz = n[2] + oz;
+                if (kx < 0 || kx >= d->nn[0] || ky < 0 || ky >= d->nn[1]) continue;
+                if (DIM == 3 && (kz < 0 || kz >= d->nn[2])) continue;
+                surf |= !(d->M[pad_index(d, kx, ky, kz)] > 0.0);
+            }
+    if (!surf) return;
+    const int64_t k = pn * (DIM + 1) + DIM;
+    d->dfree[k] = 0;
+    d->X[k] = 0.0;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Stages 3-4: G2P update of the working (sorted) state in place
 // ---------------------------------------------------------------------------------------------
@@ -479,6 +507,12 @@ void launch_p2g(const Group& g, hipStream_t st) {
     if (g.dim == 2 && g.shape == 0) PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<2, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
     else if (g.dim == 2 && g.shape == 1) PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<2, 1>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
     else PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<3, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
+}
+
+void launch_drain_surface(const Group& g, hipStream_t st) {
+    Batch B = make_batch(g.ddev, g.nnode, TPB);
+    if (g.dim == 2) hipLaunchKernelGGL((k_drain_surface<2>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
+    else hipLaunchKernelGGL((k_drain_surface<3>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
 }
 
 void launch_cell_proj(const Group& g, hipStream_t st) {

@@ -97,6 +97,7 @@ struct Dev {
     // per-step parameters
     double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
     double kin;   // inertia factor of the Newmark fixed-stress modulus (fs_term)
+    int drain;    // 1: zero pore pressure on the free surface of the material (k_drain_surface)
     int nlev;
     int ltail;    // first level handled by the fused small-level kernel
     int ls_stop;  // Schur-block hierarchy ends here with two Jacobi sweeps (>= ltail: not truncated)

@@ -440,6 +440,9 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
     launch_sort(g, st);
     if (g.shape == 0) launch_cell_proj(g, st);
     launch_p2g(g, st);
+    bool drain = false;
+    for (const ppmpm_problem* p : ps) drain |= p->h.drain != 0;
+    if (drain) launch_drain_surface(g, st);
     return PPMPM_OK;
 }
 
@@ -901,6 +904,7 @@ static ppmpm_status init_problem(ppmpm_problem* p, const ppmpm_grid* grid, const
     h.kappa = mat->k / mat->mu_f;
     h.phi0 = mat->phi0;
     h.alpha_vis = opt->dynamic ? mat->alpha_vis : 0.0;   // quasi-static: no viscous stress
+    h.drain = opt->drained_surface ? 1 : 0;
     h.rho_f = mat->rho_f;
     for (int a = 0; a < 3; ++a) h.g[a] = a < grid->dim ? mat->g[a] : 0.0;
     h.dt = 1.0;

@@ -126,12 +126,13 @@ def _run_steps(w, nsteps, precision, **over):
     pr = O.from_workload(w)
     gp = B.Problem.from_workload(w, precision=precision, **over)
     dyn, gimp = bool(w.options.dynamic), w.options.shape == W.GIMP
+    dt_of = w.meta.get("dt_of", lambda n: w.dt)
     errs = []
     try:
         for n in range(1, nsteps + 1):
             bc = w.bc(n)
-            st_o = pr.step(w.dt, bc)
-            st_g = gp.step(w.dt, bc)
+            st_o = pr.step(dt_of(n), bc)
+            st_g = gp.step(dt_of(n), bc)
             fe = field_errors(gpu_state(gp), oracle_state(pr), dyn, gimp)
             errs.append(dict(step=n, f=fe, newton=(st_o["newton_iters"], st_g["newton_iters"]),
                              krylov=st_g["krylov_total"]))
@@ -178,6 +179,10 @@ STEP_CASES = {
     # the paper's Newmark parameters (Sec. 3.2)
     "footing2d_dyn_paper_newmark": (lambda: W.config(2, nx=16, ny=16, width=2.5, empty_rows=2, nsteps=4,
                                                      beta=0.3025, gamma=0.6), 4),
+    # consolidation under self weight (Sec. 5.3) at the paper's coarser resolution: Hencky,
+    # Kozeny-Carman, gravity, drained free surface following the settling top, dt growing 1.2x
+    "self_weight_gimp": (lambda: W.self_weight(), 40),
+    "self_weight_linear_closed": (lambda: W.self_weight(h=0.25, ppa=2, shape=W.LINEAR, right_drained=False), 40),
 }
 
 
@@ -219,7 +224,8 @@ def test_step_parity_fp64(name):
 
 
 @pytest.mark.parametrize("name", ["terzaghi", "footing2d_qs_gimp", "footing3d", "footing2d_qs_gimp_kc",
-                                  "footing2d_dyn_gimp", "footing2d_dyn_paper_newmark", "footing2d_dyn_damped"])
+                                  "footing2d_dyn_gimp", "footing2d_dyn_paper_newmark", "footing2d_dyn_damped",
+                                  "self_weight_gimp"])
 def test_step_parity_mixed(name):
     make, nsteps = STEP_CASES[name]
     w = make()
