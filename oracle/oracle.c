@@ -353,6 +353,102 @@ void or_p2g(const or_grid* g, int shape, long np, const double* x, const double*
     }
 }
 
+/* Consistent mass matrix of eq. map-from-particles-to-nodes-consistent, M_ij = sum_mp S_i S_j m,
+ * as COO triplets: one per material point and ordered pair of its basis nodes (the caller sums
+ * duplicates).  Capacity: np * OR_MAXN^2 triplets.  Returns the number written. */
+long or_mass_matrix(const or_grid* g, int shape, long np, const double* x, const double* lp, const double* m,
+                    long* ri, long* ci, double* v) {
+    int d = g->dim;
+    int nodes[OR_MAXN];
+    double S[OR_MAXN], G[OR_MAXN * 3];
+    long cnt = 0;
+    for (long q = 0; q < np; q++) {
+        int n = or_basis(g, shape, x + q * d, lp ? lp + q * d : NULL, nodes, S, G, NULL);
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) {
+                ri[cnt] = nodes[i];
+                ci[cnt] = nodes[j];
+                v[cnt] = S[i] * S[j] * m[q];
+                cnt++;
+            }
+    }
+    return cnt;
+}
+
+/* 1D weights of the nodes base..base+cnt-1 along axis a for a point at xa with half-length lpa:
+ * the hat of the containing cell (original MPM) or the GIMP weights of eq. gimp-basis (domain
+ * clipped to the grid, nodes whose support only touches the domain carry 0).  Returns cnt. */
+static int axis_weights(const or_grid* g, int shape, int a, double xa, double lpa, int* base, double* w) {
+    int c = cell_of(g, a, xa);
+    if (shape == 0) {
+        *base = c;
+        double xl = g->x0[a] + g->h * c;
+        for (int k = 0; k < 2; k++) {
+            w[k] = 1.0 - fabs(xa - (xl + g->h * k)) / g->h;
+            if (w[k] < 0.0) w[k] = 0.0;
+        }
+        return 2;
+    }
+    double lo = g->x0[a], hi = g->x0[a] + g->h * g->nc[a];
+    double A = xa - lpa, B = xa + lpa;
+    if (A < lo) A = lo;
+    if (B > hi) B = hi;
+    *base = c - 1;
+    for (int k = 0; k < 4; k++) {
+        int ni = c - 1 + k;
+        double xi = g->x0[a] + g->h * ni, dw;
+        w[k] = 0.0;
+        if (ni < 0 || ni > g->nc[a]) continue;
+        if (gimp_s0_1d(A, B, xi, g->h) == 0.0) continue;
+        gimp_1d(A, B, xi, g->h, &w[k], &dw);
+    }
+    return 4;
+}
+
+/* Nodal forces of surface tractions carried by material points (the Neumann load of the strip
+ * footing of Sec. 5.2, applied through the boundary points' domains): point q carries the force
+ * F_q (the traction times the point's share of the loaded boundary) on the face of its domain
+ * whose outward normal is the coordinate axis n_q (+-1 in one component, 0 elsewhere).  Along
+ * that axis the grid's linear hat is evaluated on the face, x_a + lp_a n_a; along the other axes
+ * the point's own 1D basis (hat or GIMP) distributes the force.  nrm NULL, or a zero normal: the
+ * force acts through the point's own basis along every axis.  fext[nnode*dim] is accumulated. */
+void or_surface_force(const or_grid* g, int shape, long np, const double* x, const double* lp,
+                      const double* F, const double* nrm, double* fext) {
+    int d = g->dim;
+    int n1[3] = {g->nc[0] + 1, g->nc[1] + 1, d == 3 ? g->nc[2] + 1 : 1};
+    for (long q = 0; q < np; q++) {
+        int any = 0;
+        for (int a = 0; a < d; a++) any |= F[q * d + a] != 0.0;
+        if (!any) continue;
+        int base[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+        double w[3][4];
+        for (int a = 0; a < d; a++) {
+            double xa = x[q * d + a], lpa = lp ? lp[q * d + a] : 0.0;
+            double na = nrm ? nrm[q * d + a] : 0.0;
+            if (fabs(na) > 0.5) {
+                double e = xa + lpa * (na > 0 ? 1.0 : -1.0);
+                cnt[a] = axis_weights(g, 0, a, e, 0.0, &base[a], w[a]);   /* hat on the face */
+            } else {
+                cnt[a] = axis_weights(g, shape, a, xa, lpa, &base[a], w[a]);
+            }
+        }
+        for (int k2 = 0; k2 < cnt[2]; k2++)
+            for (int k1 = 0; k1 < cnt[1]; k1++)
+                for (int k0 = 0; k0 < cnt[0]; k0++) {
+                    int kk[3] = {k0, k1, k2}, idx[3] = {0, 0, 0}, skip = 0;
+                    double s = 1.0;
+                    for (int a = 0; a < d; a++) {
+                        idx[a] = base[a] + kk[a];
+                        if (idx[a] < 0 || idx[a] >= n1[a]) skip = 1;
+                        else s *= w[a][kk[a]];
+                    }
+                    if (skip || s == 0.0) continue;
+                    long node = idx[0] + (long)n1[0] * (idx[1] + (long)n1[1] * idx[2]);
+                    for (int b = 0; b < d; b++) fext[node * d + b] += s * F[q * d + b];
+                }
+    }
+}
+
 /* Cell sums of the projection operator for original MPM (eq. projection-operator, integrated at
  * the material points of each cell with their t_n volumes): Ve[c] = sum V, qe[c*2^d + k] =
  * sum V N_k over the points of cell c; Pi N_k = qe/Ve. */

@@ -82,6 +82,9 @@ def lib():
         _lib.or_assemble.restype = l
         _lib.or_assemble.argtypes = [vp, vp, vp, l, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, l, vp, vp]
         _lib.or_g2p.restype = l
+        _lib.or_mass_matrix.restype = l
+        _lib.or_mass_matrix.argtypes = [vp, i, l] + [vp] * 6
+        _lib.or_surface_force.argtypes = [vp, i, l] + [vp] * 5
         _lib.or_g2p.argtypes = [vp, vp, vp, l] + [vp] * 13
     return _lib
 
@@ -181,7 +184,9 @@ class OracleProblem:
         return s, keep
 
     def p2g(self) -> Dict[str, np.ndarray]:
-        """Stage 1 (eq. map-from-particles-to-nodes), lumped mass."""
+        """Stage 1: eq. map-from-particles-to-nodes (lumped mass), or, with the consistent_mass
+        option, eq. map-from-particles-to-nodes-consistent (solve M f = sum S m f_mp with the
+        consistent mass matrix over the active nodes) for every mapped field."""
         g, d = self.grid, self.grid.dim
         nn = g.nnode
         M = np.zeros(nn)
@@ -203,12 +208,70 @@ class OracleProblem:
             out["an"] = np.where(act[:, None], Ma.reshape(nn, d) / safe[:, None], 0.0).reshape(-1)
             out["pdn"] = np.where(act, Mpd / safe, 0.0)
             out["pddn"] = np.where(act, Mpdd / safe, 0.0)
+        if getattr(self.opt, "consistent_mass", 0):
+            cols = {"Pn": Mp}
+            if dyn:
+                cols.update(vn=Mv, an=Ma, pdn=Mpd, pddn=Mpdd)
+            for k, f in self.consistent_map(M, cols).items():
+                out[k] = f
         if self.opt.shape == 0:
             nc = g.ncells
             Ve = np.zeros(nc)
             qe = np.zeros(nc * (1 << d))
             lib().or_cell_proj(_a(self._g), self.np, _p(self.x), _p(self.V), _p(Ve), _p(qe))
             out["Ve"], out["qe"] = Ve, qe
+        return out
+
+    def mass_matrix(self):
+        """Consistent mass matrix M_ij = sum_mp S_i S_j m (eq. map-from-particles-to-nodes-consistent), CSR."""
+        g, d = self.grid, self.grid.dim
+        nb = 4 ** d if self.opt.shape == 1 else 2 ** d
+        cap = self.np * nb * nb
+        ri = np.empty(cap, np.int64)
+        ci = np.empty(cap, np.int64)
+        v = np.empty(cap)
+        n = lib().or_mass_matrix(_a(self._g), self.opt.shape, self.np, _p(self.x), _p(self.lp), _p(self.m),
+                                 _p(ri), _p(ci), _p(v))
+        return sp.coo_matrix((v[:n], (ri[:n], ci[:n])), shape=(g.nnode, g.nnode)).tocsr()
+
+    # Nodes whose lumped mass is below this fraction of the step's largest nodal mass keep the
+    # lumped value in the consistent mapping (reading: the consistent mass matrix is singular in
+    # the limit of nodes that a point domain barely reaches).
+    LIGHT_NODE = 1e-2
+
+    def consistent_map(self, mass, sums):
+        """Nodal fields f of eq. map-from-particles-to-nodes-consistent from their right-hand sides
+        b = sum_mp S_i m f_mp (dict of flat arrays, vector fields node-major).  Nodes with lumped
+        mass M_i >= LIGHT_NODE max M ("heavy") solve sum_j M_ij f_j = b_i, the other active nodes
+        ("light") keep the lumped value b_i / M_i and enter the heavy rows as known values
+        (M_HH f_H = b_H - M_HL f_L, sparse direct, one factorization); inactive nodes get 0."""
+        nn = self.grid.nnode
+        act = mass > 0
+        heavy = act & (mass >= self.LIGHT_NODE * mass.max())
+        light = act & ~heavy
+        H, L = np.flatnonzero(heavy), np.flatnonzero(light)
+        Mall = self.mass_matrix()
+        lu = spla.splu(Mall[H][:, H].tocsc())
+        MHL = Mall[H][:, L]
+        safe = np.where(act, mass, 1.0)
+        out = {}
+        for k, b in sums.items():
+            nc = b.size // nn
+            B = b.reshape(nn, nc)
+            X = np.where(act[:, None], B / safe[:, None], 0.0)       # lumped values
+            for c in range(nc):
+                X[H, c] = lu.solve(np.ascontiguousarray(B[H, c] - MHL @ X[L, c]))
+            out[k] = X.reshape(-1) if nc > 1 else X[:, 0].copy()
+        return out
+
+    def surface_force(self, F, nrm=None):
+        """Nodal forces [nnode*dim] of the tractions carried by the points (or_surface_force)."""
+        g, d = self.grid, self.grid.dim
+        F = np.ascontiguousarray(F, np.float64).reshape(self.np, d)
+        nr = None if nrm is None else np.ascontiguousarray(nrm, np.float64).reshape(self.np, d)
+        out = np.zeros(g.nnode * d)
+        lib().or_surface_force(_a(self._g), self.opt.shape, self.np, _p(self.x), _p(self.lp), _p(F), _p(nr),
+                               _p(out))
         return out
 
     def assemble(self, U, P, nodal, dt, want_J=True, vin=None):
@@ -275,6 +338,8 @@ class OracleProblem:
         P = np.where(pfix, p_val, nodal["Pn"]) * act
         fext = np.zeros((nn, d + 1))
         fext[:, :d] = bc["f_ext"].reshape(nn, d)
+        if bc.get("point_force") is not None:
+            fext[:, :d] += self.surface_force(bc["point_force"], bc.get("point_normal")).reshape(nn, d)
         fext[:, d] = -bc["q_ext"]
         fext = fext.reshape(-1)
         scale_u = self.mat.E * g.h ** (d - 1)

@@ -101,6 +101,7 @@ class Options:
     krylov_rtol: float = 1e-8
     krylov_max: int = 4000
     drained_surface: int = 0       # 1: zero pore pressure on the current free surface of the material
+    consistent_mass: int = 0       # 1: consistent-mass P2G mapping (solve with M_ij) instead of lumped
 
 
 @dataclass
@@ -359,6 +360,61 @@ def self_weight(h: float = 0.125, ppa: int = 5, width: float = 2.0, height: floa
 
     return Workload("self_weight", grid, mat, opt, parts, dt0, nsteps, bc,
                     meta=dict(H=height, W=width, K=K, dt_of=dt_of, k=k))
+
+
+def harmonic_footing(h: float = 0.25, ppa: int = 2, width: float = 10.0, depth: float = 10.0,
+                     half_b: float = 1.0, empty_rows: int = 4, dt: float = 1e-3, nsteps: int = 400,
+                     w0: float = 3e6, omega: float = 100.0, shape: int = GIMP, tau_kind: int = TAU_WHITE,
+                     consistent_mass: int = 1) -> Workload:
+    """Strip footing under harmonic loading (the paper's second example): right half of a 20 m
+    wide, 10 m deep saturated ground, 40 x 40 cells of 0.25 m with 2 x 2 points per cell and 4
+    empty rows (160 cells) above, Hencky skeleton with lambda = 8.4 MPa and G = 5.6 MPa,
+    k = 1e-14 m^2, mu_f = 1e-3 Pa s, rho_s = 2.5 t/m^3, rho_f = 1 t/m^3, porosity 0.33, Kelvin
+    damping alpha_vis = 0.04 s, Newmark with the paper's beta = 0.3025, gamma = 0.6, consistent
+    mass mapping, dt = 1e-3 s for 400 steps.  The footing (half-width 1 m) pushes with
+    w = w0 (1 - cos(omega t)), w0 = 3 MPa, omega = 100 rad/s, as a traction on the top faces of
+    the points under it (point_force, outward normal +y, at the end of each step).
+    Readings: the footing is impermeable and the rest of the top is drained (p = 0 on the grid
+    nodes at and above the initial ground level beyond the footing, so that the drained
+    boundary holds where the ground heaves); the base is fixed, the lateral faces are rollers,
+    and both are impermeable.  meta['probes']: the points A, B, C (elevations 9.4375, 4.9375,
+    0.0625 m on the symmetry line)."""
+    nx, ny = int(round(width / h)), int(round(depth / h))
+    grid = Grid(2, (nx, ny + empty_rows), h, (0.0, 0.0, 0.0))
+    lam, G = 8.4e6, 5.6e6
+    E = G * (3 * lam + 2 * G) / (lam + G)
+    nu = lam / (2 * (lam + G))
+    mat = Material(model=HENCKY, E=E, nu=nu, k=1e-14, mu_f=1e-3, rho_s=2500.0, rho_f=1000.0, phi0=0.33,
+                   g=(0.0, 0.0, 0.0), alpha_vis=0.04)
+    opt = Options(shape=shape, dynamic=1, beta=0.3025, gamma=0.6, tau_kind=tau_kind,
+                  consistent_mass=consistent_mass)
+    parts = fill_particles(grid, (0, 0), (nx, ny), mat.rho0, ppa=ppa)
+    X = grid.node_coords()
+    t = _tol(grid)
+    x = parts.x
+    top = x[:, 1] > depth - h / ppa
+    loaded = top & (x[:, 0] < half_b)
+    seg = 2.0 * parts.lp[:, 0]                   # each loaded point's share of the footing width
+    normal = np.zeros_like(x)
+    normal[loaded, 1] = 1.0
+
+    def load(step: int) -> float:
+        return w0 * (1.0 - np.cos(omega * step * dt))
+
+    def bc(step: int):
+        b = empty_bc(grid)
+        box_supports(grid, b, (width,))
+        b["p_fixed"][(X[:, 1] >= depth - t) & (X[:, 0] > half_b + t)] = 1
+        f = np.zeros_like(x)
+        f[loaded, 1] = -load(step) * seg[loaded]
+        b["point_force"] = f
+        b["point_normal"] = normal
+        return b
+
+    probes = {name: int(np.argmin(np.hypot(x[:, 0] - h / (2 * ppa), x[:, 1] - y)))
+              for name, y in (("A", 9.4375), ("B", 4.9375), ("C", 0.0625))}
+    return Workload("harmonic_footing", grid, mat, opt, parts, dt, nsteps, bc,
+                    meta=dict(load=load, probes=probes, loaded=np.flatnonzero(loaded), half_b=half_b))
 
 
 def jittered_box(nx: int = 8, ny: int = 8, h: float = 0.25, seed: int = 0, shape: int = LINEAR,
