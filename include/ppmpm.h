@@ -95,6 +95,14 @@ typedef struct {
  *   krylov_rtol      BiCGStab stops at ||r|| <= krylov_rtol ||R^k||; krylov_max caps iterations
  *   krylov_check     iterations between host checks of the convergence flag (>= 1)
  *   mg_smooth        pre/post smoothing sweeps of each multigrid V-cycle (>= 1)
+ *   consistent_mass  1: Stage 1 maps p (and v, a, pdot, pddot on dynamic steps) with the consistent
+ *                    mass matrix (eq. map-from-particles-to-nodes-consistent, used by the paper for
+ *                    cyclic loading, Sec. 5.2): sum_j M_ij f_j = sum_mp S_i m f_mp, M_ij = sum_mp
+ *                    S_i S_j m, solved by conjugate gradients to 1e-13 relative residual.  Nodes
+ *                    whose lumped mass is below 1e-2 of the problem's largest nodal mass keep the
+ *                    lumped value (the consistent matrix is singular in the limit of nodes that a
+ *                    point domain barely reaches).  Costs a stream synchronization every 8
+ *                    iterations; more workspace (ppmpm_workspace_bytes).  0: lumped (default)
  *   drained_surface  1: zero pore pressure on the current free surface of the material (Sec. 5.3:
  *                    a drained top that follows the settling material), imposed at the start
  *                    of every step on the active nodes that have an inactive node among their
@@ -115,6 +123,7 @@ typedef struct {
     int krylov_check;
     int mg_smooth;
     int drained_surface;
+    int consistent_mass;
 } ppmpm_options;
 
 /* Boundary data of one step on the grid nodes (natural order).
@@ -124,8 +133,18 @@ typedef struct {
  *   p_fixed[nnode], p_val     Dirichlet pore pressure p^ at the end of the step
  *   f_ext[nnode*dim]          nodal external forces (integrated traction t^)
  *   q_ext[nnode]              nodal inflow (integrated flux q^ = -n.q)
+ *   point_force[np*dim]       forces carried by material points (traction times the point's share
+ *                             of the loaded boundary; caller's point order), for Neumann loads
+ *                             that follow the material (Sec. 5.2): the force acts on the face of
+ *                             the point's domain whose outward normal is point_normal (a
+ *                             coordinate axis, +-1 in one component); along that axis the grid's
+ *                             linear hat is evaluated on the face x_a + lp_a n_a, along the other
+ *                             axes the point's own basis (hat or GIMP) distributes it.  The nodal
+ *                             forces of the loaded points are added with atomics (sums in
+ *                             nondeterministic order, rounding-level differences only)
+ *   point_normal[np*dim]      NULL or a zero row: the force acts through the point's own basis
  * Any pointer may be NULL (no condition / zero).  Conditions on inactive nodes (no material
- * point support) are ignored. */
+ * point support) are ignored.  The point arrays are read with the same `where` as the others. */
 typedef struct {
     const uint8_t* u_fixed;
     const double* u_inc;
@@ -134,6 +153,8 @@ typedef struct {
     const double* f_ext;
     const double* q_ext;
     int where;
+    const double* point_force;
+    const double* point_normal;
 } ppmpm_bc;
 
 #define PPMPM_MAX_HIST 64
@@ -153,6 +174,7 @@ typedef struct {
     double t_sort, t_assemble, t_precond, t_krylov, t_g2p, t_total;
     int krylov_breakdowns;
     int ngrid_levels;
+    int mass_iters;   /* CG iterations of the consistent-mass mapping (0: lumped) */
 } ppmpm_step_stats;
 
 /* Device bytes of workspace a problem with this grid, particle count and options needs.

@@ -46,13 +46,13 @@ class Options(ctypes.Structure):
                 ("newton_atol_u", ctypes.c_double), ("newton_atol_p", ctypes.c_double),
                 ("newton_max", ctypes.c_int), ("krylov_rtol", ctypes.c_double),
                 ("krylov_max", ctypes.c_int), ("krylov_check", ctypes.c_int), ("mg_smooth", ctypes.c_int),
-                ("drained_surface", ctypes.c_int)]
+                ("drained_surface", ctypes.c_int), ("consistent_mass", ctypes.c_int)]
 
 
 class BC(ctypes.Structure):
     _fields_ = [("u_fixed", ctypes.c_void_p), ("u_inc", ctypes.c_void_p), ("p_fixed", ctypes.c_void_p),
                 ("p_val", ctypes.c_void_p), ("f_ext", ctypes.c_void_p), ("q_ext", ctypes.c_void_p),
-                ("where", ctypes.c_int)]
+                ("where", ctypes.c_int), ("point_force", ctypes.c_void_p), ("point_normal", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -61,7 +61,7 @@ class StepStats(ctypes.Structure):
                 ("res_u", ctypes.c_double * MAX_HIST), ("res_p", ctypes.c_double * MAX_HIST),
                 ("t_sort", ctypes.c_double), ("t_assemble", ctypes.c_double), ("t_precond", ctypes.c_double),
                 ("t_krylov", ctypes.c_double), ("t_g2p", ctypes.c_double), ("t_total", ctypes.c_double),
-                ("krylov_breakdowns", ctypes.c_int), ("ngrid_levels", ctypes.c_int)]
+                ("krylov_breakdowns", ctypes.c_int), ("ngrid_levels", ctypes.c_int), ("mass_iters", ctypes.c_int)]
 
     def as_dict(self) -> Dict:
         n = self.newton_iters
@@ -69,7 +69,8 @@ class StepStats(ctypes.Structure):
                     krylov_iters=list(self.krylov_iters[:n]), res_u=list(self.res_u[: n + 1]),
                     res_p=list(self.res_p[: n + 1]), t_sort=self.t_sort, t_assemble=self.t_assemble,
                     t_precond=self.t_precond, t_krylov=self.t_krylov, t_g2p=self.t_g2p, t_total=self.t_total,
-                    krylov_breakdowns=self.krylov_breakdowns, ngrid_levels=self.ngrid_levels)
+                    krylov_breakdowns=self.krylov_breakdowns, ngrid_levels=self.ngrid_levels,
+                    mass_iters=self.mass_iters)
 
 
 _lib = None
@@ -151,9 +152,13 @@ def make_options(o, precision: int = FP64, **over) -> Options:
                 tau_scale=o.tau_scale, precision=precision, newton_rtol=o.newton_rtol,
                 newton_atol_u=getattr(o, "newton_atol_u", 0.0), newton_atol_p=getattr(o, "newton_atol_p", 0.0),
                 newton_max=o.newton_max, krylov_rtol=o.krylov_rtol, krylov_max=o.krylov_max,
-                krylov_check=4, mg_smooth=1, drained_surface=int(getattr(o, "drained_surface", 0)))
+                krylov_check=4, mg_smooth=1, drained_surface=int(getattr(o, "drained_surface", 0)),
+                consistent_mass=int(getattr(o, "consistent_mass", 0)))
     vals.update(over)
     return Options(**vals)
+
+
+BC_KEYS = ("u_fixed", "u_inc", "p_fixed", "p_val", "f_ext", "q_ext", "point_force", "point_normal")
 
 
 class BCArrays:
@@ -161,7 +166,7 @@ class BCArrays:
 
     def __init__(self, d: Dict):
         self.keep = {}
-        for k in ("u_fixed", "u_inc", "p_fixed", "p_val", "f_ext", "q_ext"):
+        for k in BC_KEYS:
             v = d.get(k)
             if v is not None and isinstance(v, np.ndarray):
                 dt = np.uint8 if k in ("u_fixed", "p_fixed") else np.float64
@@ -169,8 +174,8 @@ class BCArrays:
             self.keep[k] = v
         first = next((v for v in self.keep.values() if v is not None), None)
         where = HOST if first is None else _where(first)
-        self.c = BC(*[_ptr(self.keep[k]) for k in ("u_fixed", "u_inc", "p_fixed", "p_val", "f_ext", "q_ext")],
-                    where)
+        ptr = {k: _ptr(self.keep[k]) for k in BC_KEYS}
+        self.c = BC(*[ptr[k] for k in BC_KEYS[:6]], where, ptr["point_force"], ptr["point_normal"])
 
 
 class Problem:

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libppmpm.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["kern_particles.hip", "kern_assemble.hip", "kern_solver.hip", "kern_mg.hip", "runtime.hip"]
+SOURCES = ["kern_particles.hip", "kern_assemble.hip", "kern_solver.hip", "kern_mg.hip", "kern_mass.hip", "runtime.hip"]
 # packed FP32 instructions are kept out of every HIP object
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

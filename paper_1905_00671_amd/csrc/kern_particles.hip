@@ -308,6 +308,19 @@ __global__ void k_p2g(Batch B) {
     d->M[pn] = M;
     d->Pn[pn] = Mp * inv;
     d->Mp[pn] = Vs;
+    if (d->cons) {
+        // right-hand sides sum S m f of the consistent mapping (kern_mass.hip), natural node order
+        const int64_t N = d->Nnode;
+        d->mb[tid] = Mp;
+        if (dyn) {
+            for (int a = 0; a < DIM; ++a) {
+                d->mb[(1 + a) * N + tid] = Mv[a];
+                d->mb[(1 + DIM + a) * N + tid] = Ma[a];
+            }
+            d->mb[(1 + 2 * DIM) * N + tid] = Mpd;
+            d->mb[(2 + 2 * DIM) * N + tid] = Mpdd;
+        }
+    }
     if (dyn) {
         for (int a = 0; a < DIM; ++a) {
             bool fx = d->bcfix[pn * bs + a] != 0;

@@ -8,6 +8,7 @@
 #include <initializer_list>
 #include <vector>
 
+#include "../../include/ppmpm.h"
 #include "ppmpm_internal.hpp"
 
 namespace ppm {
@@ -109,6 +110,14 @@ void launch_bc(const Dev* dd, int64_t nnode, const uint8_t* uf, const double* ui
 void launch_p2g(const Group& g, hipStream_t st);
 // zero pore pressure on the free surface of the problems with Dev::drain set (after launch_p2g)
 void launch_drain_surface(const Group& g, hipStream_t st);
+
+// kern_mass.hip
+// nodal forces of the point tractions F[q] (caller order, NULL: none) on the sorted points
+void launch_point_force(const Group& g, const std::vector<const double*>& F, const std::vector<const double*>& nrm,
+                        hipStream_t st);
+// consistent-mass mapping of the P2G fields of the problems with Dev::cons set (after
+// launch_p2g); synchronizes the stream to check convergence; iters: CG iterations taken
+ppmpm_status launch_mass_solve(const Group& g, const std::vector<const Dev*>& host_copies, hipStream_t st, int* iters);
 void launch_cell_proj(const Group& g, hipStream_t st);
 void launch_g2p(const Group& g, hipStream_t st);
 

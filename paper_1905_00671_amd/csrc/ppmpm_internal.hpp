@@ -9,6 +9,7 @@ namespace ppm {
 
 constexpr int MAXB = 64;      // problems per batched launch
 constexpr int TPB = 256;      // threads per block of the streaming kernels
+constexpr int MCOL = 9;       // most fields of one consistent-mass mapping (3D dynamic: 2 dim + 3)
 constexpr int MAXLEV = 12;    // multigrid levels
 constexpr int CMAX = 112;     // largest coarsest-level system solved by a dense inverse (LDS, 101 KB)
 constexpr int TAILMAX = 200;  // levels with at most this many nodes run inside one fused kernel
@@ -98,6 +99,19 @@ struct Dev {
     double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
     double kin;   // inertia factor of the Newmark fixed-stress modulus (fs_term)
     int drain;    // 1: zero pore pressure on the free surface of the material (k_drain_surface)
+    // consistent-mass mapping of the P2G fields (kern_mass.hip), when cons is set
+    int cons;
+    int ncol;         // mapped fields: p (quasi-static); p, v, a, pdot, pddot (dynamic: 2 dim + 3)
+    double* mrow;     // [S][Nnode] consistent mass rows over the fixed stencil (natural node order)
+    double* mb;       // [ncol][Nnode] right-hand sides sum S m f
+    double* mx;       // [ncol][Nnode] CG iterate (the mapped fields)
+    double* mr;       // [ncol][Nnode] residual
+    double* mz;       // [ncol][Nnode] preconditioned residual
+    double* md;       // [ncol][Nnode] search direction
+    double* mq;       // [ncol][Nnode] M d
+    uint8_t* mheavy;  // [Nnode] 1: row solved with the consistent mass; 0: lumped value kept
+    double* mpart;    // [maxblocks][3 MCOL] block partials
+    double* mscal;    // [MCOL * 8 + 8] per-column CG scalars, then problem-wide slots
     int nlev;
     int ltail;    // first level handled by the fused small-level kernel
     int ls_stop;  // Schur-block hierarchy ends here with two Jacobi sweeps (>= ltail: not truncated)

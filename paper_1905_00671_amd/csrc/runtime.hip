@@ -102,6 +102,7 @@ struct ppmpm_problem {
     bool have_particles = false;
     bool have_jacobian = false;
     int nrec = 0;
+    int mass_iters = 0;      // CG iterations of the last consistent-mass mapping
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -263,6 +264,20 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
     h.maxblocks = std::max<int64_t>(std::max<int64_t>((maxrows + TPB - 1) / TPB + 1, node_tiles(D, h.nn)),
                                     spmv_blocks(D, h.Nnode, true));
     h.partial = c.take<double>((size_t)h.maxblocks * 4);
+    h.cons = o->consistent_mass ? 1 : 0;
+    h.ncol = o->dynamic ? 2 * D + 3 : 1;
+    if (h.cons) {
+        const int64_t N = h.Nnode;
+        h.mrow = c.take<double>((size_t)h.S * N);
+        double** mv[6] = {&h.mb, &h.mx, &h.mr, &h.mz, &h.md, &h.mq};
+        for (auto* v : mv) *v = c.take<double>((size_t)h.ncol * N);
+        h.mheavy = c.take<uint8_t>(N);
+        h.mpart = c.take<double>((size_t)h.maxblocks * 3 * MCOL);
+        h.mscal = c.take<double>(MCOL * 8 + 8);
+    } else {
+        h.mrow = h.mb = h.mx = h.mr = h.mz = h.md = h.mq = h.mpart = h.mscal = nullptr;
+        h.mheavy = nullptr;
+    }
     h.scal = c.take<double>(NSCAL);
     h.flags = c.take<int>(NFLAG);
     return c.off + 256;
@@ -272,7 +287,8 @@ size_t io_bytes(const Dev& h) {
     const int D = h.dim;
     size_t a = (size_t)h.Np * (3 * D + 3) * sizeof(double);
     size_t b = (size_t)h.Np * 9 * sizeof(double);
-    size_t c = (size_t)h.Nnode * (D + 1) * 34 + 8192;   // boundary data + state + residual
+    // boundary data (+ point tractions and normals) + state + residual
+    size_t c = (size_t)h.Nnode * (D + 1) * 34 + (size_t)h.Np * D * 16 + 8192;
     size_t e = (size_t)h.Nnode * (D + 1) * sizeof(double) * 2;
     return std::max(std::max(a, b), std::max(c, e)) + 4096;
 }
@@ -398,6 +414,8 @@ ppmpm_status read_scalars(const std::vector<ppmpm_problem*>& ps, hipStream_t st)
 // cells, P2G.  BC staging happens per problem.
 ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, const ppmpm_bc* const* bcs,
                     hipStream_t st) {
+    std::vector<const double*> pforce, pnormal;
+    bool any_force = false;
     for (size_t i = 0; i < ps.size(); ++i) {
         ppmpm_problem* p = ps[i];
         Dev& h = p->h;
@@ -433,15 +451,31 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
         const double* pv = bc ? (const double*)to_device(p, bc->p_val, nn * 8, where, off, st) : nullptr;
         const double* fe = bc ? (const double*)to_device(p, bc->f_ext, nn * D * 8, where, off, st) : nullptr;
         const double* qe = bc ? (const double*)to_device(p, bc->q_ext, nn * 8, where, off, st) : nullptr;
+        const double* pfo = bc ? (const double*)to_device(p, bc->point_force, p->np * D * 8, where, off, st) : nullptr;
+        const double* pno = pfo ? (const double*)to_device(p, bc->point_normal, p->np * D * 8, where, off, st) : nullptr;
         if (off > p->iob) return fail(PPMPM_E_OOM, "io staging too small");
         launch_bc(p->d, nn, uf, ui, pf, pv, fe, qe, st);
+        pforce.push_back(pfo);
+        pnormal.push_back(pno);
+        any_force |= pfo != nullptr;
     }
     Group g = make_group(ps);
     launch_sort(g, st);
+    if (any_force) launch_point_force(g, pforce, pnormal, st);
     if (g.shape == 0) launch_cell_proj(g, st);
     launch_p2g(g, st);
-    bool drain = false;
-    for (const ppmpm_problem* p : ps) drain |= p->h.drain != 0;
+    bool drain = false, cons = false;
+    for (const ppmpm_problem* p : ps) {
+        drain |= p->h.drain != 0;
+        cons |= p->h.cons != 0;
+    }
+    if (cons) {
+        int it = 0;
+        ppmpm_status s = launch_mass_solve(g, g.hdev, st, &it);
+        if (s) return fail(s, s == PPMPM_E_NEWTON ? "consistent mass mapping did not converge"
+                                                  : "consistent mass mapping failed");
+        for (ppmpm_problem* p : ps) p->mass_iters = p->h.cons ? it : 0;
+    }
     if (drain) launch_drain_surface(g, st);
     return PPMPM_OK;
 }
@@ -786,6 +820,7 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
             so.t_g2p = secs(t6, t7);
             so.status = g.ns[k].status;
             so.ngrid_levels = g.ps[k]->h.nlev;
+            so.mass_iters = g.ps[k]->mass_iters;
             so.t_total = secs(t0, t7);
         }
     return PPMPM_OK;
@@ -1001,6 +1036,7 @@ ppmpm_status ppmpm_eval_residual(ppmpm_problem* p, double dt, const ppmpm_bc* bc
     const int D = p->h.dim;
     // stage1 used the front of the io region for the boundary data; stage the state after it
     size_t off = (size_t)nn * (D + 1) * (2 * sizeof(double) + 2) + 4096;
+    if (bc && bc->point_force) off += (size_t)p->np * D * 16 + 512;
     const double* dU = (const double*)to_device(p, U, nn * D * 8, where, off);
     const double* dP = (const double*)to_device(p, P, nn * 8, where, off);
     double* dR = where == PPMPM_DEVICE ? R : (double*)(p->io + ((off + 255) & ~size_t(255)));

@@ -63,7 +63,8 @@ def _run(w, ref, nsteps, precision, tol, tol_other):
                     worst[k] = max(worst.get(k, 0.0), v)
                 assert fe["u"] < tol and fe["p"] < tol, (n, fe)
                 for k, v in fe.items():
-                    assert v < tol_other, (n, k, fe)
+                    lim = tol_other.get(k, 10 * tol) if isinstance(tol_other, dict) else tol_other
+                    assert v < lim, (n, k, fe)
     finally:
         gp.close()
     return worst
@@ -120,3 +121,48 @@ def test_config4_replica_mixed_prefix():
     w = W.footing3d(n=24, size=3.0, half_b=0.25, nsteps=20)
     print(f"[config 4 replica mixed] {w.particles.n} points, 10 steps", flush=True)
     _run(w, ref, 10, 1, 1e-6, 1e-5)
+
+
+def test_harmonic_footing_fp64_all_steps():
+    """Sec. 5.2 strip footing under the harmonic load w = 3 - 3 cos(100 t) MPa: consistent-mass
+    mapping, tractions on the top faces of the points under the footing, Hencky skeleton, Kelvin
+    damping, Newmark beta = 0.3025, gamma = 0.6; all 400 steps against the oracle."""
+    ref = _load("harmonic_footing")
+    w = W.harmonic_footing()
+    last = int(ref["last_step"])
+    print(f"[harmonic footing fp64] {w.particles.n} points, {last} steps", flush=True)
+    # pddot = (p - p_pred) / (beta dt^2) amplifies a relative p difference by about
+    # 1 / (beta (omega dt)^2) ~ 330 at dt = 1 ms, omega = 100 rad/s (pdot by ~ 1 / (beta omega dt))
+    _run(w, ref, last, 0, 1e-10, {"pdd": 1e-7, "pd": 1e-8})
+
+
+def test_harmonic_footing_newton_krylov_pattern():
+    """Convergence pattern of Table 1 at the paper's tolerances (Newton 1e-8 per residual block,
+    BiCGStab 1e-8 ||R^k||) at steps 100, 200, 300 and 400: three Newton iterations, each cutting
+    the residual by orders of magnitude (near-quadratic convergence of the exact Jacobian), and a
+    small number of Krylov iterations per Newton iteration with the block preconditioner."""
+    from paper_1905_00671_amd import binding as B
+    w = W.harmonic_footing()
+    gp = B.Problem.from_workload(w, precision=0)
+    rows = {}
+    try:
+        for n in range(1, w.nsteps + 1):
+            st = gp.step(w.dt, w.bc(n))
+            assert st["status"] == 0, (n, st["status"])
+            if n % 100 == 0:
+                r = np.hypot(np.array(st["res_u"]), np.array(st["res_p"]))
+                rows[n] = (st["newton_iters"], r / r[0], st["krylov_iters"], st["mass_iters"])
+                print(f"  step {n}: newton={st['newton_iters']} |R^k|/|R^0|=" +
+                      " ".join(f"{v:.1e}" for v in r / r[0]) + f" krylov={st['krylov_iters']}"
+                      f" mass_cg={st['mass_iters']}", flush=True)
+    finally:
+        gp.close()
+    # Table 1: three Newton iterations (1.2e-3, 2.3e-6, 3.4e-9 at step 100; the exact Jacobian,
+    # damping and inertia terms included, converges faster here: about 1e-3, 1e-8, 1e-15) and
+    # 12-17 Krylov iterations with the paper's AMG-based block preconditioner (the geometric
+    # multigrid V(1,1) blocks here take 35-85)
+    for n, (newton, ratio, krylov, mass_it) in rows.items():
+        assert newton == 3, (n, newton)
+        assert ratio[1] < 1e-2 and ratio[2] < 1e-6 and ratio[-1] < 1e-8, (n, ratio)
+        assert max(krylov) <= 120, (n, krylov)
+        assert 0 < mass_it <= 400, (n, mass_it)
