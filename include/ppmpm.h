@@ -275,11 +275,13 @@ const char* ppmpm_last_error(void);
  * launching stream around every launch of the kernels below; ppmpm_timing_get returns the number
  * of launches and their summed duration in milliseconds since the last reset.
  *   0 SpMV of the Krylov solver   1 Jacobian block rows   2 quadrature records   3 residual
- *   4 multigrid residual on the finest level   5 P2G   6 G2P   7 sort permutation
- *   8 Galerkin coarse operators   9 3D cell matrices (the block rows of 3D problems are then
- *   summed from them by launch 1) */
+ *   4 finest-level sweeps of the displacement-block multigrid   5 P2G   6 G2P
+ *   7 sort permutation   8 Galerkin coarse operators   9 3D cell matrices (the block rows of 3D
+ *   problems are then summed from them by launch 1)   10 finest-level sweeps of the Schur-block
+ *   multigrid */
 enum { PPMPM_K_SPMV = 0, PPMPM_K_JACOBIAN, PPMPM_K_RECORDS, PPMPM_K_RESIDUAL, PPMPM_K_MG0_RESID,
-       PPMPM_K_P2G, PPMPM_K_G2P, PPMPM_K_PERMUTE, PPMPM_K_RAP, PPMPM_K_CELLMAT, PPMPM_K_COUNT };
+       PPMPM_K_P2G, PPMPM_K_G2P, PPMPM_K_PERMUTE, PPMPM_K_RAP, PPMPM_K_CELLMAT, PPMPM_K_MG0_S,
+       PPMPM_K_COUNT };
 ppmpm_status ppmpm_timing_enable(int on);
 ppmpm_status ppmpm_timing_reset(void);
 ppmpm_status ppmpm_timing_get(int kernel, int64_t* launches, double* total_ms);

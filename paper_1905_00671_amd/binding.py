@@ -321,7 +321,7 @@ def step_batched(problems: Sequence[Problem], dts: Sequence[float], bcs: Sequenc
     return [stats[i].as_dict() for i in range(n)]
 
 
-KERNELS = ["spmv", "jacobian", "records", "residual", "mg0_resid", "p2g", "g2p", "permute", "rap", "cellmat"]
+KERNELS = ["spmv", "jacobian", "records", "residual", "mg0_resid", "p2g", "g2p", "permute", "rap", "cellmat", "mg0_s"]
 
 
 def timing_enable(on: bool = True):

@@ -1271,7 +1271,7 @@ static void vcycle_down(const Group& g, const std::vector<const Dev*>& hc, int f
         hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR);
         hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, LX, LR);
     }
-    PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
+    PPM_TIMED((l == 0 ? (fam == 0 ? KT_MG0_RESID : KT_MG0_S) : -1), st,
               hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR));
     Batch Bc = make_batch(g.ddev, level_rows(hc, l + 1), TPB);
     hipLaunchKernelGGL((k_mg_restrict<DIM, R, BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l, LR, LB);
@@ -1290,7 +1290,7 @@ static void vcycle_up(const Group& g, const std::vector<const Dev*>& hc, int fam
         hipLaunchKernelGGL((k_mg_resid<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, LR);
         hipLaunchKernelGGL((k_mg_update<DIM, R, BB, T>), gl, tb, 0, st, Bl, fam, l, LX, LR);
     }
-    PPM_TIMED((l == 0 ? KT_MG0_RESID : -1), st,
+    PPM_TIMED((l == 0 ? (fam == 0 ? KT_MG0_RESID : KT_MG0_S) : -1), st,
               hipLaunchKernelGGL((k_mg_post<DIM, R, BB, T, FULL>), gl, tb, 0, st, Bl, fam, l, rhs, LX, out));
 }
 
@@ -1330,7 +1330,7 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
         for (auto* h : hc) level0 = level0 && h->ls_stop == 0;
         if (level0) {
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, 0));
-            PPM_TIMED(KT_MG0_RESID, st,
+            PPM_TIMED(KT_MG0_S, st,
                       hipLaunchKernelGGL((k_mg_up<DIM, R, BB, T, false, true>), dim3(Bt.pfx[Bt.n]), tb, 0, st, Bt, fam, 0,
                                          rhs0, out0));
             return;
@@ -1341,7 +1341,7 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
             const dim3 gt(Bt.pfx[Bt.n]);
             if (l == 0)
-                PPM_TIMED(KT_MG0_RESID, st,
+                PPM_TIMED(fam == 0 ? KT_MG0_RESID : KT_MG0_S, st,
                           hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, false>), gt, tb, 0, st, Bt, fam, 0, rhs0));
             else {
                 // restriction of the finer residual once per coarse node, then the sweep reads it
@@ -1364,7 +1364,7 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
             const dim3 gt(Bt.pfx[Bt.n]);
             if (l == 0)
-                PPM_TIMED(KT_MG0_RESID, st,
+                PPM_TIMED(fam == 0 ? KT_MG0_RESID : KT_MG0_S, st,
                           hipLaunchKernelGGL((k_mg_up<DIM, R, BB, T, false>), gt, tb, 0, st, Bt, fam, 0, rhs0, out0));
             else
                 hipLaunchKernelGGL((k_mg_up<DIM, R, BB, T, true>), gt, tb, 0, st, Bt, fam, l, LB, LR);

@@ -24,7 +24,7 @@ struct Group {
 
 // Per-kernel timing with HIP events recorded on the launching stream (off unless enabled).
 enum KernelId : int { KT_SPMV = 0, KT_JACOBIAN, KT_RECORDS, KT_RESIDUAL, KT_MG0_RESID, KT_P2G, KT_G2P, KT_PERMUTE,
-                      KT_RAP, KT_CELLMAT, KT_COUNT };
+                      KT_RAP, KT_CELLMAT, KT_MG0_S, KT_COUNT };
 bool timing_on();
 void timing_begin(hipStream_t st, int id, hipEvent_t* a, hipEvent_t* b);
 void timing_end(hipStream_t st, hipEvent_t b);
