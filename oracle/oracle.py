@@ -200,7 +200,12 @@ class OracleProblem:
                      _p(self.p), _p(self.v) if dyn else None, _p(self.a) if dyn else None,
                      _p(self.pd) if dyn else None, _p(self.pdd) if dyn else None,
                      _p(M), _p(Mp), _p(Mv), _p(Ma), _p(Mpd), _p(Mpdd))
-        act = M > 0
+        # a node whose mass is a negligible fraction of the largest (a point domain that only just
+        # reaches its support) is inactive: its rows would otherwise be ~1e-18 of the others and
+        # the Newton update there unbounded (reading: below NEGLIGIBLE_MASS of the step's largest
+        # nodal mass the node is treated as outside the material)
+        act = M > self.NEGLIGIBLE_MASS * M.max()
+        M = np.where(act, M, 0.0)
         safe = np.where(act, M, 1.0)
         out = dict(M=M, active=act, Pn=np.where(act, Mp / safe, 0.0))
         if dyn:
@@ -233,6 +238,8 @@ class OracleProblem:
         n = lib().or_mass_matrix(_a(self._g), self.opt.shape, self.np, _p(self.x), _p(self.lp), _p(self.m),
                                  _p(ri), _p(ci), _p(v))
         return sp.coo_matrix((v[:n], (ri[:n], ci[:n])), shape=(g.nnode, g.nnode)).tocsr()
+
+    NEGLIGIBLE_MASS = 1e-15
 
     # Nodes whose lumped mass is below this fraction of the step's largest nodal mass keep the
     # lumped value in the consistent mapping (reading: the consistent mass matrix is singular in
@@ -323,6 +330,17 @@ class OracleProblem:
             surf = free_surface_nodes(g, act)
             pfix = pfix | surf
             p_val = np.where(surf, 0.0, p_val)
+        if bc.get("point_p_fixed") is not None:
+            # pressure conditions carried by material points (Sec. 5.4, reading: every grid node
+            # in the basis of a flagged point holds the point's value)
+            pfix = pfix.copy()
+            p_val = p_val.copy()
+            val = bc.get("point_p_val")
+            for q in np.flatnonzero(np.asarray(bc["point_p_fixed"]).astype(bool)):
+                nodes, S, _, _ = basis(g, self.opt.shape, self.x[q], self.lp[q])
+                nodes = nodes[S > 0.0]
+                pfix[nodes] = True
+                p_val[nodes] = 0.0 if val is None else float(val[q])
         if self.opt.dynamic:
             # constrained components of the nodal kinematics start from rest
             for k in ("vn", "an"):

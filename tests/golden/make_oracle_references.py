@@ -1,7 +1,7 @@
 """Writes the oracle's reference states for the GPU parity tests of the benchmark configurations
 whose oracle runs take minutes to hours on one core (config 2: 100 dynamic steps; config 3:
 several seeds; config 4: a 24^3 replica over all 20 steps; the harmonic strip footing over its
-400 steps).
+400 steps; the two-body impact on a coarse grid through contact).
 
 TEST INFRASTRUCTURE: calls only the CPU oracle (oracle/) and the seeded input generators
 (paper_1905_00671_amd/workloads.py, no method arithmetic).  Nothing here runs the HIP library.
@@ -49,6 +49,9 @@ CASES = {
     "config4_r24": (_config4_replica, 20, (1, 10, 20), 64),
     # Sec. 5.2: harmonic strip footing, consistent mass, point tractions, all 400 steps
     "harmonic_footing": (lambda: W.harmonic_footing(), 400, (100, 200, 300, 400), 8),
+    # Sec. 5.4: two-body impact on a coarse grid (h = 0.05 m, 2 x 2 points per cell), through the
+    # contact at t ~ 1.5 s and the rebound
+    "impact_coarse": (lambda: W.two_body_impact(h=0.05, ppa=2), 2200, (1000, 1600, 2000, 2200), 1),
 }
 for _s in range(5):
     CASES[f"config3_seed{_s}_128x64"] = ((lambda s=_s: _config3(s)), 4, (1, 4), 32)

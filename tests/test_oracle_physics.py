@@ -182,8 +182,9 @@ def test_rigid_translation_dynamic():
 
 
 def test_mass_conservation_and_volume():
-    """Lumped P2G preserves the total mass (partition of unity, eq. map-from-particles-to-nodes);
-    the point volume follows V = det(dF) V_n, so sum V equals sum J V_0 after steps."""
+    """Lumped P2G preserves the total mass (partition of unity, eq. map-from-particles-to-nodes)
+    up to the nodes below 1e-15 of the largest nodal mass, which are outside the material; the
+    point volume follows V = det(dF) V_n, so sum V equals sum J V_0 after steps."""
     w = W.config(2, nx=8, ny=8, nsteps=3, dt=1e-2)
     pr = O.from_workload(w)
     m0 = pr.m.sum()
@@ -191,7 +192,9 @@ def test_mass_conservation_and_volume():
     for n in range(1, 4):
         pr.step(w.dt, w.bc(n))
         nodal = pr.p2g()
-        assert nodal["M"].sum() == pytest.approx(m0, rel=1e-13)
+        nn = nodal["M"].size
+        assert nodal["M"].sum() == pytest.approx(m0, rel=1e-13 + nn * 1e-15 * nodal["M"].max() / m0)
+        assert nodal["M"].sum() <= m0 * (1 + 1e-13)
     J = np.linalg.det(pr.F)
     assert np.abs(pr.V - J * V0).max() < 1e-13 * V0.max()
 
@@ -401,3 +404,27 @@ def test_self_weight_consolidation_end_state():
     assert np.abs(total[inner] + rho0 * g * (H - Z[inner])).max() < 0.03 * rho0 * g * H
     assert -pr.u[:, 1].min() > 0.2            # large strain: tens of centimetres on a 2 m column
     assert np.linalg.det(pr.F).min() < 0.75
+
+
+def test_two_body_impact_momentum_and_contact():
+    """Sec. 5.4 impact of two poroelastic discs (coarse grid, discs started closer so that they
+    meet early): the bodies share the grid's single velocity field (the method's own no-slip
+    contact), there are no external forces, and the internal forces of every node sum to zero
+    (partition of unity of the basis), so the total momentum stays zero through the contact to
+    the Newton tolerance; the collision takes kinetic energy into strain and pore pressure, and
+    the points that carry the drained condition keep p = 0 (all nodes of their basis hold it)."""
+    w = W.two_body_impact(h=0.05, ppa=2, v0=0.1, dt=1e-3, centre=0.3)
+    pr = O.from_workload(w)
+    n1 = w.meta["bodies"][0]
+    body = np.abs((pr.m[:n1, None] * pr.v[:n1]).sum(0)).max()
+    assert body > 10.0 and np.abs((pr.m[:, None] * pr.v).sum(0)).max() < 1e-12 * body
+    ke0 = 0.5 * (pr.m * (pr.v ** 2).sum(1)).sum()
+    for n in range(1, 601):
+        pr.step(w.dt, w.bc(n))
+        if n % 100 == 0:
+            assert np.abs((pr.m[:, None] * pr.v).sum(0)).max() < 1e-10 * body, n
+    ke = 0.5 * (pr.m * (pr.v ** 2).sum(1)).sum()
+    assert ke < 0.75 * ke0                      # the collision is under way
+    assert np.abs(pr.p).max() > 10.0            # and has raised pore pressure
+    assert np.abs(pr.p[w.meta["drained"]]).max() == 0.0
+    assert np.linalg.det(pr.F).min() < 0.9
