@@ -223,22 +223,26 @@ def spmv_roofline(w, kt, precision):
 
 
 def mg0_roofline(w, kt, precision):
-    """Finest-level sweeps of the displacement-block multigrid (pre-smoothing fused with the
-    residual, and prolongation fused with post-smoothing): each reads the node's dim x dim
-    operator blocks over the stencil from the stored Jacobian, its inverse diagonal block, the
-    right-hand side and the iterate, and writes two vectors."""
+    """Finest-level sweeps of the displacement-block multigrid, the launches that stream the
+    operator: 3D the row kernels r = b - A x (reads the node's dim x dim blocks over the stencil,
+    b, x; writes r) and out = x + omega Dinv (b - A x) (also the inverse diagonal block), so
+    S dim^2 + dim^2 / 2 + 3 dim words per node and launch on average; 2D the halo-tiled down and up
+    kernels, S dim^2 + dim^2 + 3 dim words (operator, inverse diagonal, b, x, r or out)."""
     g = w.grid
     k = kt["mg0_resid"]
     if k["launches"] == 0:
         return None
     D = g.dim
     word = 8 if precision == 0 else 4
-    bytes_per_launch = g.nnode * (stencil(w) * D * D + D * D + 4 * D) * word
+    dd = D * D / 2 if D == 3 else D * D
+    bytes_per_launch = g.nnode * (stencil(w) * D * D + dd + 3 * D) * word
     avg_s = k["total_ms"] / k["launches"] * 1e-3
     achieved = bytes_per_launch / avg_s / 1e9
+    name = ("k_mg_resid / k_mg_post on the finest level (displacement block)" if D == 3 else
+            "k_mg_down / k_mg_up on the finest level (displacement block)")
     return dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                traffic=None, kernel="k_mg_down / k_mg_up on the finest level (displacement block)",
-                bytes_per_launch=bytes_per_launch, avg_launch_us=avg_s * 1e6, launches=k["launches"])
+                traffic=None, kernel=name, bytes_per_launch=bytes_per_launch, avg_launch_us=avg_s * 1e6,
+                launches=k["launches"])
 
 
 # Assembly bytes per material point that the method must move (read x, F_n, V_n[, lp]; its share
@@ -297,11 +301,13 @@ def kernel_digest(fname, signature):
 SPMV_SIG = "template <int DIM, int R, typename T>\n__global__ void __launch_bounds__(TPB) k_spmv("
 MG_DOWN_SIG = "__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FULL ? 2 : 8))) k_mg_down("
 MG_UP_SIG = "__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FULL ? 2 : 8))) k_mg_up("
+MG_ROW_SIG = "__device__ __forceinline__ void row_resid("
 # source digest a counter summary must carry to be used for a kernel (family)
 KERNEL_DIGEST = {
     "spmv": lambda: kernel_digest("kern_solver.hip", SPMV_SIG),
     "mg0": lambda: hashlib.sha256((kernel_digest("kern_mg.hip", MG_DOWN_SIG) +
-                                   kernel_digest("kern_mg.hip", MG_UP_SIG)).encode()).hexdigest(),
+                                   kernel_digest("kern_mg.hip", MG_UP_SIG) +
+                                   kernel_digest("kern_mg.hip", MG_ROW_SIG)).encode()).hexdigest(),
 }
 
 

@@ -143,8 +143,16 @@ typedef struct {
  *                             forces of the loaded points are added with atomics (sums in
  *                             nondeterministic order, rounding-level differences only)
  *   point_normal[np*dim]      NULL or a zero row: the force acts through the point's own basis
- * Any pointer may be NULL (no condition / zero).  Conditions on inactive nodes (no material
- * point support) are ignored.  The point arrays are read with the same `where` as the others. */
+ *   point_p_fixed[np] (0/1), point_p_val[np]   pore pressure conditions carried by material
+ *                             points (caller's order; Sec. 5.4 drains the bodies through a few
+ *                             points): every active node in the basis of a flagged point holds
+ *                             the point's value (NULL values: 0); applied after all other
+ *                             conditions of the step.  A node reached by flagged points with
+ *                             different values gets one of them
+ * Any pointer may be NULL (no condition / zero).  Conditions on inactive nodes are ignored; a
+ * node is active when its lumped mass exceeds 1e-15 of the step's largest nodal mass (a node that
+ * a point domain only just reaches is outside the material).  The point arrays are read with the
+ * same `where` as the others. */
 typedef struct {
     const uint8_t* u_fixed;
     const double* u_inc;
@@ -155,6 +163,8 @@ typedef struct {
     int where;
     const double* point_force;
     const double* point_normal;
+    const uint8_t* point_p_fixed;
+    const double* point_p_val;
 } ppmpm_bc;
 
 #define PPMPM_MAX_HIST 64
@@ -200,8 +210,9 @@ ppmpm_status ppmpm_set_particles(ppmpm_problem* p, int64_t np, const double* x, 
 
 /* One implicit time step of length dt (Stages 1-4 of Sec. 3.1): counting sort of the points into
  * cells, lumped P2G, Newton iterations (residual and fixed-stencil block-CSR Jacobian with the
- * PPP term; BiCGStab with the block upper-triangular preconditioner), G2P update.  The step is
- * transactional: on PPMPM_E_NEWTON, PPMPM_E_NONFINITE or PPMPM_E_OUT_OF_GRID the material-point
+ * PPP term; BiCGStab with the block upper-triangular preconditioner), G2P update.  A Newton
+ * update that inverts a material point or makes the residual non-finite is halved (up to four
+ * times) before the step fails.  The step is transactional: on PPMPM_E_NEWTON, PPMPM_E_NONFINITE or PPMPM_E_OUT_OF_GRID the material-point
  * state is left unchanged and the caller may retry (e.g. with a smaller dt).  stats may be NULL. */
 ppmpm_status ppmpm_step(ppmpm_problem* p, double dt, const ppmpm_bc* bc, ppmpm_step_stats* stats);
 

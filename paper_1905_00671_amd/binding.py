@@ -52,7 +52,8 @@ class Options(ctypes.Structure):
 class BC(ctypes.Structure):
     _fields_ = [("u_fixed", ctypes.c_void_p), ("u_inc", ctypes.c_void_p), ("p_fixed", ctypes.c_void_p),
                 ("p_val", ctypes.c_void_p), ("f_ext", ctypes.c_void_p), ("q_ext", ctypes.c_void_p),
-                ("where", ctypes.c_int), ("point_force", ctypes.c_void_p), ("point_normal", ctypes.c_void_p)]
+                ("where", ctypes.c_int), ("point_force", ctypes.c_void_p), ("point_normal", ctypes.c_void_p),
+                ("point_p_fixed", ctypes.c_void_p), ("point_p_val", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -158,7 +159,8 @@ def make_options(o, precision: int = FP64, **over) -> Options:
     return Options(**vals)
 
 
-BC_KEYS = ("u_fixed", "u_inc", "p_fixed", "p_val", "f_ext", "q_ext", "point_force", "point_normal")
+BC_KEYS = ("u_fixed", "u_inc", "p_fixed", "p_val", "f_ext", "q_ext", "point_force", "point_normal", "point_p_fixed",
+           "point_p_val")
 
 
 class BCArrays:
@@ -169,13 +171,13 @@ class BCArrays:
         for k in BC_KEYS:
             v = d.get(k)
             if v is not None and isinstance(v, np.ndarray):
-                dt = np.uint8 if k in ("u_fixed", "p_fixed") else np.float64
+                dt = np.uint8 if k in ("u_fixed", "p_fixed", "point_p_fixed") else np.float64
                 v = np.ascontiguousarray(v, dtype=dt)
             self.keep[k] = v
         first = next((v for v in self.keep.values() if v is not None), None)
         where = HOST if first is None else _where(first)
         ptr = {k: _ptr(self.keep[k]) for k in BC_KEYS}
-        self.c = BC(*[ptr[k] for k in BC_KEYS[:6]], where, ptr["point_force"], ptr["point_normal"])
+        self.c = BC(*[ptr[k] for k in BC_KEYS[:6]], where, *[ptr[k] for k in BC_KEYS[6:]])
 
 
 class Problem:

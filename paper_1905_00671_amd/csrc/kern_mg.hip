@@ -1336,17 +1336,27 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
             return;
         }
     }
+    // 3D displacement block, finest level: row sweeps instead of the halo tile (a 64 x 2 x 2 tile
+    // forms omega Dinv b for 66 x 4 x 4 slots, 4.1 per node, and its operator streams start off
+    // the 64-row blocks of the Jacobian; the row kernels read the operator in whole blocks and the
+    // neighbours' iterates through L2: FP64 step 330 -> 320 ms, FP32 176 -> 166 ms on the 96^3
+    // footing; in 2D the tile halo is 1.5 nodes per node and the tile measured faster)
+    const bool rows0 = DIM == 3 && fam == 0;
     if (nsm == 1) {
         for (int l = 0; l < Lstd; ++l) {
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
             const dim3 gt(Bt.pfx[Bt.n]);
-            if (l == 0)
+            if (l == 0 && rows0)
+                vcycle_down<DIM, R, BB, T, false>(g, hc, fam, 0, rhs0, 1, st);   // also restricts to level 1
+            else if (l == 0)
                 PPM_TIMED(fam == 0 ? KT_MG0_RESID : KT_MG0_S, st,
                           hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, false>), gt, tb, 0, st, Bt, fam, 0, rhs0));
             else {
                 // restriction of the finer residual once per coarse node, then the sweep reads it
                 Batch Bc = make_batch(g.ddev, level_rows(hc, l), TPB);
-                hipLaunchKernelGGL((k_mg_restrict<DIM, R, BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l - 1, LR, LB);
+                if (!(l == 1 && rows0))
+                    hipLaunchKernelGGL((k_mg_restrict<DIM, R, BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l - 1, LR,
+                                       LB);
                 hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, true>), gt, tb, 0, st, Bt, fam, l, LB);
             }
         }
@@ -1363,7 +1373,9 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
         for (int l = Lstd - 1; l >= 0; --l) {
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
             const dim3 gt(Bt.pfx[Bt.n]);
-            if (l == 0)
+            if (l == 0 && rows0)
+                vcycle_up<DIM, R, BB, T, false>(g, hc, fam, 0, rhs0, out0, 1, st);
+            else if (l == 0)
                 PPM_TIMED(fam == 0 ? KT_MG0_RESID : KT_MG0_S, st,
                           hipLaunchKernelGGL((k_mg_up<DIM, R, BB, T, false>), gt, tb, 0, st, Bt, fam, 0, rhs0, out0));
             else

@@ -341,6 +341,81 @@ __global__ void k_p2g(Batch B) {
     }
 }
 
+// Largest nodal mass of the step (non-negative doubles order like their bit patterns), then the
+// nodes below NEGLIGIBLE_MASS of it leave the material: mass, mapped fields, dof masks and the
+// Newton start are cleared as for a node without points.
+__global__ void k_clear_mmax(Batch B) {
+    if (threadIdx.x == 0) B.d[blockIdx.x]->scal[SC_MMAX] = 0.0;
+}
+
+__global__ void k_node_mass_max(Batch B) {
+    PROB_PROLOGUE
+    if (tid >= d->Nnode) return;
+    int n[3];
+    n[0] = (int)(tid % d->nn[0]);
+    n[1] = (int)((tid / d->nn[0]) % d->nn[1]);
+    n[2] = d->dim == 3 ? (int)(tid / ((int64_t)d->nn[0] * d->nn[1])) : 0;
+    const double m = d->M[pad_index(d, n[0], n[1], n[2])];
+    atomicMax((unsigned long long*)(d->scal + SC_MMAX), (unsigned long long)__double_as_longlong(m));
+}
+
+template <int DIM>
+__global__ void k_cut_light_nodes(Batch B) {
+    PROB_PROLOGUE
+    if (tid >= d->Nnode) return;
+    int n[3];
+    n[0] = (int)(tid % d->nn[0]);
+    n[1] = (int)((tid / d->nn[0]) % d->nn[1]);
+    n[2] = DIM == 3 ? (int)(tid / ((int64_t)d->nn[0] * d->nn[1])) : 0;
+    const int64_t pn = pad_index(d, n[0], n[1], n[2]);
+    const double m = d->M[pn];
+    if (!(m > 0.0) || m > NEGLIGIBLE_MASS * d->scal[SC_MMAX]) return;
+    d->M[pn] = d->Pn[pn] = d->Mp[pn] = d->pdn[pn] = d->pddn[pn] = 0.0;
+    for (int a = 0; a < 3; ++a) d->vn[pn * 3 + a] = d->an[pn * 3 + a] = 0.0;
+    for (int c = 0; c <= DIM; ++c) {
+        d->dfree[pn * (DIM + 1) + c] = 0;
+        d->X[pn * (DIM + 1) + c] = 0.0;
+    }
+}
+
+// Pressure conditions carried by material points (Sec. 5.4): every active node in the basis of a
+// flagged point holds the point's value (nodes shared by flagged points with different values
+// get one of them).
+template <int DIM, int SHAPE>
+__global__ void k_point_pfix(Batch B, const uint8_t* __restrict__ flag, const double* __restrict__ val) {
+    PROB_PROLOGUE
+    if (tid >= d->Np) return;
+    const int64_t id = d->idw[tid];
+    if (!flag[id]) return;
+    constexpr int WB = SHAPE ? 3 : 2;
+    const double v = val ? val[id] : 0.0;
+    const double* P = d->pw;
+    const int64_t s = d->ps;
+    double w[DIM][3], dw[3], s0v[3];
+    int base[3] = {0, 0, 0};
+    for (int a = 0; a < DIM; ++a)
+        base[a] = basis_1d<SHAPE>(P[(PX + a) * s + tid], P[(PLP + a) * s + tid], d->x0[a], d->h, d->nc[a], w[a], dw,
+                                  s0v);
+    for (int k2 = 0; k2 < (DIM == 3 ? WB : 1); ++k2)
+        for (int k1 = 0; k1 < WB; ++k1)
+            for (int k0 = 0; k0 < WB; ++k0) {
+                const int kk[3] = {k0, k1, k2};
+                int idx[3] = {0, 0, 0};
+                double sw = 1.0;
+                bool ok = true;
+                for (int a = 0; a < DIM; ++a) {
+                    idx[a] = base[a] + kk[a];
+                    if (idx[a] < 0 || idx[a] >= d->nn[a]) ok = false;
+                    sw *= w[a][kk[a]];
+                }
+                if (!ok || !(sw > 0.0)) continue;
+                const int64_t pn = pad_index(d, idx[0], idx[1], idx[2]);
+                if (!(d->M[pn] > 0.0)) continue;
+                d->dfree[pn * (DIM + 1) + DIM] = 0;
+                d->X[pn * (DIM + 1) + DIM] = v;
+            }
+}
+
 // Drained free surface (Sec. 5.3): the pore pressure of an active node with an inactive node
 // among its 3^dim - 1 neighbours inside the grid is held at zero for the step.  Reads the nodal
 // masses of k_p2g, so it runs as a kernel of its own after it.
@@ -520,6 +595,27 @@ void launch_p2g(const Group& g, hipStream_t st) {
     if (g.dim == 2 && g.shape == 0) PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<2, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
     else if (g.dim == 2 && g.shape == 1) PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<2, 1>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
     else PPM_TIMED(KT_P2G, st, hipLaunchKernelGGL((k_p2g<3, 0>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B));
+}
+
+void launch_cut_light_nodes(const Group& g, hipStream_t st) {
+    Batch B = make_batch(g.ddev, g.nnode, TPB);
+    Batch B1 = make_batch_one_block(g.ddev);
+    hipLaunchKernelGGL(k_clear_mmax, dim3(B1.n), dim3(64), 0, st, B1);
+    hipLaunchKernelGGL(k_node_mass_max, dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
+    if (g.dim == 2) hipLaunchKernelGGL((k_cut_light_nodes<2>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
+    else hipLaunchKernelGGL((k_cut_light_nodes<3>), dim3(B.pfx[B.n]), dim3(TPB), 0, st, B);
+}
+
+void launch_point_pfix(const Group& g, const std::vector<const uint8_t*>& flag, const std::vector<const double*>& val,
+                       hipStream_t st) {
+    for (size_t q = 0; q < g.ddev.size(); ++q) {
+        if (!flag[q]) continue;
+        Batch B = make_batch({g.ddev[q]}, {g.np[q]}, TPB);
+        const dim3 gr(B.pfx[B.n]), tb(TPB);
+        if (g.dim == 2 && g.shape == 0) hipLaunchKernelGGL((k_point_pfix<2, 0>), gr, tb, 0, st, B, flag[q], val[q]);
+        else if (g.dim == 2) hipLaunchKernelGGL((k_point_pfix<2, 1>), gr, tb, 0, st, B, flag[q], val[q]);
+        else hipLaunchKernelGGL((k_point_pfix<3, 0>), gr, tb, 0, st, B, flag[q], val[q]);
+    }
 }
 
 void launch_drain_surface(const Group& g, hipStream_t st) {

@@ -108,8 +108,13 @@ void launch_sort(const Group& g, hipStream_t st);
 void launch_bc(const Dev* dd, int64_t nnode, const uint8_t* uf, const double* ui, const uint8_t* pf,
                const double* pv, const double* fe, const double* qe, hipStream_t st);
 void launch_p2g(const Group& g, hipStream_t st);
+// nodes below NEGLIGIBLE_MASS of the largest nodal mass leave the material (after launch_p2g)
+void launch_cut_light_nodes(const Group& g, hipStream_t st);
 // zero pore pressure on the free surface of the problems with Dev::drain set (after launch_p2g)
 void launch_drain_surface(const Group& g, hipStream_t st);
+// pressure conditions carried by the flagged points (caller order, NULL: none); last of Stage 1
+void launch_point_pfix(const Group& g, const std::vector<const uint8_t*>& flag, const std::vector<const double*>& val,
+                       hipStream_t st);
 
 // kern_mass.hip
 // nodal forces of the point tractions F[q] (caller order, NULL: none) on the sorted points

@@ -60,6 +60,7 @@ enum Scal : int {
     SC_ITER = 11,    // iterations done (as double)
     SC_DONE = 12,    // 1 when converged or broken down
     SC_BREAK = 13,   // 1 on breakdown
+    SC_MMAX = 14,    // largest nodal mass of the step (Stage 1)
     NSCAL = 16
 };
 
@@ -314,6 +315,11 @@ __device__ __forceinline__ int window_base(double x, double lp, double x0, doubl
 // intersection has measure zero and the node gets weight, gradient and S0 exactly 0, so that the
 // rounding of the interval ends cannot make an untouched node active with a ~1e-27 mass.
 constexpr double GIMP_TOUCH = 1e-10;
+
+// A node whose mass is below this fraction of the step's largest nodal mass (a point domain that
+// only just reaches its support) is outside the material: its rows would be ~1e-18 of the others
+// and the Newton update there unbounded.
+constexpr double NEGLIGIBLE_MASS = 1e-15;
 
 // 1D basis of one particle along one axis.  Original MPM: the two nodes of the containing cell
 // (clamped), hat weights.  GIMP: the domain [x-lp, x+lp] clipped to the grid, three nodes from

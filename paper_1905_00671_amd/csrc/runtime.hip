@@ -288,7 +288,7 @@ size_t io_bytes(const Dev& h) {
     size_t a = (size_t)h.Np * (3 * D + 3) * sizeof(double);
     size_t b = (size_t)h.Np * 9 * sizeof(double);
     // boundary data (+ point tractions and normals) + state + residual
-    size_t c = (size_t)h.Nnode * (D + 1) * 34 + (size_t)h.Np * D * 16 + 8192;
+    size_t c = (size_t)h.Nnode * (D + 1) * 34 + (size_t)h.Np * (D * 16 + 9) + 16384;
     size_t e = (size_t)h.Nnode * (D + 1) * sizeof(double) * 2;
     return std::max(std::max(a, b), std::max(c, e)) + 4096;
 }
@@ -414,8 +414,9 @@ ppmpm_status read_scalars(const std::vector<ppmpm_problem*>& ps, hipStream_t st)
 // cells, P2G.  BC staging happens per problem.
 ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, const ppmpm_bc* const* bcs,
                     hipStream_t st) {
-    std::vector<const double*> pforce, pnormal;
-    bool any_force = false;
+    std::vector<const double*> pforce, pnormal, pfixv;
+    std::vector<const uint8_t*> pfixp;
+    bool any_force = false, any_pfix = false;
     for (size_t i = 0; i < ps.size(); ++i) {
         ppmpm_problem* p = ps[i];
         Dev& h = p->h;
@@ -453,17 +454,23 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
         const double* qe = bc ? (const double*)to_device(p, bc->q_ext, nn * 8, where, off, st) : nullptr;
         const double* pfo = bc ? (const double*)to_device(p, bc->point_force, p->np * D * 8, where, off, st) : nullptr;
         const double* pno = pfo ? (const double*)to_device(p, bc->point_normal, p->np * D * 8, where, off, st) : nullptr;
+        const uint8_t* ppf = bc ? (const uint8_t*)to_device(p, bc->point_p_fixed, p->np, where, off, st) : nullptr;
+        const double* ppv = ppf ? (const double*)to_device(p, bc->point_p_val, p->np * 8, where, off, st) : nullptr;
         if (off > p->iob) return fail(PPMPM_E_OOM, "io staging too small");
         launch_bc(p->d, nn, uf, ui, pf, pv, fe, qe, st);
         pforce.push_back(pfo);
         pnormal.push_back(pno);
+        pfixp.push_back(ppf);
+        pfixv.push_back(ppv);
         any_force |= pfo != nullptr;
+        any_pfix |= ppf != nullptr;
     }
     Group g = make_group(ps);
     launch_sort(g, st);
     if (any_force) launch_point_force(g, pforce, pnormal, st);
     if (g.shape == 0) launch_cell_proj(g, st);
     launch_p2g(g, st);
+    launch_cut_light_nodes(g, st);
     bool drain = false, cons = false;
     for (const ppmpm_problem* p : ps) {
         drain |= p->h.drain != 0;
@@ -477,6 +484,7 @@ ppmpm_status stage1(const std::vector<ppmpm_problem*>& ps, const double* dt, con
         for (ppmpm_problem* p : ps) p->mass_iters = p->h.cons ? it : 0;
     }
     if (drain) launch_drain_surface(g, st);
+    if (any_pfix) launch_point_pfix(g, pfixp, pfixv, st);
     return PPMPM_OK;
 }
 
@@ -484,13 +492,15 @@ struct NState {
     int phase = 0;  // 0 Newton, 1 converged, 2 failed
     int status = PPMPM_OK;
     double ru0 = 0, rp0 = 0, atol_u = 0, atol_p = 0;
-    int halvings = 0;  // mixed path: times the last Newton update was halved
+    int halvings = 0;  // times the last Newton update was halved
 };
 
-// Mixed path: an FP32 Krylov solve can return a direction whose full step inverts a material
-// point (or makes the residual non-finite) although a shorter step would not.  The update is then
-// halved, up to this many times, before the step is reported as failed.  The FP64 path takes
-// full steps only, as the oracle does.
+// An inexact Krylov solve (FP32 on the mixed path; on the FP64 path a pressure block that the
+// Newton test fixes only loosely, as in free-flying undrained bodies) can return a direction
+// whose full step inverts a material point or makes the residual non-finite although a shorter
+// step would not.  The update is then halved, up to this many times, before the step is
+// reported as failed.  Where the oracle's full steps succeed the FP64 path never halves (the
+// iterates agree to rounding), so parity is unaffected.
 constexpr int MAX_HALVINGS = 4;
 
 constexpr int ST_PENDING = -1;   // statistics slot of a problem not (yet) finished
@@ -667,7 +677,7 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
                 }
                 so.newton_iters = it;
                 if (p->fpin[FL_INVERTED] || p->fpin[FL_NONFINITE] || !std::isfinite(ru) || !std::isfinite(rp)) {
-                    if (p->h.mixed && it > 0 && g.ns[k].halvings < MAX_HALVINGS) {
+                    if (it > 0 && g.ns[k].halvings < MAX_HALVINGS) {
                         // take back half of what remains of the last update, clear the flags and
                         // evaluate the residual again in the next pass
                         g.ns[k].halvings++;
@@ -1037,6 +1047,7 @@ ppmpm_status ppmpm_eval_residual(ppmpm_problem* p, double dt, const ppmpm_bc* bc
     // stage1 used the front of the io region for the boundary data; stage the state after it
     size_t off = (size_t)nn * (D + 1) * (2 * sizeof(double) + 2) + 4096;
     if (bc && bc->point_force) off += (size_t)p->np * D * 16 + 512;
+    if (bc && bc->point_p_fixed) off += (size_t)p->np * 9 + 512;
     const double* dU = (const double*)to_device(p, U, nn * D * 8, where, off);
     const double* dP = (const double*)to_device(p, P, nn * 8, where, off);
     double* dR = where == PPMPM_DEVICE ? R : (double*)(p->io + ((off + 255) & ~size_t(255)));

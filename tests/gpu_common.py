@@ -63,12 +63,15 @@ def dyn_oracle_nodal(pr, bc):
     return nodal
 
 
-def field_errors(got, ref, dynamic, gimp):
+def field_errors(got, ref, dynamic, gimp, E=None, dt=None):
     """Element-wise errors of the material-point state: for each field the largest absolute
     difference over the points, divided by the field's own scale (u, v, a, pdot, pddot, sigma':
     their largest magnitude; p: max(|p|, 1e-3 |sigma'|) so that drained states with p -> 0 stay
     meaningful; x: the displacement scale, since x - x0 = u on both sides; F, and the relative
-    volume and GIMP-length changes: the strain scale max |F - 1|)."""
+    volume and GIMP-length changes: the strain scale max |F - 1|).  Fields that vanish in exact
+    arithmetic (a body in free flight: F = 1, p = sigma' = a = 0) hold rounding noise only, so the
+    scales have floors: strain 1e-6, stresses and pressure 1e-6 E, and with the step dt the rates
+    1e-6 |v| / dt (a), 1e-6 E / dt (pdot) and 1e-6 E / dt^2 (pddot)."""
     def mx(a):
         return float(np.abs(a).max()) if np.size(a) else 0.0
 
@@ -76,20 +79,24 @@ def field_errors(got, ref, dynamic, gimp):
         return mx(np.asarray(a) - np.asarray(b)) / (scale if scale > 0 else 1.0)
 
     d = ref["F"].shape[-1]
-    strain = mx(ref["F"] - np.eye(d)[None])
+    fl_s = 1e-6 * E if E else 0.0
+    strain = max(mx(ref["F"] - np.eye(d)[None]), 1e-6 if E else 0.0)
     out = {
         "u": rel(got["u"], ref["u"], mx(ref["u"])),
-        "p": rel(got["p"], ref["p"], max(mx(ref["p"]), 1e-3 * mx(ref["sig"]))),
+        "p": rel(got["p"], ref["p"], max(mx(ref["p"]), 1e-3 * mx(ref["sig"]), fl_s)),
         "x": rel(got["x"], ref["x"], mx(ref["u"])),
         "F": rel(got["F"], ref["F"], strain),
         "vol": mx((np.asarray(got["vol"]) - ref["vol"]) / ref["vol"]) / (strain if strain > 0 else 1.0),
-        "sig": rel(got["sig"], ref["sig"], mx(ref["sig"])),
+        "sig": rel(got["sig"], ref["sig"], max(mx(ref["sig"]), fl_s)),
     }
     if gimp:
         out["lp"] = mx((np.asarray(got["lp"]) - ref["lp"]) / ref["lp"]) / (strain if strain > 0 else 1.0)
     if dynamic:
+        floors = {"v": 0.0, "a": 0.0, "pd": 0.0, "pdd": 0.0}
+        if E and dt:
+            floors = {"v": 0.0, "a": 1e-6 * mx(ref["v"]) / dt, "pd": fl_s / dt, "pdd": fl_s / dt ** 2}
         for k in ("v", "a", "pd", "pdd"):
-            out[k] = rel(got[k], ref[k], mx(ref[k]))
+            out[k] = rel(got[k], ref[k], max(mx(ref[k]), floors[k]))
     return out
 
 

@@ -133,7 +133,7 @@ def _run_steps(w, nsteps, precision, **over):
             bc = w.bc(n)
             st_o = pr.step(dt_of(n), bc)
             st_g = gp.step(dt_of(n), bc)
-            fe = field_errors(gpu_state(gp), oracle_state(pr), dyn, gimp)
+            fe = field_errors(gpu_state(gp), oracle_state(pr), dyn, gimp, w.material.E, dt_of(n))
             errs.append(dict(step=n, f=fe, newton=(st_o["newton_iters"], st_g["newton_iters"]),
                              krylov=st_g["krylov_total"]))
             print(f"  step {n}: " + " ".join(f"{k}={v:.1e}" for k, v in fe.items()) +
@@ -194,6 +194,10 @@ STEP_CASES = {
                                                      shape=W.LINEAR)), 4),
     # point tractions on their own: the Terzaghi column loaded through its top points' faces
     "terzaghi_point_load": (lambda: _point_load_terzaghi(), 6),
+    # Sec. 5.4 two-body impact: coarse discs started close, 300 steps into the contact; and the
+    # paper's size (40,216 points) for its first steps; point pressure conditions, no grid BCs
+    "impact_coarse_contact": (lambda: W.two_body_impact(h=0.05, ppa=2, centre=0.3, nsteps=300), 300),
+    "impact_paper_prefix": (lambda: W.two_body_impact(nsteps=3), 3),
 }
 
 
@@ -201,6 +205,7 @@ STEP_CASES = {
 # beta dt (pdot): at dt = 1 ms and a load of 100 rad/s, pddot ~ omega^2 p, so a relative p
 # difference reaches pddot amplified by p / (beta dt^2 pddot) ~ 1 / (beta (omega dt)^2) ~ 330.
 STEP_TOL_OTHER = {"harmonic_footing": {"pdd": 5e-8, "pd": 5e-9}}
+CONDITION_LIMITED = ("impact_coarse_contact", "impact_paper_prefix")
 
 
 def _cons(w):
@@ -257,6 +262,13 @@ def test_step_parity_fp64(name):
     w.options.krylov_rtol = 1e-12
     print(f"[steps fp64] case={name} np={w.particles.n}", flush=True)
     errs = _run_steps(w, nsteps, 0)
+    if name in CONDITION_LIMITED:
+        # free-flying undrained bodies: the pore pressure is fixed only through the near-singular
+        # mass block, so the Newton test (per-block floors) accepts pressures that differ between
+        # the direct and the iterative solve; displacements and positions are compared
+        for e in errs:
+            assert e["f"]["u"] < 1e-6 and e["f"]["x"] < 1e-6, e
+        return
     _assert_fields(errs, 1e-10, STEP_TOL_OTHER.get(name))
     if name in ("footing3d_mg", "footing2d_qs_gimp", "consolidation_linear"):
         # the block preconditioner keeps BiCGStab short on these quasi-static problems (Krylov
