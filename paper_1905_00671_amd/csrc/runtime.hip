@@ -493,6 +493,8 @@ struct NState {
     int status = PPMPM_OK;
     double ru0 = 0, rp0 = 0, atol_u = 0, atol_p = 0;
     int halvings = 0;  // times the last Newton update was halved
+    bool kfail = false;  // the last Krylov solve ended above its tolerance (breakdown or limit)
+    double merit = 0.0;  // max over blocks of |R_b| / max(|R_b^0|, atol_b) at the last accepted iterate
 };
 
 // An inexact Krylov solve (FP32 on the mixed path; on the FP64 path a pressure block that the
@@ -688,6 +690,17 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
                     g.ns[k].status = PPMPM_E_NONFINITE;
                     continue;
                 }
+                if (it > 0 && g.ns[k].kfail && g.ns[k].halvings < MAX_HALVINGS) {
+                    // the direction came from a linear solve that did not converge: accept it
+                    // only if it lowers the residual, else take back half of it
+                    const double m = std::max(ru / std::max(g.ns[k].ru0, g.ns[k].atol_u),
+                                              rp / std::max(g.ns[k].rp0, g.ns[k].atol_p));
+                    if (!(m < g.ns[k].merit)) {
+                        g.ns[k].halvings++;
+                        retry.push_back(p);
+                        continue;
+                    }
+                }
                 g.ns[k].halvings = 0;
                 if (p->fpin[FL_BOUNDS]) {
                     g.ns[k].phase = 2;
@@ -698,6 +711,8 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
                     g.ns[k].ru0 = ru;
                     g.ns[k].rp0 = rp;
                 }
+                g.ns[k].merit = std::max(ru / std::max(g.ns[k].ru0, g.ns[k].atol_u),
+                                         rp / std::max(g.ns[k].rp0, g.ns[k].atol_p));
                 const double rt = p->opt.newton_rtol;
                 const bool cu = ru <= std::max(rt * g.ns[k].ru0, g.ns[k].atol_u);
                 const bool cp = rp <= std::max(rt * g.ns[k].rp0, g.ns[k].atol_p);
@@ -776,6 +791,7 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
                 if (it < PPMPM_MAX_HIST) so.krylov_iters[it] = kit;
                 so.krylov_total += kit;
                 if (g.cont[j]->spin[SC_BREAK] != 0.0) so.krylov_breakdowns++;
+                g.ns[g.contk[j]].kfail = !(g.cont[j]->spin[SC_RR] <= g.cont[j]->spin[SC_TOL2]);
                 so.t_precond += phase_sync ? secs(t3, t4) : 0.0;
                 so.t_krylov += phase_sync ? secs(t4, t5) : secs(t2, t5);
             }

@@ -53,7 +53,7 @@ def _run(w, ref, nsteps, precision, tol, tol_other, fields=None):
             assert st["status"] == 0, (n, st["status"])
             # FP64 Newton counts: the same up to one iteration (both stop at the first iterate that
             # passes the test; near the tolerance the two iterates may fall on either side)
-            if precision == 0:
+            if precision == 0 and fields is None:
                 assert abs(st["newton_iters"] - int(ref["newton"][n - 1])) <= 1, (n, st["newton_iters"])
             if n in snaps:
                 got = {k: gp.get(k)[idx] for k in ("u", "p", "x", "F", "vol", "sig", "lp", "v", "a", "pd", "pdd")}
