@@ -1339,8 +1339,10 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
     // 3D displacement block, finest level: row sweeps instead of the halo tile (a 64 x 2 x 2 tile
     // forms omega Dinv b for 66 x 4 x 4 slots, 4.1 per node, and its operator streams start off
     // the 64-row blocks of the Jacobian; the row kernels read the operator in whole blocks and the
-    // neighbours' iterates through L2: FP64 step 330 -> 320 ms, FP32 176 -> 166 ms on the 96^3
-    // footing; in 2D the tile halo is 1.5 nodes per node and the tile measured faster)
+    // neighbours' iterates through L2: HBM bytes 1.35x -> 1.05x the algorithmic ones, FP64 step
+    // 330 -> 320 ms, FP32 176 -> 166 ms on the 96^3 footing).  In 2D the tile halo is 1.5 nodes
+    // per node and the two extra launches of the row form cost more than they save (512 x 256
+    // footing: 31.6 -> 32.3 ms per FP64 step).
     const bool rows0 = DIM == 3 && fam == 0;
     if (nsm == 1) {
         for (int l = 0; l < Lstd; ++l) {
