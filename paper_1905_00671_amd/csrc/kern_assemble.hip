@@ -409,6 +409,115 @@ __global__ void __launch_bounds__(TPB) k_residual(Batch B) {
     }
 }
 
+// 3D residual in two passes: the points of a cell (its sort bucket) reach exactly the cell's 8
+// corner nodes, so k_rescell3 sums each cell's contributions per corner, one wavefront per cell
+// with a lane per (corner, point slot of 8) and a fixed butterfly over the slots, and
+// k_resgather3 adds the 8 cell sums of every node.  Each record is read once instead of once per
+// node it reaches (the node gather re-read 11 GB per launch on the 96^3 footing, half of it from
+// HBM).  The cell sums [Ncell][8][4] (FP64) use the cell-matrix buffer, which the Jacobian only
+// fills after the residual.
+__global__ void __launch_bounds__(TPB) k_rescell3(Batch B) {
+    const int q = batch_find(B, blockIdx.x);
+    const Dev* __restrict__ d = B.d[q];
+    const int64_t lb = blockIdx.x - B.pfx[q];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t c = lb * (TPB / 64) + wave;
+    if (c >= d->Ncell) return;   // uniform over the wavefront
+    using L = RecLayout<3, 2>;
+    const int k = lane & 7, j = lane >> 3;   // corner (x + 2 y + 4 z), point slot
+    const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
+    const int p0 = d->cstart[c], p1 = d->cstart[c + 1];
+    const double pic = p1 > p0 ? d->cellpi[c * 8 + k] : 0.0;
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int base = p0; base < p1; base += 8) {
+        const int p = base + j;
+        if (p >= p1) continue;
+        const RecRef rc(d->rec, p, L::N);
+        const double w[3] = {rc[L::W_ + kx], rc[L::W_ + 2 + ky], rc[L::W_ + 4 + kz]};
+        const double dw[3] = {rc[L::DW_ + kx], rc[L::DW_ + 2 + ky], rc[L::DW_ + 4 + kz]};
+        const double Sv = w[0] * w[1] * w[2];
+        const double G[3] = {dw[0] * w[1] * w[2], w[0] * dw[1] * w[2], w[0] * w[1] * dw[2]};
+        double gS[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double t = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) t += rc[L::FI_ + cc * 3 + a] * G[cc];
+            gS[a] = t;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double t = rc[L::BF_ + a] * Sv;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) t += rc[L::SG_ + a * 3 + cc] * gS[cc];
+            r[a] += t;
+        }
+        double gw = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gw += gS[a] * rc[L::QW_ + a];
+        r[3] += Sv * rc[L::DT_] + rc[L::DK_] * gw + rc[L::ST_] * (Sv - pic);
+    }
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) r[a] += __shfl_xor(r[a], off, 64);
+    if (j == 0) {
+        double* cr = (double*)d->Ke + (c * 8 + k) * 4;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) cr[a] = r[a];
+    }
+}
+
+__global__ void __launch_bounds__(TPB) k_resgather3(Batch B) {
+    PROB_PROLOGUE
+    double ru2 = 0.0, rp2 = 0.0;
+    bool bad = false;
+    if (tid < d->Nnode) {
+        int n[3];
+        n[0] = (int)(tid % d->nn[0]);
+        n[1] = (int)((tid / d->nn[0]) % d->nn[1]);
+        n[2] = (int)(tid / ((int64_t)d->nn[0] * d->nn[1]));
+        const double* cr = (const double*)d->Ke;
+        double r[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int kz = 0; kz < 2; ++kz)
+            for (int ky = 0; ky < 2; ++ky)
+                for (int kx = 0; kx < 2; ++kx) {
+                    const int c0 = n[0] - kx, c1 = n[1] - ky, c2 = n[2] - kz;
+                    if (c0 < 0 || c0 >= d->nc[0] || c1 < 0 || c1 >= d->nc[1] || c2 < 0 || c2 >= d->nc[2]) continue;
+                    const int64_t c = c0 + (int64_t)d->nc[0] * (c1 + (int64_t)d->nc[1] * c2);
+                    const double* v = cr + (c * 8 + kx + 2 * ky + 4 * kz) * 4;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) r[a] += v[a];
+                }
+        const int64_t pn = pad_index(d, n[0], n[1], n[2]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double v = r[a] + d->fext[pn * 4 + a];
+            if (!d->dfree[pn * 4 + a]) v = 0.0;
+            if (!isfinite(v)) bad = true;
+            d->Rv[pn * 4 + a] = v;
+            if (a < 3) ru2 += v * v;
+            else rp2 += v * v;
+        }
+    }
+    if (bad) atomicOr(&d->flags[FL_NONFINITE], 1);
+    __shared__ double sh[2][TPB];
+    sh[0][threadIdx.x] = ru2;
+    sh[1][threadIdx.x] = rp2;
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + off];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d->partial[lb * 4 + 0] = sh[0][0];
+        d->partial[lb * 4 + 1] = sh[1][0];
+    }
+}
+
 // Contribution of one point to the (ca, cc) entries of row node i, for every column node k of
 // the point's window; LI is node i's window-local index (compile-time, so that the stencil slot
 // of each k is a constant and the accumulators stay in registers).  With gi = dF^{-T} grad_n S_i,
@@ -878,7 +987,15 @@ void launch_assemble(const Group& g, bool want_J, hipStream_t st) {
         PPM_TIMED(KT_RESIDUAL, st, hipLaunchKernelGGL((k_residual<2, 1>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn));
     } else {
         PPM_TIMED(KT_RECORDS, st, hipLaunchKernelGGL((k_records<3, 0>), dim3(Bp.pfx[Bp.n]), dim3(TPB), 0, st, Bp));
-        PPM_TIMED(KT_RESIDUAL, st, hipLaunchKernelGGL((k_residual<3, 0>), dim3(Bn.pfx[Bn.n]), dim3(TPB), 0, st, Bn));
+        std::vector<int64_t> cw;
+        for (size_t q = 0; q < g.ddev.size(); ++q) cw.push_back((g.ncell[q] + TPB / 64 - 1) / (TPB / 64));
+        Batch Bc = make_batch_blocks(g.ddev, cw);
+        Batch Bg = make_batch(g.ddev, g.nnode, TPB);
+        PPM_TIMED(KT_RESIDUAL, st, hipLaunchKernelGGL(k_rescell3, dim3(Bc.pfx[Bc.n]), dim3(TPB), 0, st, Bc);
+                  hipLaunchKernelGGL(k_resgather3, dim3(Bg.pfx[Bg.n]), dim3(TPB), 0, st, Bg));
+        hipLaunchKernelGGL(k_finalize_norms, dim3(Bg.n), dim3(TPB), 0, st, Bg);
+        if (want_J) launch_jacobian(g, st);
+        return;
     }
     hipLaunchKernelGGL(k_finalize_norms, dim3(Bn.n), dim3(TPB), 0, st, Bn);
     if (want_J) launch_jacobian(g, st);
