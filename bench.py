@@ -158,9 +158,8 @@ def run_path(w, precision, warmup, steps, bcs, tag="", **over):
             torch.cuda.synchronize()
             log(f"{tag} precision={precision} warm-up step {n}: {(time.perf_counter() - ts) * 1e3:.1f} ms "
                 f"newton={st['newton_iters']} krylov={st['krylov_iters']}")
+        # the timed region, as a caller runs it (the Krylov chunks replayed from captured graphs)
         torch.cuda.synchronize()
-        B.timing_reset()
-        B.timing_enable(True)
         lat, stats = [], []
         t0 = time.perf_counter()
         for n in range(warmup + 1, warmup + steps + 1):
@@ -172,8 +171,19 @@ def run_path(w, precision, warmup, steps, bcs, tag="", **over):
                 f"krylov={st['krylov_iters']}")
         torch.cuda.synchronize()
         T = time.perf_counter() - t0
+        # kernel-timing pass: the next `steps` steps with HIP events around every launch (direct
+        # launches; the events would not fit in a captured graph) for the per-kernel averages
+        B.timing_reset()
+        B.timing_enable(True)
+        kstats = []
+        tk = time.perf_counter()
+        for n in range(warmup + steps + 1, warmup + 2 * steps + 1):
+            kstats.append(p.step(w.dt, bcs[n]))
+        torch.cuda.synchronize()
+        Tk = time.perf_counter() - tk
         B.timing_enable(False)
         kt = B.timing_get()
+        log(f"{tag} precision={precision} kernel-timing pass: {Tk / steps * 1e3:.1f} ms per step")
         ws_bytes = p.workspace_bytes
     finally:
         p.close()
@@ -193,10 +203,12 @@ def run_path(w, precision, warmup, steps, bcs, tag="", **over):
         krylov_per_newton=[s["krylov_iters"] for s in stats],
         final_rel_residual=[max(s["res_u"][-1] / max(s["res_u"][0], 1e-300), s["res_p"][-1] / max(s["res_p"][0], 1e-300))
                             for s in stats],
-        phase_s=dict(assemble=sum(s["t_assemble"] for s in stats), precond=sum(s["t_precond"] for s in stats),
-                     krylov=sum(s["t_krylov"] for s in stats), sort=sum(s["t_sort"] for s in stats),
-                     g2p=sum(s["t_g2p"] for s in stats)),
+        phase_s=dict(assemble=sum(s["t_assemble"] for s in kstats), precond=sum(s["t_precond"] for s in kstats),
+                     krylov=sum(s["t_krylov"] for s in kstats), sort=sum(s["t_sort"] for s in kstats),
+                     g2p=sum(s["t_g2p"] for s in kstats)),
         kernels=kt,
+        kernel_timing_pass=dict(steps=steps, ms_per_step=Tk / steps * 1e3,
+                                newton_per_step=[s["newton_iters"] for s in kstats]),
         hbm_footprint_bytes=ws_bytes,
     )
 
@@ -339,7 +351,7 @@ def bench_workload(name, warmup, steps, control=True):
     """FP64 and mixed paths (and the FP64 control at the mixed Krylov tolerance) on one workload."""
     w = workload(name)
     t = time.perf_counter()
-    bcs = device_bcs(w, range(1, warmup + steps + 1))
+    bcs = device_bcs(w, range(1, warmup + 2 * steps + 1))
     log(f"{name}: {w.particles.n} points, {w.grid.nnode} nodes, inputs on the device in {time.perf_counter() - t:.1f} s")
     res = {"fp64": run_path(w, 0, warmup, steps, bcs, name), "mixed": run_path(w, 1, warmup, steps, bcs, name)}
     if control:
@@ -349,7 +361,7 @@ def bench_workload(name, warmup, steps, control=True):
         prec = 1 if key == "mixed" else 0
         out[key] = {k: r[k] for k in ("particle_updates_per_s", "particle_steps_per_s", "ms_per_step", "latency_ms",
                                       "newton_iters", "krylov_iters", "newton_per_step", "krylov_per_newton",
-                                      "final_rel_residual", "phase_s", "hbm_footprint_bytes")}
+                                      "final_rel_residual", "phase_s", "hbm_footprint_bytes", "kernel_timing_pass")}
         out[key]["kernels_ms"] = {k: v for k, v in r["kernels"].items() if v["launches"]}
         spmv = spmv_roofline(w, r["kernels"], prec)
         if spmv is not None:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -103,6 +104,7 @@ struct ppmpm_problem {
     bool have_jacobian = false;
     int nrec = 0;
     int mass_iters = 0;      // CG iterations of the last consistent-mass mapping
+    uint64_t gen = 0;        // creation number (keys the captured Krylov graphs)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -541,6 +543,120 @@ struct GroupRun {
     int kiters = 0;
 };
 
+// ---------------------------------------------------------------------------------------------
+// Krylov iterations replayed from captured HIP graphs
+// ---------------------------------------------------------------------------------------------
+// A chunk of krylov_check BiCGStab iterations is about 40 dependent kernel launches per
+// iteration, most of them short on small grids.  The chunk is captured once per (problems, their
+// multigrid shapes, iteration count, tolerance, limit) and then replayed: the kernels read every
+// scalar from the device and skip their work once a problem has converged, and the chunk holds
+// no memory set, copy, event or wait, so a replay is the work of the launches.  Capture runs on a
+// private stream (the caller's may be the legacy default stream, which cannot be captured) and
+// the graph is launched on the group's stream.  Not used while kernel timing is on (it records
+// events around launches); any capture error falls back to direct launches.
+struct KGraph {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+};
+std::mutex g_kg_mu;
+std::vector<KGraph> g_kg;
+uint64_t g_kg_clock = 0;
+constexpr size_t KG_MAX = 32;
+
+hipStream_t capture_stream() {
+    static std::mutex mu;
+    static std::vector<std::pair<int, hipStream_t>> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& e : streams)
+        if (e.first == dev) return e.second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams.push_back({dev, s});
+    return s;
+}
+
+// drops the graphs that replay work of problem p (before it is destroyed)
+void forget_graphs(const ppmpm_problem* p) {
+    std::lock_guard<std::mutex> lk(g_kg_mu);
+    for (size_t i = 0; i < g_kg.size();) {
+        bool hit = false;
+        for (size_t j = 0; j + 1 < g_kg[i].key.size(); j += 6)
+            if (g_kg[i].key[j] == p->gen) hit = true;
+        if (hit) {
+            (void)hipGraphExecDestroy(g_kg[i].exec);
+            g_kg.erase(g_kg.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+void krylov_chunk(const std::vector<ppmpm_problem*>& cont, int iters, double rtol, int maxit, hipStream_t st) {
+    Group gr = make_group(cont);
+    const std::vector<const Dev*> hc = host_copies(cont);
+    if (ppm::g_timing) {
+        launch_krylov_iters(gr, hc, iters, rtol, maxit, st);
+        return;
+    }
+    std::vector<uint64_t> key;
+    for (const ppmpm_problem* p : cont) {
+        key.push_back(p->gen);
+        key.push_back((uint64_t)p->h.nlev);
+        key.push_back((uint64_t)p->h.ltail);
+        key.push_back((uint64_t)p->h.ls_stop);
+        key.push_back((uint64_t)p->h.mg_nsm);
+        key.push_back((uint64_t)(uintptr_t)p->d);
+    }
+    uint64_t rb;
+    std::memcpy(&rb, &rtol, sizeof(rb));
+    key.push_back((uint64_t)iters);
+    key.push_back(rb);
+    key.push_back((uint64_t)maxit);
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_kg_mu);
+        for (auto& e : g_kg)
+            if (e.key == key) {
+                e.used = ++g_kg_clock;
+                exec = e.exec;
+                break;
+            }
+    }
+    if (!exec) {
+        hipStream_t cs = capture_stream();
+        hipGraph_t graph = nullptr;
+        bool ok = cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            launch_krylov_iters(gr, hc, iters, rtol, maxit, cs);
+            ok = hipStreamEndCapture(cs, &graph) == hipSuccess && graph;
+        }
+        if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!ok) {
+            (void)hipGetLastError();
+            exec = nullptr;
+            launch_krylov_iters(gr, hc, iters, rtol, maxit, st);
+            return;
+        }
+        std::lock_guard<std::mutex> lk(g_kg_mu);
+        if (g_kg.size() >= KG_MAX) {
+            size_t lru = 0;
+            for (size_t i = 1; i < g_kg.size(); ++i)
+                if (g_kg[i].used < g_kg[lru].used) lru = i;
+            (void)hipGraphExecDestroy(g_kg[lru].exec);
+            g_kg.erase(g_kg.begin() + lru);
+        }
+        g_kg.push_back(KGraph{key, exec, ++g_kg_clock});
+    }
+    if (hipGraphLaunch(exec, st) != hipSuccess) {
+        (void)hipGetLastError();
+        launch_krylov_iters(gr, hc, iters, rtol, maxit, st);
+    }
+}
+
 // The batched step.  Problems are grouped by kernel variant (dimension, basis, precision) and
 // Krylov options, at most MAXB per group; all groups advance through the stages in lockstep,
 // each on its own stream, with one host wait per stage for all of them.  S[i].status is set for
@@ -760,7 +876,7 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
             bool pending = false;
             for (auto& g : G) {
                 if (g.kdone) continue;
-                launch_krylov_iters(make_group(g.cont), host_copies(g.cont), g.kcheck, g.krtol, g.kmax, g.st);
+                krylov_chunk(g.cont, g.kcheck, g.krtol, g.kmax, g.st);
                 HIPCHK(hipGetLastError());
                 ppmpm_status s = fetch_scalars(g.cont, g.st);
                 if (s) return s;
@@ -942,6 +1058,8 @@ ppmpm_status ppmpm_create(const ppmpm_grid* grid, const ppmpm_material* mat, con
 static ppmpm_status init_problem(ppmpm_problem* p, const ppmpm_grid* grid, const ppmpm_material* mat,
                                  const ppmpm_options* opt, void* workspace, size_t ws_bytes, void* hip_stream,
                                  int64_t np) {
+    static std::atomic<uint64_t> generation{0};
+    p->gen = ++generation;
     p->grid = *grid;
     p->mat = *mat;
     p->opt = *opt;
@@ -1147,6 +1265,7 @@ ppmpm_status ppmpm_get_nodal(const ppmpm_problem* pc, int field, double* out, in
 ppmpm_status ppmpm_destroy(ppmpm_problem* p) {
     if (!p) return PPMPM_OK;
     if (p->st) (void)hipStreamSynchronize(p->st);
+    forget_graphs(p);
     if (p->hpin) (void)hipHostFree(p->hpin);
     if (p->spin) (void)hipHostFree(p->spin);
     if (p->fpin) (void)hipHostFree(p->fpin);

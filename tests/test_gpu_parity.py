@@ -499,3 +499,33 @@ def test_batched_per_problem_krylov_options():
     finally:
         for p in ps:
             p.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_krylov_graph_replay_equals_direct_launches(precision):
+    """The Krylov iterations are replayed from captured HIP graphs unless kernel timing is on (the
+    timing records events around launches).  Stepping the same problems both ways gives the same
+    bits: a 2D GIMP footing (every chunk replayed many times per step, with the assembly and the
+    Newton update launched directly in between) and a 3D footing with multigrid levels."""
+    B = _binding()
+    cases = (lambda: W.config(3, nx=32, ny=16, width=2.0, empty_rows=2, nsteps=3),
+             lambda: W.footing3d(n=12, size=1.5, half_b=0.25, nsteps=2))
+    for make in cases:
+        outs, krylov = [], []
+        for timing in (False, True):
+            w = make()
+            B.timing_enable(timing)
+            try:
+                gp = B.Problem.from_workload(w, precision=precision)
+                ks = []
+                for n in range(1, w.nsteps + 1):
+                    ks.append(gp.step(w.dt, w.bc(n))["krylov_total"])
+                outs.append({k: gp.get(k) for k in ("u", "p", "F", "sig")})
+                krylov.append(ks)
+                gp.close()
+            finally:
+                B.timing_enable(False)
+        print(f"[graph vs direct] np={w.particles.n} krylov {krylov}", flush=True)
+        assert krylov[0] == krylov[1]
+        for k in outs[0]:
+            assert np.array_equal(outs[0][k], outs[1][k]), k
