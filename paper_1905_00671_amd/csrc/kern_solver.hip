@@ -103,7 +103,7 @@ __device__ __forceinline__ int64_t node_pad(const Dev* d, int64_t tid) {
 // before writing, through restrict-qualified pointers, so the loads of all b components are in
 // flight together.
 
-// x = 0, r = rhat = -R, p = v = 0; partial (r, r)
+// x = x_best = 0, r = rhat = -R, p = v = 0; partial (r, r)
 template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_init(Batch B) {
     PROB_PROLOGUE
@@ -116,12 +116,14 @@ __global__ void __launch_bounds__(TPB) k_bicg_init(Batch B) {
         T* __restrict__ h = vp<T>(d->kh);
         T* __restrict__ pp = vp<T>(d->kp);
         T* __restrict__ vv = vp<T>(d->kv);
+        T* __restrict__ xb = vp<T>(d->kxb);
         T rv[BS];
 #pragma unroll
         for (int a = 0; a < BS; ++a) rv[a] = (T)(-Rv[k0 + a]);
 #pragma unroll
         for (int a = 0; a < BS; ++a) {
             x[k0 + a] = 0;
+            xb[k0 + a] = 0;
             r[k0 + a] = rv[a];
             h[k0 + a] = rv[a];
             pp[k0 + a] = 0;
@@ -277,6 +279,9 @@ __global__ void k_bicg_scalars(Batch B, int stage, double rtol, int maxit) {
         sc[SC_BETA] = 0.0;
         sc[SC_ITER] = 0.0;
         sc[SC_BREAK] = 0.0;
+        sc[SC_BEST] = s0;
+        sc[SC_SREF] = s0;
+        sc[SC_SITER] = 0.0;
         sc[SC_DONE] = (s0 == 0.0 || maxit <= 0) ? 1.0 : 0.0;
     } else {
         double rho_new = s0;
@@ -292,6 +297,67 @@ __global__ void k_bicg_scalars(Batch B, int stage, double rtol, int maxit) {
         sc[SC_BETA] = (rho_new / sc[SC_RHO]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
         sc[SC_RHO] = rho_new;
     }
+}
+
+// Best iterate and stagnation.  BiCGStab's residual is not monotone, and in FP32 it can stall
+// above the tolerance or grow without bound once rounding has taken over the recurrences (the
+// near-incompressible blocks of the mixed path).  At the end of every chunk of iterations the
+// iterate is copied to x_best when its residual is the smallest seen so far at a chunk end
+// (k_bicg_keep, then k_bicg_keep_scal records it); a solve that ends above its tolerance hands
+// the better of x and x_best to the Newton update (k_bicg_pick).  The mixed path also stops a
+// solve whose residual norm has not halved in STALL_ITERS iterations: the Newton update then
+// takes x_best under the residual-decrease test of the outer loop, and the next Newton iteration
+// refines it.
+constexpr int STALL_ITERS = 256;
+
+__device__ __forceinline__ bool keep_best(const Dev* d) {
+    const double rr = d->scal[SC_RR];
+    return isfinite(rr) && rr < d->scal[SC_BEST];
+}
+
+template <int BS, typename T>
+__global__ void __launch_bounds__(TPB) k_bicg_keep(Batch B) {
+    PROB_PROLOGUE
+    if (krylov_done(d) || !keep_best(d) || tid >= d->Nnode) return;
+    const int64_t k0 = node_pad<T>(d, tid) * BS;
+    const T* __restrict__ x = vp<T>(d->kx);
+    T* __restrict__ xb = vp<T>(d->kxb);
+    T xv[BS];
+#pragma unroll
+    for (int a = 0; a < BS; ++a) xv[a] = x[k0 + a];
+#pragma unroll
+    for (int a = 0; a < BS; ++a) xb[k0 + a] = xv[a];
+}
+
+// one block per problem, after k_bicg_keep (which reads SC_BEST)
+__global__ void k_bicg_keep_scal(Batch B) {
+    const Dev* d = B.d[blockIdx.x];
+    if (threadIdx.x != 0 || krylov_done(d)) return;
+    double* sc = d->scal;
+    const double rr = sc[SC_RR];
+    if (keep_best(d)) sc[SC_BEST] = rr;
+    if (rr < 0.25 * sc[SC_SREF]) {
+        sc[SC_SREF] = rr;
+        sc[SC_SITER] = sc[SC_ITER];
+    } else if (d->mixed && sc[SC_ITER] - sc[SC_SITER] >= (double)STALL_ITERS) {
+        sc[SC_DONE] = 1.0;
+    }
+}
+
+// after the solve: a problem that ended above its tolerance takes x_best when x is worse
+template <int BS, typename T>
+__global__ void __launch_bounds__(TPB) k_bicg_pick(Batch B) {
+    PROB_PROLOGUE
+    const double rr = d->scal[SC_RR];
+    if (rr <= d->scal[SC_TOL2] || rr <= d->scal[SC_BEST] || tid >= d->Nnode) return;
+    const int64_t k0 = node_pad<T>(d, tid) * BS;
+    T* __restrict__ x = vp<T>(d->kx);
+    const T* __restrict__ xb = vp<T>(d->kxb);
+    T xv[BS];
+#pragma unroll
+    for (int a = 0; a < BS; ++a) xv[a] = xb[k0 + a];
+#pragma unroll
+    for (int a = 0; a < BS; ++a) x[k0 + a] = xv[a];
 }
 
 // X += s x (Newton update, FP64; s = 1, or a negative fraction that takes back part of the last
@@ -332,6 +398,8 @@ static void krylov_iters_t(const Group& g, const std::vector<const Dev*>& hc, in
         hipLaunchKernelGGL((k_bicg_xr<DIM + 1, T>), gN, tb, 0, st, Bn);
         hipLaunchKernelGGL(k_bicg_scalars, dim3(B1.n), tb, 0, st, B1, 3, rtol, maxit);
     }
+    hipLaunchKernelGGL((k_bicg_keep<DIM + 1, T>), gN, tb, 0, st, Bn);
+    hipLaunchKernelGGL(k_bicg_keep_scal, dim3(B1.n), dim3(64), 0, st, B1);
 }
 
 void launch_krylov_init(const Group& g, double rtol, int maxit, hipStream_t st) {
@@ -360,6 +428,18 @@ void launch_krylov_iters(const Group& g, const std::vector<const Dev*>& hc, int 
     } else {
         if (g.mixed) krylov_iters_t<3, 1, float>(g, hc, iters, rtol, maxit, st);
         else krylov_iters_t<3, 1, double>(g, hc, iters, rtol, maxit, st);
+    }
+}
+
+void launch_krylov_pick(const Group& g, hipStream_t st) {
+    Batch Bn = make_batch(g.ddev, g.nnode, TPB);
+    const dim3 gN(Bn.pfx[Bn.n]), tb(TPB);
+    if (g.dim == 2) {
+        if (g.mixed) hipLaunchKernelGGL((k_bicg_pick<3, float>), gN, tb, 0, st, Bn);
+        else hipLaunchKernelGGL((k_bicg_pick<3, double>), gN, tb, 0, st, Bn);
+    } else {
+        if (g.mixed) hipLaunchKernelGGL((k_bicg_pick<4, float>), gN, tb, 0, st, Bn);
+        else hipLaunchKernelGGL((k_bicg_pick<4, double>), gN, tb, 0, st, Bn);
     }
 }
 

@@ -139,6 +139,7 @@ void launch_krylov_init(const Group& g, double rtol, int maxit, hipStream_t st);
 void launch_krylov_iters(const Group& g, const std::vector<const Dev*>& host_copies, int iters, double rtol,
                          int maxit, hipStream_t st);
 // X += s x on the free dofs (s = 1: the Newton update; s < 0 takes back part of the last one)
+void launch_krylov_pick(const Group& g, hipStream_t st);
 void launch_newton_update(const Group& g, hipStream_t st, double s = 1.0);
 void launch_apply_jacobian(const Dev* dd, const Dev* hd, const double* v_nat, double* y_nat, hipStream_t st);
 void launch_nodal_out(const Dev* dd, const Dev* hd, int field, double* out, hipStream_t st);

@@ -61,7 +61,10 @@ enum Scal : int {
     SC_DONE = 12,    // 1 when converged or broken down
     SC_BREAK = 13,   // 1 on breakdown
     SC_MMAX = 14,    // largest nodal mass of the step (Stage 1)
-    NSCAL = 16
+    SC_BEST = 15,    // smallest ||r||^2 seen at a chunk end (its iterate is kept in kxb)
+    SC_SREF = 16,    // ||r||^2 when the stagnation count last restarted
+    SC_SITER = 17,   // iteration count at that restart
+    NSCAL = 18
 };
 
 struct MgLevel {
@@ -153,6 +156,7 @@ struct Dev {
     void* Ke;
     // Krylov vectors [Npad*b], precision T
     void* kx; void* kr; void* kh; void* kp; void* kv; void* ks; void* kt; void* kph; void* ksh;
+    void* kxb;        // [Npad*b] iterate of the smallest residual seen at a chunk end
     void* kbt;        // [Npad*dim] rhs of the A cycle (r_u - B1 z_p)
     // multigrid hierarchy
     MgLevel lev[MAXLEV];

@@ -238,7 +238,7 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
     h.rec = c.take<double>((size_t)nrec * rec_points_padded(np));
     h.J = c.take<char>((size_t)h.S * bs * bs * jrows_padded(h.Nnode) * TS);
     h.Ke = c.take<char>(D == 3 ? (size_t)h.Ncell * 16 * 64 * TS : 0);
-    void** kv[9] = {&h.kx, &h.kr, &h.kh, &h.kp, &h.kv, &h.ks, &h.kt, &h.kph, &h.ksh};
+    void** kv[10] = {&h.kx, &h.kr, &h.kh, &h.kp, &h.kv, &h.ks, &h.kt, &h.kph, &h.ksh, &h.kxb};
     for (auto* p : kv) *p = c.take<char>((size_t)P * bs * TS);
     h.kbt = c.take<char>((size_t)P * D * TS);
     for (int l = 0; l < nl; ++l) {
@@ -894,7 +894,11 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
             }
         }
         for (auto& g : G)
-            if (!g.cont.empty()) launch_newton_update(make_group(g.cont), g.st);
+            if (!g.cont.empty()) {
+                Group gc = make_group(g.cont);
+                launch_krylov_pick(gc, g.st);
+                launch_newton_update(gc, g.st);
+            }
         HIPCHK(hipGetLastError());
         if (phase_sync)
             for (auto& g : G)

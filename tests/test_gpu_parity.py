@@ -529,3 +529,22 @@ def test_krylov_graph_replay_equals_direct_launches(precision):
         assert krylov[0] == krylov[1]
         for k in outs[0]:
             assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_truncated_krylov_solves_still_converge(precision):
+    """Krylov solves cut off far above their tolerance (6 iterations): each hands the better of its
+    last and its best iterate to the Newton update, which keeps it only if the residual drops, so
+    Newton still converges (linearly) to the oracle's state at the parity bar."""
+    make, nsteps = STEP_CASES["footing2d_qs_gimp"]
+    w = make()
+    w.options.newton_rtol = 1e-10 if precision == 0 else 1e-8
+    w.options.krylov_max = 6
+    w.options.krylov_check = 2
+    w.options.newton_max = 60
+    print(f"[truncated krylov] precision={precision}", flush=True)
+    errs = _run_steps(w, 2, precision)
+    _assert_fields(errs, 1e-10 if precision == 0 else 1e-6)
+    for e in errs:
+        assert e["krylov"] <= 6 * e["newton"][1], e
+        assert e["newton"][1] > e["newton"][0], e      # the truncated solves cost Newton iterations
