@@ -160,11 +160,14 @@ __global__ void k_mass_clear(Batch B) {
 // largest nodal mass (non-negative doubles order like their bit patterns)
 __global__ void __launch_bounds__(TPB) k_mass_max(Batch B) {
     PROB_PROLOGUE
-    if (tid >= d->Nnode || !d->cons) return;
-    int n[3];
-    node_coords(d, tid, n);
-    const double m = d->M[pad_index(d, n[0], n[1], n[2])];
-    atomicMax((unsigned long long*)(mglob(d) + MG_MAX), (unsigned long long)__double_as_longlong(m));
+    if (!d->cons) return;   // uniform over the block (one problem per block)
+    double m = 0.0;
+    if (tid < d->Nnode) {
+        int n[3];
+        node_coords(d, tid, n);
+        m = d->M[pad_index(d, n[0], n[1], n[2])];
+    }
+    block_max_nonneg(mglob(d) + MG_MAX, m);
 }
 
 // heavy / light split and the lumped start x = b / M

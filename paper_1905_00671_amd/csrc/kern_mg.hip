@@ -547,6 +547,111 @@ __global__ void __launch_bounds__(TPB) k_mg_rap2(Batch B, int fam, int l) {
     }
 }
 
+// Galerkin coarse operator of level l+1 (3D) as three one-axis products.  The prolongation is a
+// tensor product of 1D interpolations, P = P_x P_y P_z (each acting on one axis), so
+//   R A P = P_z^T (P_y^T (P_x^T A P_x) P_y) P_z:
+// pass p coarsens axis p of the rows and of the stencil offsets, on a grid whose axes before p
+// are already coarse and whose axes after p are still fine.  Every operator on the way keeps the
+// 27-point stencil (a 3-point coupling under linear interpolation spans 3 coarse points).  The
+// two intermediates are FP64, in the scratch of the 3D cell matrices (free between the Jacobian
+// gather and the next assembly); the first pass applies the level-0 dof masks and the
+// fixed-stress diagonal, the last writes the level's operator (unit diagonal in empty rows).  One
+// thread per (output row, component pair): 3 fine candidates x 27 slots loaded, 27 stores, where
+// the single-pass product (k_mg_rap2) loads 27 x 27 per coarse row and pair.
+__device__ __forceinline__ int64_t rap_axis_rows(const MgLevel& F, const MgLevel& C, int p) {
+    int64_t r = 1;
+    for (int ax = 0; ax < 3; ++ax) r *= ax <= p ? C.n[ax] : F.n[ax];
+    return r;
+}
+
+template <int BB, typename T, bool FIRST, bool LAST>
+__global__ void __launch_bounds__(TPB) k_mg_rap_axis(Batch B, int fam, int l, int p) {
+    PROB_PROLOGUE
+    if (l + 1 >= d->nlev || (fam == 1 && l + 1 > d->ls_stop)) return;
+    const MgLevel& F = d->lev[l];
+    const MgLevel& C = d->lev[l + 1];
+    int gin[3], gout[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        gin[ax] = ax < p ? C.n[ax] : F.n[ax];
+        gout[ax] = ax <= p ? C.n[ax] : F.n[ax];
+    }
+    const int64_t nin = (int64_t)gin[0] * gin[1] * gin[2];
+    const int64_t nout = (int64_t)gout[0] * gout[1] * gout[2];
+    if (tid >= nout) return;
+    const int a = blockIdx.y / BB, c = blockIdx.y % BB;
+    double* t1 = (double*)d->Ke;   // after pass 0: [27][BB][BB][rows of pass 0]
+    double* t2 = t1 + rap_axis_rows(F, C, 0) * 27 * BB * BB;   // after pass 1
+    const double* src = p == 1 ? t1 : t2;
+    double* dst = p == 0 ? t1 : t2;
+    int O[3];
+    O[0] = (int)(tid % gout[0]);
+    O[1] = (int)((tid / gout[0]) % gout[1]);
+    O[2] = (int)(tid / ((int64_t)gout[0] * gout[1]));
+    const int cz = F.cz[p], nf = F.n[p], nc = C.n[p];
+    const int stride = p == 0 ? 1 : (p == 1 ? 3 : 9);
+    double acc[27];
+#pragma unroll
+    for (int s = 0; s < 27; ++s) acc[s] = 0.0;
+    Op<T> o;
+    if (FIRST) o = op_of<T>(d, fam, l);
+    for (int k = 0; k < 3; ++k) {
+        const int i = cand(O[p], k, cz);
+        if (i < 0 || i >= nf) continue;
+        const double wi = pwa(i, O[p], nf, cz);
+        if (wi == 0.0) continue;
+        int I[3] = {O[0], O[1], O[2]};
+        I[p] = i;
+        const int64_t irow = I[0] + (int64_t)gin[0] * (I[1] + (int64_t)gin[1] * I[2]);
+        double v[27];
+        if (FIRST) {
+#pragma unroll
+            for (int s = 0; s < 27; ++s) v[s] = o.at(s, a, c, irow);
+            if (l == 0) {
+                const int64_t ipn = padded(I, F.np, d->R, 3);
+                const double rm = mask0(d, fam, ipn, a);
+                if (fam == 1) v[13] += fs_term(d, ipn);
+#pragma unroll
+                for (int s = 0; s < 27; ++s) {
+                    const int J[3] = {I[0] + s % 3 - 1, I[1] + (s / 3) % 3 - 1, I[2] + s / 9 - 1};
+                    v[s] *= rm * mask0(d, fam, padded(J, F.np, d->R, 3), c);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 27; ++s) v[s] = src[((int64_t)(s * BB + a) * BB + c) * nin + irow];
+        }
+#pragma unroll
+        for (int s = 0; s < 27; ++s) {
+            const int dl = (s / stride) % 3 - 1;
+            const int j = i + dl;
+            if (j < 0 || j >= nf || v[s] == 0.0) continue;
+            const double vv = wi * v[s];
+            int off[2] = {0, 0};
+            const int npar = rap_parents(cz, k, dl, off);
+            for (int q2 = 0; q2 < npar; ++q2) {
+                const int Jp = O[p] + off[q2];
+                if (Jp < 0 || Jp >= nc) continue;
+                const double wj = cz ? pw1(j, Jp, nf) : 1.0;
+                acc[s + (off[q2] - dl) * stride] += wj * vv;
+            }
+        }
+    }
+    if (!LAST) {
+#pragma unroll
+        for (int s = 0; s < 27; ++s) dst[((int64_t)(s * BB + a) * BB + c) * nout + tid] = acc[s];
+        return;
+    }
+    T* out = (T*)(fam == 0 ? C.A : C.Sm);
+#pragma unroll
+    for (int s = 0; s < 27; ++s) {
+        const int J[3] = {O[0] + s % 3 - 1, O[1] + (s / 3) % 3 - 1, O[2] + s / 9 - 1};
+        const bool valid = J[0] >= 0 && J[1] >= 0 && J[2] >= 0 && J[0] < C.n[0] && J[1] < C.n[1] && J[2] < C.n[2];
+        double w = valid ? acc[s] : 0.0;
+        if (s == 13 && a == c && w == 0.0) w = 1.0;
+        out[((int64_t)(s * BB + a) * BB + c) * C.nrow + tid] = (T)w;
+    }
+}
+
 // Dense inverse of the coarsest operator, Gauss-Jordan with partial pivoting in FP64 in LDS,
 // one block per problem (n <= CMAX).
 template <int BB, typename T>
@@ -1173,6 +1278,26 @@ static std::vector<int64_t> level_rows(const std::vector<const Dev*>& hc, int l)
     return v;
 }
 
+// rows of pass p of the one-axis Galerkin products from level l (3D)
+static int64_t rap_axis_rows_host(const Dev* h, int l, int p) {
+    int64_t r = 1;
+    for (int ax = 0; ax < 3; ++ax) r *= ax <= p ? h->lev[l + 1].n[ax] : h->lev[l].n[ax];
+    return r;
+}
+
+// the two FP64 intermediates of the one-axis products from level l fit every problem's cell-matrix
+// scratch
+static bool rap_axis_fits(const std::vector<const Dev*>& hc, int l) {
+    for (auto* h : hc) {
+        if (h->dim != 3 || !h->Ke) return false;
+        if (l + 1 >= h->nlev) continue;
+        const size_t need = (size_t)(rap_axis_rows_host(h, l, 0) + rap_axis_rows_host(h, l, 1)) * 27 * 9 * sizeof(double);
+        const size_t have = (size_t)h->Ncell * 16 * 64 * (h->mixed ? sizeof(float) : sizeof(double));
+        if (need > have) return false;
+    }
+    return true;
+}
+
 static int max_levels(const std::vector<const Dev*>& hc) {
     int L = 0;
     for (auto* h : hc) L = std::max(L, h->nlev);
@@ -1226,7 +1351,26 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, b
                 // 3D: the LDS scatter on large levels; on small ones (a latency chain either way)
                 // the pair loop, which reaches its loads sooner
                 const std::vector<int64_t> rows = level_rows(hc, l);
-                if (*std::max_element(rows.begin(), rows.end()) > 4096) {
+                if (*std::max_element(rows.begin(), rows.end()) > 4096 && rap_axis_fits(hc, l - 1)) {
+                    // three one-axis products through the cell-matrix scratch
+                    Batch Bp[3];
+                    for (int p = 0; p < 3; ++p) {
+                        std::vector<int64_t> r;
+                        for (auto* h : hc) r.push_back(l < h->nlev ? rap_axis_rows_host(h, l - 1, p) : 1);
+                        Bp[p] = make_batch(g.ddev, r, TPB);
+                    }
+                    const dim3 g0(Bp[0].pfx[Bp[0].n], DIM * DIM), g1(Bp[1].pfx[Bp[1].n], DIM * DIM),
+                        g2(Bp[2].pfx[Bp[2].n], DIM * DIM), tb(TPB);
+                    PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap_axis<DIM, T, true, false>), g0, tb, 0, st, Bp[0], 0, l - 1, 0));
+                    PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap_axis<DIM, T, false, false>), g1, tb, 0, st, Bp[1], 0, l - 1, 1));
+                    PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap_axis<DIM, T, false, true>), g2, tb, 0, st, Bp[2], 0, l - 1, 2));
+                    if (l < LmaxS) {
+                        const dim3 h0(Bp[0].pfx[Bp[0].n], 1), h1(Bp[1].pfx[Bp[1].n], 1), h2(Bp[2].pfx[Bp[2].n], 1);
+                        hipLaunchKernelGGL((k_mg_rap_axis<1, T, true, false>), h0, tb, 0, st, Bp[0], 1, l - 1, 0);
+                        hipLaunchKernelGGL((k_mg_rap_axis<1, T, false, false>), h1, tb, 0, st, Bp[1], 1, l - 1, 1);
+                        hipLaunchKernelGGL((k_mg_rap_axis<1, T, false, true>), h2, tb, 0, st, Bp[2], 1, l - 1, 2);
+                    }
+                } else if (*std::max_element(rows.begin(), rows.end()) > 4096) {
                     PPM_TIMED(KT_RAP, st, hipLaunchKernelGGL((k_mg_rap2<DIM, R, DIM, T>), dim3(Bc.pfx[Bc.n], DIM * DIM), dim3(TPB), 0, st, Bc, 0, l - 1));
                     if (l < LmaxS) hipLaunchKernelGGL((k_mg_rap2<DIM, R, 1, T>), dim3(Bc.pfx[Bc.n], 1), dim3(TPB), 0, st, Bc, 1, l - 1);
                 } else {

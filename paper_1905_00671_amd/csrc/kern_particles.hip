@@ -348,15 +348,17 @@ __global__ void k_clear_mmax(Batch B) {
     if (threadIdx.x == 0) B.d[blockIdx.x]->scal[SC_MMAX] = 0.0;
 }
 
-__global__ void k_node_mass_max(Batch B) {
+__global__ void __launch_bounds__(TPB) k_node_mass_max(Batch B) {
     PROB_PROLOGUE
-    if (tid >= d->Nnode) return;
-    int n[3];
-    n[0] = (int)(tid % d->nn[0]);
-    n[1] = (int)((tid / d->nn[0]) % d->nn[1]);
-    n[2] = d->dim == 3 ? (int)(tid / ((int64_t)d->nn[0] * d->nn[1])) : 0;
-    const double m = d->M[pad_index(d, n[0], n[1], n[2])];
-    atomicMax((unsigned long long*)(d->scal + SC_MMAX), (unsigned long long)__double_as_longlong(m));
+    double m = 0.0;
+    if (tid < d->Nnode) {
+        int n[3];
+        n[0] = (int)(tid % d->nn[0]);
+        n[1] = (int)((tid / d->nn[0]) % d->nn[1]);
+        n[2] = d->dim == 3 ? (int)(tid / ((int64_t)d->nn[0] * d->nn[1])) : 0;
+        m = d->M[pad_index(d, n[0], n[1], n[2])];
+    }
+    block_max_nonneg(d->scal + SC_MMAX, m);
 }
 
 template <int DIM>

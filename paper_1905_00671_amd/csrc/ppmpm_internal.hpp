@@ -483,4 +483,19 @@ __device__ __forceinline__ int64_t pad_index(const Dev* d, int ix, int iy, int i
     return (int64_t)(ix + R) + (int64_t)d->np1[0] * ((iy + R) + (int64_t)d->np1[1] * (iz + R));
 }
 
+// *addr = max(*addr, max over the block's m) for non-negative m (their bit patterns order like
+// the values): a shuffle tree per wavefront, then one atomic per block that holds a positive m.
+// Every thread of the block must call it (it has a barrier).
+__device__ __forceinline__ void block_max_nonneg(double* addr, double m) {
+    __shared__ double wmax[TPB / 64];
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = wmax[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmax(b, wmax[w]);
+        if (b > 0.0) atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(b));
+    }
+}
+
 }  // namespace ppm
