@@ -1348,11 +1348,11 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, b
                         hipLaunchKernelGGL((k_mg_rap<DIM, 1, T, true>), dim3(Bc.pfx[Bc.n], g.S), dim3(TPB), 0, st, Bc, 1, l - 1);
                 }
             } else {
-                // 3D: the LDS scatter on large levels; on small ones (a latency chain either way)
-                // the pair loop, which reaches its loads sooner
+                // 3D: three one-axis products through the cell-matrix scratch on every level
+                // (level 0 -> 1 on the 96^3 footing: 11.1 -> 2.3 ms; the 2,197-row level 0.59 ms
+                // -> three short launches); the single-pass forms remain for a scratch too small
                 const std::vector<int64_t> rows = level_rows(hc, l);
-                if (*std::max_element(rows.begin(), rows.end()) > 4096 && rap_axis_fits(hc, l - 1)) {
-                    // three one-axis products through the cell-matrix scratch
+                if (rap_axis_fits(hc, l - 1)) {
                     Batch Bp[3];
                     for (int p = 0; p < 3; ++p) {
                         std::vector<int64_t> r;
