@@ -1439,6 +1439,10 @@ static void vcycle_up(const Group& g, const std::vector<const Dev*>& hc, int fam
 }
 
 
+// 3D displacement block: levels 0 .. ROW_LEVELS_3D - 1 are swept row by row, the others by halo
+// tiles (see vcycle)
+constexpr int ROW_LEVELS_3D = 2;
+
 static std::vector<int64_t> level_tiles(const std::vector<const Dev*>& hc, int l) {
     std::vector<int64_t> v;
     for (auto* h : hc) v.push_back(l < h->nlev ? mg_tiles(h->dim, h->lev[l].n) : 1);
@@ -1486,21 +1490,25 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
     // neighbours' iterates through L2: HBM bytes 1.35x -> 1.05x the algorithmic ones, FP64 step
     // 330 -> 320 ms, FP32 176 -> 166 ms on the 96^3 footing).  In 2D the tile halo is 1.5 nodes
     // per node and the two extra launches of the row form cost more than they save (512 x 256
-    // footing: 31.6 -> 32.3 ms per FP64 step).
-    const bool rows0 = DIM == 3 && fam == 0;
+    // footing: 31.6 -> 32.3 ms per FP64 step).  The first coarse level (120k rows on the 96^3
+    // footing) gains from the row form too (FP64 step 293 -> 288 ms, mixed 130 -> 128); the
+    // second no longer does.
+    const int nrows = DIM == 3 && fam == 0 ? ROW_LEVELS_3D : 0;   // levels swept row by row
     if (nsm == 1) {
         for (int l = 0; l < Lstd; ++l) {
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
             const dim3 gt(Bt.pfx[Bt.n]);
-            if (l == 0 && rows0)
-                vcycle_down<DIM, R, BB, T, false>(g, hc, fam, 0, rhs0, 1, st);   // also restricts to level 1
-            else if (l == 0)
+            if (l < nrows) {
+                // also restricts to level l + 1
+                if (l == 0) vcycle_down<DIM, R, BB, T, false>(g, hc, fam, 0, rhs0, 1, st);
+                else vcycle_down<DIM, R, BB, T, true>(g, hc, fam, l, LB, 1, st);
+            } else if (l == 0) {
                 PPM_TIMED(fam == 0 ? KT_MG0_RESID : KT_MG0_S, st,
                           hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, false>), gt, tb, 0, st, Bt, fam, 0, rhs0));
-            else {
+            } else {
                 // restriction of the finer residual once per coarse node, then the sweep reads it
                 Batch Bc = make_batch(g.ddev, level_rows(hc, l), TPB);
-                if (!(l == 1 && rows0))
+                if (l != nrows)
                     hipLaunchKernelGGL((k_mg_restrict<DIM, R, BB, T>), dim3(Bc.pfx[Bc.n]), tb, 0, st, Bc, fam, l - 1, LR,
                                        LB);
                 hipLaunchKernelGGL((k_mg_down<DIM, R, BB, T, true>), gt, tb, 0, st, Bt, fam, l, LB);
@@ -1519,9 +1527,10 @@ static void vcycle(const Group& g, const std::vector<const Dev*>& hc, int fam, V
         for (int l = Lstd - 1; l >= 0; --l) {
             Batch Bt = make_batch_blocks(g.ddev, level_tiles(hc, l));
             const dim3 gt(Bt.pfx[Bt.n]);
-            if (l == 0 && rows0)
-                vcycle_up<DIM, R, BB, T, false>(g, hc, fam, 0, rhs0, out0, 1, st);
-            else if (l == 0)
+            if (l < nrows) {
+                if (l == 0) vcycle_up<DIM, R, BB, T, false>(g, hc, fam, 0, rhs0, out0, 1, st);
+                else vcycle_up<DIM, R, BB, T, true>(g, hc, fam, l, LB, LR, 1, st);
+            } else if (l == 0)
                 PPM_TIMED(fam == 0 ? KT_MG0_RESID : KT_MG0_S, st,
                           hipLaunchKernelGGL((k_mg_up<DIM, R, BB, T, false>), gt, tb, 0, st, Bt, fam, 0, rhs0, out0));
             else
