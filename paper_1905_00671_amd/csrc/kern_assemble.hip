@@ -33,18 +33,15 @@ namespace ppm {
     const int64_t lb = blockIdx.x - B.pfx[q];           \
     const int64_t tid = lb * blockDim.x + threadIdx.x;
 
-template <int DIM, int SHAPE>
-__global__ void __launch_bounds__(TPB) k_records(Batch B) {
-    PROB_PROLOGUE
-    if (tid >= d->Np) return;
+// The record of point i, written through rec (global memory, or the wavefront's LDS stage).
+template <int DIM, int SHAPE, typename Rec>
+__device__ __forceinline__ void record_point(const Dev* __restrict__ d, int64_t i, const Rec& rec) {
     constexpr int WB = SHAPE ? 3 : 2;
     constexpr int NN = DIM == 2 ? WB * WB : WB * WB * WB;
     using L = RecLayout<DIM, WB>;
     const int bs = DIM + 1;
     const double* P = d->pw;
     const int64_t s = d->ps;
-    const int64_t i = tid;
-    const RecRef rec(d->rec, i, L::N);
     double w[DIM][3], dw[DIM][3], s0v[DIM][3];
     int base[3] = {0, 0, 0};
     for (int a = 0; a < DIM; ++a) {
@@ -264,6 +261,61 @@ __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     rec[L::TC_] = d->tau * d->ct * Vn;
     rec[L::DT_] = dv * theta;
     rec[L::ST_] = d->tau * Vn * pst;
+}
+
+// A point's record in its wavefront's LDS stage: 80 words per lane, the word index swizzled
+// within its 16-word group by the lane (k ^ (lane & 15)) so that the 64 lanes writing the same
+// field spread over the banks.
+struct StageRec {
+    double* b;
+    int sw;
+    __device__ __forceinline__ double& operator[](int k) const { return b[k ^ sw]; }
+};
+
+// One thread per (sorted) material point.  3D: the 80-word records are staged in LDS and each
+// wavefront then stores its 64 records (40 KB, contiguous) with 16-byte stores that cover whole
+// cache lines; written directly, the 80 stores of a thread land 640 B apart across the
+// wavefront, and the partly written lines leave L2 as 1.8x the record bytes.  The stage is
+// 160 KB per block, one block per CU (the kernel's registers allow one wavefront per SIMD
+// anyway).
+template <int DIM, int SHAPE>
+__global__ void __launch_bounds__(TPB) k_records(Batch B) {
+    PROB_PROLOGUE
+    if constexpr (DIM == 3) {
+        constexpr int NW = RecLayout<3, 2>::N;
+        static_assert(NW == 80, "record stage assumes 80-word records");
+        __shared__ double stage[(TPB / 64) * 64 * NW];
+        const int lane = threadIdx.x & 63;
+        double* ws = stage + (threadIdx.x >> 6) * 64 * NW;
+        const int64_t p0 = tid - lane;   // first point of the wavefront
+        if (p0 >= d->Np) return;         // uniform over the wavefront
+        const int nv = (int)min((int64_t)64, d->Np - p0);
+        if (lane < nv) {
+            const StageRec rec{ws + lane * NW, lane & 15};
+            rec[NW - 2] = 0.0;
+            rec[NW - 1] = 0.0;
+            record_point<DIM, SHAPE>(d, tid, rec);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double* g = d->rec + p0 * NW;
+#pragma unroll 4
+        for (int j = 0; j < NW / 2; ++j) {
+            const int q = j * 128 + 2 * lane;   // word offset inside the wavefront's records
+            const int r = q / NW, w = q - r * NW;
+            if (r < nv) {
+                const int sw = r & 15;
+                double2 v;
+                v.x = ws[r * NW + (w ^ sw)];
+                v.y = ws[r * NW + ((w + 1) ^ sw)];
+                *reinterpret_cast<double2*>(g + q) = v;
+            }
+        }
+    } else {
+        if (tid >= d->Np) return;
+        record_point<DIM, SHAPE>(d, tid, RecRef(d->rec, tid, RecLayout<DIM, SHAPE ? 3 : 2>::N));
+    }
 }
 
 // Node of tile lane t: blocks cover tiles of TILE_X x TILE_Y (x TILE_Z) nodes so that the
