@@ -182,7 +182,7 @@ typedef struct {
     double res_u[PPMPM_MAX_HIST];
     double res_p[PPMPM_MAX_HIST];
     double t_sort, t_assemble, t_precond, t_krylov, t_g2p, t_total;
-    int krylov_breakdowns;
+    int krylov_breakdowns;   /* BiCGStab breakdowns: restarted from the current residual, or ending a solve */
     int ngrid_levels;
     int mass_iters;   /* CG iterations of the consistent-mass mapping (0: lumped) */
 } ppmpm_step_stats;

@@ -263,58 +263,60 @@ __device__ __forceinline__ void record_point(const Dev* __restrict__ d, int64_t 
     rec[L::ST_] = d->tau * Vn * pst;
 }
 
-// A point's record in its wavefront's LDS stage: 80 words per lane, the word index swizzled
-// within its 16-word group by the lane (k ^ (lane & 15)) so that the 64 lanes writing the same
-// field spread over the banks.
+// A point's record in its wavefront's LDS stage: a row of whole 16-word groups per lane, the word
+// index swizzled within its group by the lane (k ^ (lane & 15)) so that the 64 lanes writing the
+// same field spread over the banks.
 struct StageRec {
     double* b;
     int sw;
     __device__ __forceinline__ double& operator[](int k) const { return b[k ^ sw]; }
 };
 
-// One thread per (sorted) material point.  3D: the 80-word records are staged in LDS and each
-// wavefront then stores its 64 records (40 KB, contiguous) with 16-byte stores that cover whole
-// cache lines; written directly, the 80 stores of a thread land 640 B apart across the
-// wavefront, and the partly written lines leave L2 as 1.8x the record bytes.  The stage is
-// 160 KB per block, one block per CU (the kernel's registers allow one wavefront per SIMD
-// anyway).
+// One thread per (sorted) material point.  The records are staged in LDS and each wavefront then
+// stores its 64 records (a contiguous range) with 16-byte stores that cover whole cache lines;
+// written directly, the N stores of a thread land N words apart across the wavefront, and the
+// partly written lines left L2 as 1.8x the record bytes (3D: 8.1 GB per launch for 4.5 GB).
+// The stage is 160 KB (3D) / 128 KB (2D) per block, one block per CU: the kernel's registers
+// allow one wavefront per SIMD anyway.
 template <int DIM, int SHAPE>
 __global__ void __launch_bounds__(TPB) k_records(Batch B) {
     PROB_PROLOGUE
-    if constexpr (DIM == 3) {
-        constexpr int NW = RecLayout<3, 2>::N;
-        static_assert(NW == 80, "record stage assumes 80-word records");
-        __shared__ double stage[(TPB / 64) * 64 * NW];
-        const int lane = threadIdx.x & 63;
-        double* ws = stage + (threadIdx.x >> 6) * 64 * NW;
-        const int64_t p0 = tid - lane;   // first point of the wavefront
-        if (p0 >= d->Np) return;         // uniform over the wavefront
-        const int nv = (int)min((int64_t)64, d->Np - p0);
-        if (lane < nv) {
-            const StageRec rec{ws + lane * NW, lane & 15};
-            rec[NW - 2] = 0.0;
-            rec[NW - 1] = 0.0;
-            record_point<DIM, SHAPE>(d, tid, rec);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double* g = d->rec + p0 * NW;
+    using L = RecLayout<DIM, SHAPE ? 3 : 2>;
+    constexpr int NW = L::N;                       // words per record
+    constexpr int NS = (NW + 15) / 16 * 16;        // stage row
+    constexpr int USED = DIM == 3 ? L::S0_ + 6 : NW;   // 3D: two padding words close the record
+    __shared__ double stage[(TPB / 64) * 64 * NS];
+    const int lane = threadIdx.x & 63;
+    double* ws = stage + (threadIdx.x >> 6) * 64 * NS;
+    const int64_t p0 = tid - lane;   // first point of the wavefront
+    if (p0 >= d->Np) return;         // uniform over the wavefront
+    const int nv = (int)min((int64_t)64, d->Np - p0);
+    if (lane < nv) {
+        const StageRec rec{ws + lane * NS, lane & 15};
+#pragma unroll
+        for (int k = USED; k < NW; ++k) rec[k] = 0.0;
+        record_point<DIM, SHAPE>(d, tid, rec);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double* g = d->rec + p0 * NW;   // 16-byte aligned: p0 is a multiple of 64
+    const int total = nv * NW;
 #pragma unroll 4
-        for (int j = 0; j < NW / 2; ++j) {
-            const int q = j * 128 + 2 * lane;   // word offset inside the wavefront's records
-            const int r = q / NW, w = q - r * NW;
-            if (r < nv) {
-                const int sw = r & 15;
-                double2 v;
-                v.x = ws[r * NW + (w ^ sw)];
-                v.y = ws[r * NW + ((w + 1) ^ sw)];
-                *reinterpret_cast<double2*>(g + q) = v;
-            }
+    for (int j = 0; j < (64 * NW + 127) / 128; ++j) {
+        const int q = j * 128 + 2 * lane;   // word offset inside the wavefront's records
+        if (q >= total) continue;
+        const int r0 = q / NW, w0 = q - r0 * NW;
+        const double v0 = ws[r0 * NS + (w0 ^ (r0 & 15))];
+        if (q + 1 < total) {
+            const int r1 = (q + 1) / NW, w1 = q + 1 - r1 * NW;
+            double2 v;
+            v.x = v0;
+            v.y = ws[r1 * NS + (w1 ^ (r1 & 15))];
+            *reinterpret_cast<double2*>(g + q) = v;
+        } else {
+            g[q] = v0;
         }
-    } else {
-        if (tid >= d->Np) return;
-        record_point<DIM, SHAPE>(d, tid, RecRef(d->rec, tid, RecLayout<DIM, SHAPE ? 3 : 2>::N));
     }
 }
 

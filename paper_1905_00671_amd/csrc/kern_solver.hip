@@ -134,15 +134,27 @@ __global__ void __launch_bounds__(TPB) k_bicg_init(Batch B) {
     block_partials<1>(d, lb, v);
 }
 
-// p = r + beta (p - omega v)
+// p = r + beta (p - omega v); on a restart rhat = p = r
 template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_p(Batch B) {
     PROB_PROLOGUE
     if (krylov_done(d) || tid >= d->Nnode) return;
     const int64_t k0 = node_pad<T>(d, tid) * BS;
-    const T beta = (T)d->scal[SC_BETA], om = (T)d->scal[SC_OMEGA];
     T* __restrict__ p = vp<T>(d->kp);
     const T* __restrict__ r = vp<T>(d->kr);
+    if (d->scal[SC_RESTART] == 2.0) {
+        T* __restrict__ h = vp<T>(d->kh);
+        T rv[BS];
+#pragma unroll
+        for (int a = 0; a < BS; ++a) rv[a] = r[k0 + a];
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+            p[k0 + a] = rv[a];
+            h[k0 + a] = rv[a];
+        }
+        return;
+    }
+    const T beta = (T)d->scal[SC_BETA], om = (T)d->scal[SC_OMEGA];
     const T* __restrict__ v = vp<T>(d->kv);
     T pv[BS], rv[BS], vv[BS];
 #pragma unroll
@@ -155,9 +167,20 @@ __global__ void __launch_bounds__(TPB) k_bicg_p(Batch B) {
     for (int a = 0; a < BS; ++a) p[k0 + a] = rv[a] + beta * (pv[a] - om * vv[a]);
 }
 
+// BiCGStab breakdown ((rhat, v) = 0, rho = 0 or omega = 0 with the residual still finite and
+// above the tolerance): restart from the current iterate with rhat = p = r, at most
+// MAX_RESTARTS times per solve; after that the solve ends (breakdown reported).
+constexpr int MAX_RESTARTS = 8;
+
+__device__ __forceinline__ bool can_restart(const double* sc) {
+    const double rr = sc[SC_RR];
+    return isfinite(rr) && rr > 0.0 && sc[SC_NRESTART] < (double)MAX_RESTARTS;
+}
+
 // alpha = rho / (rhat, v) from the SpMV's partials (each block reduces them itself, in the
 // order of the scalar kernel, so all blocks agree; block 0 records alpha), then s = r - alpha v.
-// A zero or non-finite (rhat, v) is a breakdown: the problem is marked done.
+// A zero or non-finite (rhat, v) is a breakdown: the rest of the iteration is skipped (done
+// flag) and the scalar kernel sets up a restart, or ends the solve.
 template <int BS, typename T>
 __global__ void __launch_bounds__(TPB) k_bicg_s(Batch B) {
     PROB_PROLOGUE
@@ -170,7 +193,8 @@ __global__ void __launch_bounds__(TPB) k_bicg_s(Batch B) {
     if (lb == 0 && threadIdx.x == 0) {
         d->scal[SC_RV] = s0;
         if (brk) {
-            d->scal[SC_BREAK] = 1.0;
+            if (can_restart(d->scal)) d->scal[SC_RESTART] = 1.0;
+            else d->scal[SC_BREAK] = 1.0;
             d->scal[SC_DONE] = 1.0;
         } else {
             d->scal[SC_ALPHA] = alpha;
@@ -248,7 +272,24 @@ __global__ void __launch_bounds__(TPB) k_bicg_xr(Batch B) {
 __global__ void k_bicg_scalars(Batch B, int stage, double rtol, int maxit) {
     const int q = blockIdx.x;
     const Dev* d = B.d[q];
-    if (stage != 0 && krylov_done(d)) return;
+    // every thread reads the flags before thread 0 may change them, so that the block decides
+    // uniformly
+    const bool done0 = krylov_done(d);
+    const double rst0 = d->scal[SC_RESTART];
+    __syncthreads();
+    if (stage != 0 && done0 && rst0 != 1.0) return;
+    if (stage != 0 && rst0 == 1.0) {
+        // breakdown in k_bicg_s: x and r are those of the previous iteration (RR their norm)
+        if (threadIdx.x == 0) {
+            double* sc = d->scal;
+            sc[SC_ITER] += 1.0;
+            sc[SC_NRESTART] += 1.0;
+            sc[SC_RHO] = sc[SC_RR];
+            sc[SC_RESTART] = 2.0;
+            sc[SC_DONE] = sc[SC_ITER] >= (double)maxit ? 1.0 : 0.0;
+        }
+        return;
+    }
     __shared__ double sh[2][TPB];
     const int64_t nblk = (d->Nnode + TPB - 1) / TPB;
     const int slot = stage == 3 ? 2 : 0;
@@ -282,13 +323,22 @@ __global__ void k_bicg_scalars(Batch B, int stage, double rtol, int maxit) {
         sc[SC_BEST] = s0;
         sc[SC_SREF] = s0;
         sc[SC_SITER] = 0.0;
+        sc[SC_RESTART] = 0.0;
+        sc[SC_NRESTART] = 0.0;
         sc[SC_DONE] = (s0 == 0.0 || maxit <= 0) ? 1.0 : 0.0;
     } else {
         double rho_new = s0;
         sc[SC_RR] = s1;
         sc[SC_ITER] += 1.0;
+        sc[SC_RESTART] = 0.0;   // a restart set up by the previous iteration has been applied
         bool conv = s1 <= sc[SC_TOL2];
         bool brk = (rho_new == 0.0 || sc[SC_OMEGA] == 0.0 || !isfinite(s1));
+        if (!conv && brk && sc[SC_ITER] < (double)maxit && can_restart(sc)) {
+            sc[SC_NRESTART] += 1.0;
+            sc[SC_RHO] = s1;   // (rhat, r) with rhat = r
+            sc[SC_RESTART] = 2.0;
+            return;
+        }
         if (!conv && brk) sc[SC_BREAK] = 1.0;
         if (conv || brk || sc[SC_ITER] >= (double)maxit) {
             sc[SC_DONE] = 1.0;

@@ -64,7 +64,10 @@ enum Scal : int {
     SC_BEST = 15,    // smallest ||r||^2 seen at a chunk end (its iterate is kept in kxb)
     SC_SREF = 16,    // ||r||^2 when the stagnation count last restarted
     SC_SITER = 17,   // iteration count at that restart
-    NSCAL = 18
+    SC_RESTART = 18, // 1: breakdown in k_bicg_s, rest of the iteration skipped; 2: the next
+                     // iteration restarts from the current residual (rhat = p = r)
+    SC_NRESTART = 19,// restarts of this solve
+    NSCAL = 20
 };
 
 struct MgLevel {

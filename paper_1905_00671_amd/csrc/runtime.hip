@@ -910,7 +910,8 @@ ppmpm_status batched_body(ppmpm_problem* const* probs, int nprob, const double* 
                 const int kit = (int)g.cont[j]->spin[SC_ITER];
                 if (it < PPMPM_MAX_HIST) so.krylov_iters[it] = kit;
                 so.krylov_total += kit;
-                if (g.cont[j]->spin[SC_BREAK] != 0.0) so.krylov_breakdowns++;
+                // breakdowns: those restarted from the current residual, and a final one
+                so.krylov_breakdowns += (int)g.cont[j]->spin[SC_NRESTART] + (g.cont[j]->spin[SC_BREAK] != 0.0 ? 1 : 0);
                 g.ns[g.contk[j]].kfail = !(g.cont[j]->spin[SC_RR] <= g.cont[j]->spin[SC_TOL2]);
                 so.t_precond += phase_sync ? secs(t3, t4) : 0.0;
                 so.t_krylov += phase_sync ? secs(t4, t5) : secs(t2, t5);
