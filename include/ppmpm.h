@@ -108,6 +108,10 @@ typedef struct {
  *                    of every step on the active nodes that have an inactive node among their
  *                    3^dim - 1 neighbours inside the grid (the grid edges are supports or
  *                    symmetry planes, not free surfaces); 0: boundary data only
+ *   negligible_mass  a node whose lumped mass is below this fraction of the step's largest nodal
+ *                    mass is outside the material (mass, mapped fields and dofs dropped); <= 0:
+ *                    1e-15.  Larger values (1e-6 for bodies in contact) drop nodes that a point
+ *                    domain barely reaches, whose displacement is otherwise nearly undetermined
  */
 typedef struct {
     int shape;
@@ -124,6 +128,7 @@ typedef struct {
     int mg_smooth;
     int drained_surface;
     int consistent_mass;
+    double negligible_mass;
 } ppmpm_options;
 
 /* Boundary data of one step on the grid nodes (natural order).

@@ -203,8 +203,10 @@ class OracleProblem:
         # a node whose mass is a negligible fraction of the largest (a point domain that only just
         # reaches its support) is inactive: its rows would otherwise be ~1e-18 of the others and
         # the Newton update there unbounded (reading: below NEGLIGIBLE_MASS of the step's largest
-        # nodal mass the node is treated as outside the material)
-        act = M > self.NEGLIGIBLE_MASS * M.max()
+        # nodal mass, or the option negligible_mass when it is positive, the node is treated as
+        # outside the material)
+        cut = getattr(self.opt, "negligible_mass", 0.0)
+        act = M > (cut if cut > 0 else self.NEGLIGIBLE_MASS) * M.max()
         M = np.where(act, M, 0.0)
         safe = np.where(act, M, 1.0)
         out = dict(M=M, active=act, Pn=np.where(act, Mp / safe, 0.0))

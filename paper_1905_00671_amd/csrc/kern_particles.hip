@@ -342,7 +342,7 @@ __global__ void k_p2g(Batch B) {
 }
 
 // Largest nodal mass of the step (non-negative doubles order like their bit patterns), then the
-// nodes below NEGLIGIBLE_MASS of it leave the material: mass, mapped fields, dof masks and the
+// nodes below the negligible-mass fraction of it leave the material: mass, mapped fields, dof masks and the
 // Newton start are cleared as for a node without points.
 __global__ void k_clear_mmax(Batch B) {
     if (threadIdx.x == 0) B.d[blockIdx.x]->scal[SC_MMAX] = 0.0;
@@ -371,7 +371,7 @@ __global__ void k_cut_light_nodes(Batch B) {
     n[2] = DIM == 3 ? (int)(tid / ((int64_t)d->nn[0] * d->nn[1])) : 0;
     const int64_t pn = pad_index(d, n[0], n[1], n[2]);
     const double m = d->M[pn];
-    if (!(m > 0.0) || m > NEGLIGIBLE_MASS * d->scal[SC_MMAX]) return;
+    if (!(m > 0.0) || m > d->negl * d->scal[SC_MMAX]) return;
     d->M[pn] = d->Pn[pn] = d->Mp[pn] = d->pdn[pn] = d->pddn[pn] = 0.0;
     for (int a = 0; a < 3; ++a) d->vn[pn * 3 + a] = d->an[pn * 3 + a] = 0.0;
     for (int c = 0; c <= DIM; ++c) {

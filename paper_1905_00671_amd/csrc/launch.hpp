@@ -108,7 +108,8 @@ void launch_sort(const Group& g, hipStream_t st);
 void launch_bc(const Dev* dd, int64_t nnode, const uint8_t* uf, const double* ui, const uint8_t* pf,
                const double* pv, const double* fe, const double* qe, hipStream_t st);
 void launch_p2g(const Group& g, hipStream_t st);
-// nodes below NEGLIGIBLE_MASS of the largest nodal mass leave the material (after launch_p2g)
+// nodes below the negligible-mass fraction of the largest nodal mass leave the material (after
+// launch_p2g)
 void launch_cut_light_nodes(const Group& g, hipStream_t st);
 // zero pore pressure on the free surface of the problems with Dev::drain set (after launch_p2g)
 void launch_drain_surface(const Group& g, hipStream_t st);

@@ -106,6 +106,7 @@ struct Dev {
     double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
     double kin;   // inertia factor of the Newmark fixed-stress modulus (fs_term)
     int drain;    // 1: zero pore pressure on the free surface of the material (k_drain_surface)
+    double negl;  // negligible-mass fraction (k_cut_light_nodes)
     // consistent-mass mapping of the P2G fields (kern_mass.hip), when cons is set
     int cons;
     int ncol;         // mapped fields: p (quasi-static); p, v, a, pdot, pddot (dynamic: 2 dim + 3)
@@ -326,7 +327,7 @@ constexpr double GIMP_TOUCH = 1e-10;
 // A node whose mass is below this fraction of the step's largest nodal mass (a point domain that
 // only just reaches its support) is outside the material: its rows would be ~1e-18 of the others
 // and the Newton update there unbounded.
-constexpr double NEGLIGIBLE_MASS = 1e-15;
+constexpr double NEGLIGIBLE_MASS = 1e-15;   // default of ppmpm_options.negligible_mass
 
 // 1D basis of one particle along one axis.  Original MPM: the two nodes of the containing cell
 // (clamped), hat weights.  GIMP: the domain [x-lp, x+lp] clipped to the grid, three nodes from

@@ -1089,6 +1089,7 @@ static ppmpm_status init_problem(ppmpm_problem* p, const ppmpm_grid* grid, const
     h.phi0 = mat->phi0;
     h.alpha_vis = opt->dynamic ? mat->alpha_vis : 0.0;   // quasi-static: no viscous stress
     h.drain = opt->drained_surface ? 1 : 0;
+    h.negl = opt->negligible_mass > 0.0 ? opt->negligible_mass : NEGLIGIBLE_MASS;
     h.rho_f = mat->rho_f;
     for (int a = 0; a < 3; ++a) h.g[a] = a < grid->dim ? mat->g[a] : 0.0;
     h.dt = 1.0;
