@@ -196,20 +196,23 @@ def test_impact_coarse_fp64_through_contact():
     _run(w, ref, int(ref["last_step"]), 0, 1e-6, None, fields=("u", "x"))
 
 
-def test_impact_paper_size_momentum():
-    """The paper's two-body impact (2 x 20,108 points, h = 0.01 m, dt = 1 ms) over the 1,400 steps of
-    free flight before the contact at t ~ 1.5 s: every step converges and the total momentum stays
-    zero (no external force; the bodies share the grid's velocity field) to the Newton tolerance
-    (each step may leave a momentum residual of 1e-8 of the initial one, times dt).  The contact
-    itself is the skipped coarse case above."""
+def test_impact_paper_size_through_contact():
+    """The paper's two-body impact (2 x 20,108 points, h = 0.01 m, dt = 1 ms) over its 3 s: free
+    flight, the contact at t ~ 1.5 s, the compression and the rebound.  Every step converges; the
+    total momentum stays zero (no external force; the bodies share the grid's velocity field) up
+    to the Newton tolerance and what the nodes below the workload's negligible-mass cutoff carried
+    (1e-5 of the largest nodal mass: below 1e-5 of one body's momentum; ~4e-7 measured); the
+    collision takes most of the kinetic energy into strain and pore pressure and the rebound
+    returns much of it."""
     from paper_1905_00671_amd import binding as B
     import time
-    w = W.two_body_impact(nsteps=1400)
+    w = W.two_body_impact(nsteps=3000)
     m = w.particles.mass
     n1 = w.meta["bodies"][0]
     body = np.abs((m[:n1, None] * w.particles.v0[:n1]).sum(0)).max()
+    ke0 = 0.5 * (m * (w.particles.v0 ** 2).sum(1)).sum()
     gp = B.Problem.from_workload(w, precision=0)
-    newton, krylov = [], []
+    newton, krylov, kes = [], [], []
     try:
         t0 = time.perf_counter()
         for n in range(1, w.nsteps + 1):
@@ -217,14 +220,16 @@ def test_impact_paper_size_momentum():
             assert st["status"] == 0, (n, st["status"])
             newton.append(st["newton_iters"])
             krylov.append(st["krylov_total"])
-            if n % 200 == 0:
+            if n % 250 == 0:
                 v = gp.get("v")
                 p = gp.get("p")
                 mom = np.abs((m[:, None] * v).sum(0)).max()
                 ke = 0.5 * (m * (v ** 2).sum(1)).sum()
+                kes.append(ke)
                 print(f"  step {n}: momentum {mom / body:.1e} of one body's, KE {ke:.4f} J/m, max |p| {np.abs(p).max():.2f} Pa, "
-                      f"newton {np.mean(newton[-200:]):.2f}, krylov/step {np.mean(krylov[-200:]):.1f}, "
+                      f"newton {np.mean(newton[-250:]):.2f}, krylov/step {np.mean(krylov[-250:]):.1f}, "
                       f"{(time.perf_counter() - t0) / n * 1e3:.1f} ms/step", flush=True)
-                assert mom < 1e-6 * body, (n, mom)   # to the Newton tolerance
+                assert mom < 1e-5 * body, (n, mom)
     finally:
         gp.close()
+    assert min(kes) < 0.3 * ke0 and kes[-1] > 0.5 * ke0, (ke0, kes)

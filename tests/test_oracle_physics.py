@@ -432,14 +432,14 @@ def test_two_body_impact_momentum_and_contact():
 
 
 def test_two_body_impact_negligible_mass_cut():
-    """The impact workload leaves nodes below 1e-6 of the largest nodal mass out of the material.
+    """The impact workload leaves nodes below 1e-5 of the largest nodal mass out of the material.
     Momentum is then conserved up to what those nodes carried: each step drops at most a few
-    nodes of mass < 1e-6 M_max moving at < 2 v0, so over 700 steps the total stays below 1e-5 of
-    one body's momentum (measured 1e-7); and Newton takes at most 4 iterations through the contact
-    (with every node kept, the grazed nodes make this run's contact steps take up to 8, and 13 on
-    the coarse workload started at 0.2 m)."""
+    nodes of mass < 1e-5 M_max moving at < 2 v0, so over 700 steps the total stays below 1e-4 of
+    one body's momentum (measured ~1e-6); and Newton takes at most 4 iterations through the
+    contact (with every node kept, the grazed nodes make this run's contact steps take up to 8,
+    and 13 on the coarse workload started at 0.2 m)."""
     w = W.two_body_impact(h=0.05, ppa=2, v0=0.1, dt=1e-3, centre=0.3)
-    assert w.options.negligible_mass == 1e-6
+    assert w.options.negligible_mass == 1e-5
     pr = O.from_workload(w)
     n1 = w.meta["bodies"][0]
     body = np.abs((pr.m[:n1, None] * pr.v[:n1]).sum(0)).max()
@@ -448,6 +448,6 @@ def test_two_body_impact_negligible_mass_cut():
     for n in range(1, 701):
         st = pr.step(w.dt, w.bc(n))
         worst = max(worst, st["newton_iters"])
-    assert np.abs((pr.m[:, None] * pr.v).sum(0)).max() < 1e-5 * body
+    assert np.abs((pr.m[:, None] * pr.v).sum(0)).max() < 1e-4 * body
     assert worst <= 4, worst
     assert 0.5 * (pr.m * (pr.v ** 2).sum(1)).sum() < 0.75 * ke0   # through the contact
