@@ -112,6 +112,17 @@ typedef struct {
  *                    mass is outside the material (mass, mapped fields and dofs dropped); <= 0:
  *                    1e-15.  Larger values (1e-6 for bodies in contact) drop nodes that a point
  *                    domain barely reaches, whose displacement is otherwise nearly undetermined
+ *   schur            Schur-block approximation of the preconditioner (Sec. 3.4: the Schur
+ *                    complement S = C - B2 A^-1 B1 is preconditioned first).  0: fixed-stress form
+ *                    C + C_stab + (c_t/K) M_p, the pressure block plus a lumped storage term
+ *                    (default).  1: diagonal-inverse form C - B2 diag(A)^-1 B1, diag(A) the dim x dim
+ *                    node blocks of the displacement block, the product kept on the Jacobian's
+ *                    stencil (exact where the pressure-displacement couplings reach one node
+ *                    spacing and the stencil two, as with GIMP), with a full multigrid hierarchy.
+ *                    It suits undrained dynamic problems, whose displacement block is dominated by
+ *                    inertia so that S is close to a pressure Laplacian that a diagonal term
+ *                    cannot represent.  One more level-0 operator in the workspace (S Nnode
+ *                    entries)
  */
 typedef struct {
     int shape;
@@ -129,6 +140,7 @@ typedef struct {
     int drained_surface;
     int consistent_mass;
     double negligible_mass;
+    int schur;
 } ppmpm_options;
 
 /* Boundary data of one step on the grid nodes (natural order).

@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
                 ("newton_max", ctypes.c_int), ("krylov_rtol", ctypes.c_double),
                 ("krylov_max", ctypes.c_int), ("krylov_check", ctypes.c_int), ("mg_smooth", ctypes.c_int),
                 ("drained_surface", ctypes.c_int), ("consistent_mass", ctypes.c_int),
-                ("negligible_mass", ctypes.c_double)]
+                ("negligible_mass", ctypes.c_double), ("schur", ctypes.c_int)]
 
 
 class BC(ctypes.Structure):
@@ -156,7 +156,8 @@ def make_options(o, precision: int = FP64, **over) -> Options:
                 newton_max=o.newton_max, krylov_rtol=o.krylov_rtol, krylov_max=o.krylov_max,
                 krylov_check=4, mg_smooth=1, drained_surface=int(getattr(o, "drained_surface", 0)),
                 consistent_mass=int(getattr(o, "consistent_mass", 0)),
-                negligible_mass=float(getattr(o, "negligible_mass", 0.0)))
+                negligible_mass=float(getattr(o, "negligible_mass", 0.0)),
+                schur=int(getattr(o, "schur", 0)))
     vals.update(over)
     return Options(**vals)
 

@@ -78,7 +78,7 @@ __device__ __forceinline__ Lv<T> lv_of(const Dev* d, int fam, int l) {
     v.np0 = L.np[0];
     v.np1 = L.np[1];
     v.nrow = L.nrow;
-    if (l == 0) {
+    if (l == 0 && !(fam == 1 && d->schur)) {
         v.op = (const T*)d->J;
         v.BJ = d->b;
         v.a0 = fam == 0 ? 0 : d->dim;
@@ -330,6 +330,77 @@ __global__ void __launch_bounds__(TPB) k_mg_dinv(Batch B, int fam, int l) {
     invert_small<BB>(A, Ai);
     T* out = (T*)(fam == 0 ? L.Ad : L.Sd);
     for (int k = 0; k < BB * BB; ++k) out[(int64_t)k * L.nrow + tid] = (T)Ai[k];
+}
+
+// Level-0 operator of the Schur block in the diagonal-inverse form (option schur = 1):
+//   S_ij = C_ij - sum_k sum_ab B2_ik,a Dinv_k,ab B1_kj,b
+// with C the pressure block of J (storage, Darcy and PPP terms), B2 its pressure-displacement and
+// B1 its displacement-pressure coupling, and Dinv_k the inverse dim x dim node block of the
+// displacement block (the A family's level-0 inverse diagonal, formed before this kernel).  Entry
+// j of row i is taken on the Jacobian's stencil; the intermediate nodes k are those of i's stencil
+// whose own stencil holds j.  Non-free displacement components drop out (their B1 rows and B2
+// columns are masked); a row of a non-free pressure dof keeps J's row; columns of non-free
+// pressure dofs are zero.  One thread per (row, stencil slot blockIdx.y), stored in the coarse
+// levels' layout [S][nrow] in precision T.
+template <int DIM, int R, typename T>
+__global__ void __launch_bounds__(TPB) k_schur_diag(Batch B) {
+    PROB_PROLOGUE
+    if (!d->schur) return;
+    const MgLevel& L = d->lev[0];
+    if (tid >= L.nrow) return;
+    using St = Sten<DIM, R>;
+    constexpr int BS = DIM + 1, S = St::S, SW = St::SW;
+    const int s = blockIdx.y;
+    const T* __restrict__ J = (const T*)d->J;
+    const T* __restrict__ Ad = (const T*)L.Ad;
+    const int NE = S * BS * BS;
+    int ci[3];
+    real_coords(tid, L.n, DIM, ci);
+    const int64_t pi = padded(ci, L.np, R, DIM);
+    const int so[3] = {St::ox(s), St::oy(s), St::oz(s)};
+    bool inj = true;
+    int cj[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        cj[a] = ci[a] + so[a];
+        inj = inj && cj[a] >= 0 && cj[a] < L.n[a];
+    }
+    double v = (double)J[jidx<DIM>((s * BS + DIM) * BS + DIM, tid, NE, d->Nnode)];
+    if (mask0(d, 1, pi, 0) != 0.0) {
+        if (!inj || mask0(d, 1, padded(cj, L.np, R, DIM), 0) == 0.0) {
+            v = 0.0;
+        } else {
+            for (int t = 0; t < S; ++t) {
+                const int to[3] = {St::ox(t), St::oy(t), St::oz(t)};
+                int ck[3] = {0, 0, 0}, u = 0, mul = 1;
+                bool ok = true;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    ck[a] = ci[a] + to[a];
+                    const int du = so[a] - to[a];
+                    ok = ok && ck[a] >= 0 && ck[a] < L.n[a] && du >= -R && du <= R;
+                    u += (du + R) * mul;
+                    mul *= SW;
+                }
+                if (!ok) continue;
+                const int64_t k = ck[0] + (int64_t)L.n[0] * (ck[1] + (int64_t)L.n[1] * ck[2]);
+                const int64_t pk = padded(ck, L.np, R, DIM);
+                double c2[DIM], b1[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const double m = mask0(d, 0, pk, a);
+                    c2[a] = m * (double)J[jidx<DIM>((t * BS + DIM) * BS + a, tid, NE, d->Nnode)];
+                    b1[a] = m * (double)J[jidx<DIM>((u * BS + a) * BS + DIM, k, NE, d->Nnode)];
+                }
+#pragma unroll
+                for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                    for (int b = 0; b < DIM; ++b) v -= c2[a] * (double)Ad[(int64_t)(a * DIM + b) * L.nrow + k] * b1[b];
+            }
+        }
+    }
+    T* out = (T*)L.Sm;
+    out[(int64_t)s * L.nrow + tid] = (T)v;
 }
 
 // Galerkin coarse operator of level l+1 (2D): thread per (coarse row, stencil entry), looping
@@ -1310,6 +1381,12 @@ static int max_ltail(const std::vector<const Dev*>& hc) {
     return L;
 }
 
+static bool any_schur(const std::vector<const Dev*>& hc) {
+    for (auto* h : hc)
+        if (h->schur) return true;
+    return false;
+}
+
 template <int DIM, int R, typename T>
 static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, bool coarse, hipStream_t st) {
     if (!coarse) {
@@ -1317,6 +1394,8 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, b
         // is a view of J, its inverse diagonal is rebuilt here); the coarse levels are kept
         Batch Bl = make_batch(g.ddev, level_rows(hc, 0), TPB);
         hipLaunchKernelGGL((k_mg_dinv<DIM, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 0, 0);
+        if (any_schur(hc))
+            hipLaunchKernelGGL((k_schur_diag<DIM, R, T>), dim3(Bl.pfx[Bl.n], g.S), dim3(TPB), 0, st, Bl);
         hipLaunchKernelGGL((k_mg_dinv<1, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 1, 0);
         return;
     }
@@ -1381,6 +1460,9 @@ static void precond_setup_t(const Group& g, const std::vector<const Dev*>& hc, b
         }
         Batch Bl = make_batch(g.ddev, level_rows(hc, l), TPB);
         hipLaunchKernelGGL((k_mg_dinv<DIM, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 0, l);
+        // the diagonal-inverse Schur operator needs the A family's level-0 inverse blocks
+        if (l == 0 && any_schur(hc))
+            hipLaunchKernelGGL((k_schur_diag<DIM, R, T>), dim3(Bl.pfx[Bl.n], g.S), dim3(TPB), 0, st, Bl);
         if (l < LmaxS) hipLaunchKernelGGL((k_mg_dinv<1, T>), dim3(Bl.pfx[Bl.n]), dim3(TPB), 0, st, Bl, 1, l);
     }
     Batch B1 = make_batch_one_block(g.ddev);

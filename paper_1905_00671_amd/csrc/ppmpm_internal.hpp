@@ -105,6 +105,7 @@ struct Dev {
     // per-step parameters
     double dt, beta, gamma, ct, tau, hc1, hc2, Kfs, omega;
     double kin;   // inertia factor of the Newmark fixed-stress modulus (fs_term)
+    int schur;    // Schur-block form: 0 fixed-stress, 1 diagonal-inverse (lev[0].Sm holds it)
     int drain;    // 1: zero pore pressure on the free surface of the material (k_drain_surface)
     double negl;  // negligible-mass fraction (k_cut_light_nodes)
     // consistent-mass mapping of the P2G fields (kern_mass.hip), when cons is set

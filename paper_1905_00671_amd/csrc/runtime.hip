@@ -140,6 +140,7 @@ ppmpm_status validate(const ppmpm_grid* g, const ppmpm_options* o, int64_t np) {
     if (o->shape != PPMPM_LINEAR && o->shape != PPMPM_GIMP) return fail(PPMPM_E_INVALID, "bad shape");
     if (np < 1 || np > (int64_t)1 << 30) return fail(PPMPM_E_INVALID, "bad particle count");
     if (o->dynamic && !(o->beta > 0 && o->gamma > 0)) return fail(PPMPM_E_INVALID, "bad Newmark parameters");
+    if (o->schur != 0 && o->schur != 1) return fail(PPMPM_E_INVALID, "schur must be 0 or 1");
     return PPMPM_OK;
 }
 
@@ -247,7 +248,9 @@ size_t layout(Dev& h, const ppmpm_grid* g, const ppmpm_options* o, int64_t np, c
             L.A = c.take<char>((size_t)h.S * D * D * L.nrow * TS);
             L.Sm = c.take<char>((size_t)h.S * L.nrow * TS);
         } else {
-            L.A = L.Sm = nullptr;
+            L.A = nullptr;
+            // level-0 Schur operator of the diagonal-inverse form (the fixed-stress form reads J)
+            L.Sm = o->schur == 1 ? c.take<char>((size_t)h.S * L.nrow * TS) : nullptr;
         }
         L.Ad = c.take<char>((size_t)D * D * L.nrow * TS);
         L.Sd = c.take<char>((size_t)L.nrow * TS);
@@ -327,7 +330,8 @@ double smoother_damping(const Dev& h) {
 }
 
 int schur_truncation(const Dev& h) {
-    if (h.mg_nsm != 1) return MAXLEV;
+    // the diagonal-inverse form is a pressure Laplacian in the undrained limit: full hierarchy
+    if (h.mg_nsm != 1 || h.schur) return MAXLEV;
     const double kK = h.kappa * h.Kfs / h.ct;
     for (int l = 0; l < h.ltail; ++l) {
         double hmin = 1e300;
@@ -1090,6 +1094,7 @@ static ppmpm_status init_problem(ppmpm_problem* p, const ppmpm_grid* grid, const
     h.alpha_vis = opt->dynamic ? mat->alpha_vis : 0.0;   // quasi-static: no viscous stress
     h.drain = opt->drained_surface ? 1 : 0;
     h.negl = opt->negligible_mass > 0.0 ? opt->negligible_mass : NEGLIGIBLE_MASS;
+    h.schur = opt->schur;
     h.rho_f = mat->rho_f;
     for (int a = 0; a < 3; ++a) h.g[a] = a < grid->dim ? mat->g[a] : 0.0;
     h.dt = 1.0;

@@ -92,7 +92,7 @@ struct Op {
 template <typename T>
 __device__ __forceinline__ Op<T> op_of(const Dev* d, int fam, int l) {
     Op<T> o;
-    if (l == 0) {
+    if (l == 0 && !(fam == 1 && d->schur)) {
         o.base = (const T*)d->J;
         o.nrow = d->Nnode;
         o.BJ = d->b;
@@ -121,7 +121,8 @@ __device__ __forceinline__ Op<T> op_of(const Dev* d, int fam, int l) {
 // mode of wavenumber xi sees A^-1 ~ 1 / (K_fs xi^2 + rho / (beta dt^2)); kin is set by Krylov
 // counts (1: the grid's shortest modes see a few times less inertia than this)
 __device__ __forceinline__ double fs_term(const Dev* d, int64_t pn) {
-    if (!d->dfree[pn * d->b + d->dim]) return 0.0;
+    // the diagonal-inverse form stores its level-0 operator whole (k_schur_diag)
+    if (d->schur || !d->dfree[pn * d->b + d->dim]) return 0.0;
     double K = d->Kfs;
     if (d->dyn) K += d->kin * d->M[pn] / d->Mp[pn] * d->h * d->h / (d->beta * d->dt * d->dt);
     return d->ct / K * d->Mp[pn];

@@ -95,12 +95,10 @@ def test_config2_fp64_without_ppp():
     _run(w, ref, 10, 0, 1e-10, 1e-9)
 
 
-@pytest.mark.skip(reason="on this 64 x 64 undrained dynamic footing the mixed path's BiCGStab stalls from the "
-                         "second Newton iteration of step 1 on (the FP32 Jacobian and preconditioner; FP64 "
-                         "recurrence vectors stall the same way) and Newton does not reach 1e-8 within 25 "
-                         "iterations; config 2 is an FP64 configuration, the mixed path is exercised on the "
-                         "quasi-static configs, the harmonic footing and a 16 x 16 dynamic footing")
 def test_config2_mixed_prefix():
+    """The mixed path on config 2 with the workload's diagonal-inverse Schur block: with the
+    fixed-stress diagonal the FP32 solves left the pressure block nearly unreduced (its residual
+    is ~1e-5 of the momentum one, below the FP32 solves' 1e-6 target) and Newton stalled."""
     ref = _load("config2_tauW")
     w = W.config(2)
     print(f"[config 2 mixed] {w.particles.n} points, 10 steps", flush=True)
@@ -164,13 +162,14 @@ def test_harmonic_footing_newton_krylov_pattern():
     finally:
         gp.close()
     # Table 1: three Newton iterations (1.2e-3, 2.3e-6, 3.4e-9 at step 100; the exact Jacobian,
-    # damping and inertia terms included, converges faster here: about 1e-3, 1e-8, 1e-15) and
-    # 12-17 Krylov iterations with the paper's AMG-based block preconditioner (the geometric
-    # multigrid V(1,1) blocks here take 35-85)
+    # damping and inertia terms included, converges faster here: about 1e-3, 1e-8, 1e-15; a step
+    # may pass the test after two) and 12-17 Krylov iterations with the paper's AMG-based block
+    # preconditioner (the geometric multigrid V(1,1) blocks with the diagonal-inverse Schur block
+    # take 9-12 here; 35-85 with the fixed-stress diagonal)
     for n, (newton, ratio, krylov, mass_it) in rows.items():
-        assert newton == 3, (n, newton)
-        assert ratio[1] < 1e-2 and ratio[2] < 1e-6 and ratio[-1] < 1e-8, (n, ratio)
-        assert max(krylov) <= 120, (n, krylov)
+        assert 2 <= newton <= 3, (n, newton)
+        assert ratio[1] < 1e-2 and ratio[-1] < 1e-8, (n, ratio)
+        assert max(krylov) <= 17, (n, krylov)
         assert 0 < mass_it <= 400, (n, mass_it)
 
 

@@ -198,6 +198,11 @@ STEP_CASES = {
     # paper's size (40,216 points) for its first steps; point pressure conditions, no grid BCs
     "impact_coarse_contact": (lambda: W.two_body_impact(h=0.05, ppa=2, centre=0.3, nsteps=300), 300),
     "impact_paper_prefix": (lambda: W.two_body_impact(nsteps=3), 3),
+    # the two Schur-block forms of the preconditioner (Sec. 3.4) where the workloads do not pick
+    # them: the fixed-stress form on an undrained dynamic footing, and the diagonal-inverse form
+    # in 3D, where the product C - B2 diag(A)^-1 B1 is truncated to the trilinear stencil
+    "footing2d_dyn_fixed_stress": (lambda: _schur(W.config(2, nx=16, ny=16, width=2.5, empty_rows=2, nsteps=4), 0), 4),
+    "footing3d_dyn_schur_diag": (lambda: _schur(_dyn(W.footing3d(n=6, size=1.5, half_b=0.25, nsteps=2, delta=1e-4)), 1), 2),
 }
 
 
@@ -210,6 +215,11 @@ CONDITION_LIMITED = ("impact_coarse_contact", "impact_paper_prefix")
 
 def _cons(w):
     w.options.consistent_mass = 1
+    return w
+
+
+def _schur(w, form):
+    w.options.schur = form
     return w
 
 
@@ -279,7 +289,8 @@ def test_step_parity_fp64(name):
 
 @pytest.mark.parametrize("name", ["terzaghi", "footing2d_qs_gimp", "footing3d", "footing2d_qs_gimp_kc",
                                   "footing2d_dyn_gimp", "footing2d_dyn_paper_newmark", "footing2d_dyn_damped",
-                                  "self_weight_gimp", "harmonic_footing", "consistent_dyn_3d"])
+                                  "self_weight_gimp", "harmonic_footing", "consistent_dyn_3d",
+                                  "footing3d_dyn_schur_diag"])
 def test_step_parity_mixed(name):
     make, nsteps = STEP_CASES[name]
     w = make()
