@@ -1,11 +1,13 @@
 // Geometric multigrid for the two sub-blocks of the block upper-triangular preconditioner of
 // the Newton-Krylov solver (Sec. 3.4): family A (displacement block, dim x dim node blocks) and
-// family S (fixed-stress Schur approximation C + C_stab + (c_t/K) M_p, scalar).
+// family S (scalar Schur approximation: the fixed-stress form C + C_stab + (c_t/K) M_p, whose
+// level 0 is J's pressure block plus a diagonal, or the diagonal-inverse form C - B2 diag(A)^-1 B1,
+// whose level 0 is stored whole).
 //
 // Hierarchy: the structured background grid, coarsened by two along every axis that still has
 // more than three nodes (semi-coarsening keeps elongated grids solvable); bilinear/trilinear
 // transfer; Galerkin coarse operators P^T A P built on the device; level-0 operators are views
-// into the stored Jacobian blocks (no copy).  Smoother: damped block Jacobi, V(nsm, nsm).
+// into the stored Jacobian blocks (no copy; the diagonal-inverse Schur form excepted).  Smoother: damped block Jacobi, V(nsm, nsm).
 // Coarsest level: dense inverse (Gauss-Jordan in LDS, at most CMAX unknowns).
 //
 // Launch structure: levels with more than TAILMAX nodes use one kernel per operation (pre-smooth

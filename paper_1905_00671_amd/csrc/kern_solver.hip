@@ -6,7 +6,8 @@
 // geometric-multigrid V-cycle each on the structured background grid: damped block-Jacobi
 // smoothing, bilinear transfer, Galerkin coarse operators R A P built on the device, a dense
 // inverse on the coarsest level.  S is approximated by the fixed-stress form
-// C + C_stab + (c_t / K) M_p (M_p lumped, K = lam + 2G/dim).
+// C + C_stab + (c_t / K) M_p (M_p lumped, K = lam + 2G/dim), or, as an option for problems whose
+// displacement block is dominated by inertia, by C - B2 diag(A)^-1 B1 (k_schur_diag).
 //
 // Precision T is double (FP64 path) or float (mixed path: Jacobian, SpMV, preconditioner and
 // Krylov vectors in FP32; dot products accumulate in FP64; the Newton update is FP64).
