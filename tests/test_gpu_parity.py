@@ -336,6 +336,41 @@ def test_batched_equals_alone():
             p.close()
 
 
+def test_batched_schur_forms_equal_alone():
+    """A batch that mixes the two Schur-block forms (an undrained dynamic footing with each, and a
+    quasi-static footing with its truncated fixed-stress hierarchy) gives bit-identical results
+    to the problems stepped alone: the level-0 Schur operator is formed only for the problems
+    that ask for it, and each problem's hierarchy keeps its own depth."""
+    B = _binding()
+
+    def make():
+        a = W.config(2, nx=16, ny=16, width=2.5, empty_rows=2, nsteps=3)
+        b = _schur(W.config(2, nx=16, ny=16, width=2.5, empty_rows=2, nsteps=3), 0)
+        c = W.config(3, nx=16, ny=8, width=4.0, empty_rows=2, nsteps=3)
+        return [a, b, c]
+
+    ws = make()
+    assert [w.options.schur for w in ws] == [1, 0, 0]
+    alone = []
+    for w in ws:
+        p = B.Problem.from_workload(w)
+        for n in (1, 2, 3):
+            p.step(w.dt, w.bc(n))
+        alone.append((p.get("u"), p.get("p")))
+        p.close()
+    ps = [B.Problem.from_workload(w) for w in ws]
+    try:
+        for n in (1, 2, 3):
+            st = B.step_batched(ps, [w.dt for w in ws], [w.bc(n) for w in ws])
+            assert all(s["status"] == 0 for s in st), st
+        for (u0, p0), p in zip(alone, ps):
+            assert np.array_equal(p.get("u"), u0)
+            assert np.array_equal(p.get("p"), p0)
+    finally:
+        for p in ps:
+            p.close()
+
+
 def test_transactional_failure_leaves_state():
     """A step that cannot converge (one Newton iteration allowed on a loaded step that needs two)
     reports PPMPM_E_NEWTON and leaves the material points untouched."""
