@@ -314,12 +314,14 @@ SPMV_SIG = "template <int DIM, int R, typename T>\n__global__ void __launch_boun
 MG_DOWN_SIG = "__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FULL ? 2 : 8))) k_mg_down("
 MG_UP_SIG = "__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(1, FULL ? 2 : 8))) k_mg_up("
 MG_ROW_SIG = "__device__ __forceinline__ void row_resid("
+MG_LV_SIG = "__device__ __forceinline__ Lv<T> lv_of("
 # source digest a counter summary must carry to be used for a kernel (family)
 KERNEL_DIGEST = {
     "spmv": lambda: kernel_digest("kern_solver.hip", SPMV_SIG),
     "mg0": lambda: hashlib.sha256((kernel_digest("kern_mg.hip", MG_DOWN_SIG) +
                                    kernel_digest("kern_mg.hip", MG_UP_SIG) +
-                                   kernel_digest("kern_mg.hip", MG_ROW_SIG)).encode()).hexdigest(),
+                                   kernel_digest("kern_mg.hip", MG_ROW_SIG) +
+                                   kernel_digest("kern_mg.hip", MG_LV_SIG)).encode()).hexdigest(),
 }
 
 
