@@ -263,6 +263,23 @@ enum {
 };
 ppmpm_status ppmpm_get_field(const ppmpm_problem* p, int field, double* out, int where);
 
+/* Checkpoint and resume.  A problem carries nothing from one step to the next but its material
+ * points: the background grid is reset every step (Sec. 3.1) and the mappings, Newton and
+ * Krylov solves start afresh.  A checkpoint is therefore the committed point state: a 64-byte
+ * header (the bytes "PPMPMST1", format version, dim, shape, fields per point, np, cells per axis,
+ * h), every per-point field in the problem's current cell-sorted order, and the points' ids.
+ *   ppmpm_state_bytes  size of a checkpoint of p
+ *   ppmpm_save_state   writes it to out[bytes] (host or device memory, `where`); needs points
+ *   ppmpm_load_state   restores one into p, a problem created with the same grid, material,
+ *                      options and point count; steps then continue bit for bit as they would
+ *                      have from the saved problem
+ * PPMPM_E_INVALID for a null pointer, a buffer smaller than ppmpm_state_bytes, a problem without
+ * points (save), or a header that does not match p (load); p is unchanged then.  The caller owns
+ * the buffer; both calls return after the copy has completed. */
+ppmpm_status ppmpm_state_bytes(const ppmpm_problem* p, size_t* bytes);
+ppmpm_status ppmpm_save_state(const ppmpm_problem* p, void* out, size_t bytes, int where);
+ppmpm_status ppmpm_load_state(ppmpm_problem* p, const void* in, size_t bytes, int where);
+
 /* Inspection of one Newton iterate, for verification.  Performs Stage 1 (sort, P2G) for the
  * current state with boundary data bc and step dt, then evaluates the residual and assembles the
  * Jacobian at the nodal state U[nnode*dim], P[nnode] (natural order).  R[nnode*(dim+1)] receives

@@ -102,6 +102,12 @@ def lib() -> ctypes.CDLL:
         L.ppmpm_step_batched.argtypes = [vp, i32, vp, vp, vp]
         L.ppmpm_get_field.restype = i32
         L.ppmpm_get_field.argtypes = [vp, i32, vp, i32]
+        L.ppmpm_state_bytes.restype = i32
+        L.ppmpm_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ppmpm_save_state.restype = i32
+        L.ppmpm_save_state.argtypes = [vp, vp, ctypes.c_size_t, i32]
+        L.ppmpm_load_state.restype = i32
+        L.ppmpm_load_state.argtypes = [vp, vp, ctypes.c_size_t, i32]
         L.ppmpm_eval_residual.restype = i32
         L.ppmpm_eval_residual.argtypes = [vp, dbl, vp, vp, vp, vp, i32]
         L.ppmpm_apply_jacobian.restype = i32
@@ -235,6 +241,19 @@ class Problem:
         if raise_on_error:
             _check(s)
         return st.as_dict()
+
+    def save_state(self) -> np.ndarray:
+        """Checkpoint of the committed material-point state (ppmpm_save_state) as host bytes."""
+        n = ctypes.c_size_t()
+        _check(self.L.ppmpm_state_bytes(self.h, ctypes.byref(n)))
+        buf = np.zeros(n.value, np.uint8)
+        _check(self.L.ppmpm_save_state(self.h, buf.ctypes.data_as(ctypes.c_void_p), n.value, HOST))
+        return buf
+
+    def load_state(self, buf: np.ndarray) -> None:
+        """Restores a checkpoint written by save_state (ppmpm_load_state)."""
+        buf = np.ascontiguousarray(buf, np.uint8)
+        _check(self.L.ppmpm_load_state(self.h, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes, HOST))
 
     def get(self, name: str) -> np.ndarray:
         f = FIELDS[name]

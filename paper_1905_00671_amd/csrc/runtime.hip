@@ -1014,6 +1014,37 @@ static ppmpm_status scratch_address(void** out) {
 // ---------------------------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------------------------
+namespace {
+// checkpoint header (padded to STATE_HDR bytes)
+struct StateHeader {
+    char magic[8];
+    int32_t version, dim, shape, npf;
+    int64_t np;
+    int32_t ncell[3], pad;
+    double h;
+};
+constexpr size_t STATE_HDR = 64;
+static_assert(sizeof(StateHeader) <= STATE_HDR, "checkpoint header");
+
+StateHeader state_header(const ppmpm_problem* p) {
+    StateHeader hd{};
+    std::memcpy(hd.magic, "PPMPMST1", 8);
+    hd.version = 1;
+    hd.dim = p->h.dim;
+    hd.shape = p->h.shape;
+    hd.npf = NPF;
+    hd.np = p->np;
+    for (int a = 0; a < 3; ++a) hd.ncell[a] = p->h.nc[a];
+    hd.h = p->h.h;
+    return hd;
+}
+
+size_t state_field_bytes(const ppmpm_problem* p) { return (size_t)NPF * p->np * sizeof(double); }
+size_t state_bytes(const ppmpm_problem* p) {
+    return STATE_HDR + state_field_bytes(p) + ((size_t)p->np * sizeof(int) + 7) / 8 * 8;
+}
+}  // namespace
+
 extern "C" {
 
 size_t ppmpm_workspace_bytes(const ppmpm_grid* grid, int64_t np, const ppmpm_options* opt) {
@@ -1177,6 +1208,56 @@ ppmpm_status ppmpm_get_field(const ppmpm_problem* pc, int field, double* out, in
     HIPCHK(hipGetLastError());
     if (where != PPMPM_DEVICE) HIPCHK(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, p->st));
     HIPCHK(hipStreamSynchronize(p->st));
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_state_bytes(const ppmpm_problem* p, size_t* bytes) {
+    if (!p || !bytes) return fail(PPMPM_E_INVALID, "bad state_bytes arguments");
+    *bytes = state_bytes(p);
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_save_state(const ppmpm_problem* pc, void* out, size_t bytes, int where) {
+    ppmpm_problem* p = const_cast<ppmpm_problem*>(pc);
+    if (!p || !out || !p->have_particles || bytes < state_bytes(p)) return fail(PPMPM_E_INVALID, "bad save_state arguments");
+    char hbuf[STATE_HDR] = {};
+    const StateHeader hd = state_header(p);
+    std::memcpy(hbuf, &hd, sizeof(hd));
+    char* o = (char*)out;
+    const size_t fb = state_field_bytes(p), ib = (size_t)p->np * sizeof(int);
+    const hipMemcpyKind k = where == PPMPM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(o + STATE_HDR, p->h.pc, fb, k, p->st));
+    HIPCHK(hipMemcpyAsync(o + STATE_HDR + fb, p->h.idc, ib, k, p->st));
+    if (where == PPMPM_DEVICE) HIPCHK(hipMemcpyAsync(o, hbuf, STATE_HDR, hipMemcpyHostToDevice, p->st));
+    else std::memcpy(o, hbuf, STATE_HDR);
+    HIPCHK(hipStreamSynchronize(p->st));   // also keeps hbuf alive until its copy is done
+    return PPMPM_OK;
+}
+
+ppmpm_status ppmpm_load_state(ppmpm_problem* p, const void* in, size_t bytes, int where) {
+    if (!p || !in || bytes < state_bytes(p)) return fail(PPMPM_E_INVALID, "bad load_state arguments");
+    char hbuf[STATE_HDR];
+    if (where == PPMPM_DEVICE) {
+        HIPCHK(hipMemcpyAsync(hbuf, in, STATE_HDR, hipMemcpyDeviceToHost, p->st));
+        HIPCHK(hipStreamSynchronize(p->st));
+    } else {
+        std::memcpy(hbuf, in, STATE_HDR);
+    }
+    StateHeader hd;
+    std::memcpy(&hd, hbuf, sizeof(hd));
+    const StateHeader want = state_header(p);
+    bool ok = std::memcmp(hd.magic, want.magic, 8) == 0 && hd.version == want.version && hd.dim == want.dim &&
+              hd.shape == want.shape && hd.npf == want.npf && hd.np == want.np && hd.h == want.h;
+    for (int a = 0; a < 3; ++a) ok = ok && hd.ncell[a] == want.ncell[a];
+    if (!ok) return fail(PPMPM_E_INVALID, "checkpoint does not match this problem");
+    const char* i = (const char*)in;
+    const size_t fb = state_field_bytes(p), ib = (size_t)p->np * sizeof(int);
+    const hipMemcpyKind k = where == PPMPM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(p->h.pc, i + STATE_HDR, fb, k, p->st));
+    HIPCHK(hipMemcpyAsync(p->h.idc, i + STATE_HDR + fb, ib, k, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    p->have_particles = true;
+    p->have_jacobian = false;
     return PPMPM_OK;
 }
 

@@ -371,6 +371,60 @@ def test_batched_schur_forms_equal_alone():
             p.close()
 
 
+@pytest.mark.parametrize("name", ["footing2d_dyn_gimp", "harmonic_footing", "footing3d_mg", "self_weight_gimp"])
+def test_checkpoint_resume_bitwise(name):
+    """A problem restored from a checkpoint (ppmpm_save_state / ppmpm_load_state) into a fresh
+    problem steps on bit for bit like the problem it was saved from: the committed material
+    points are the whole state between steps (dynamic: with their Newmark history; consistent
+    mass; the 3D multigrid; the self-weight column's growing steps and drained surface)."""
+    B = _binding()
+    make, _ = STEP_CASES[name]
+    w = make()
+    dt = w.meta.get("dt_of", lambda n: w.dt)
+    fields = ("x", "u", "p", "F", "vol", "sig", "v", "a", "pd", "pdd", "lp")
+    a = B.Problem.from_workload(w)
+    b = B.Problem.from_workload(w)
+    try:
+        a.step(dt(1), w.bc(1))
+        ck = a.save_state()
+        for n in (2, 3):
+            a.step(dt(n), w.bc(n))
+        ref = {k: a.get(k).copy() for k in fields}
+        print(f"[checkpoint] case={name} np={w.particles.n} bytes={ck.nbytes}", flush=True)
+        b.load_state(ck)
+        for n in (2, 3):
+            b.step(dt(n), w.bc(n))
+        for k in fields:
+            assert np.array_equal(b.get(k), ref[k]), k
+    finally:
+        a.close()
+        b.close()
+
+
+def test_checkpoint_mismatch_refused():
+    """A checkpoint of another problem (other point count and grid), a truncated one and one with
+    a damaged header are refused with PPMPM_E_INVALID, and the problem keeps its points."""
+    B = _binding()
+    w1 = W.config(2, nx=16, ny=16, width=2.5, empty_rows=2, nsteps=2)
+    w2 = W.config(2, nx=12, ny=12, width=2.5, empty_rows=2, nsteps=2)
+    a = B.Problem.from_workload(w1)
+    b = B.Problem.from_workload(w2)
+    try:
+        ck = a.save_state()
+        x0 = b.get("x").copy()
+        bad = ck.copy()
+        bad[:8] = np.frombuffer(b"NOTASTAT", np.uint8)
+        own = b.save_state()
+        for buf in (ck, own[: own.nbytes - 8], bad[: own.nbytes]):
+            with pytest.raises(B.PPMPMError) as e:
+                b.load_state(buf)
+            assert e.value.status == B.E_INVALID
+        assert np.array_equal(b.get("x"), x0)
+    finally:
+        a.close()
+        b.close()
+
+
 def test_transactional_failure_leaves_state():
     """A step that cannot converge (one Newton iteration allowed on a loaded step that needs two)
     reports PPMPM_E_NEWTON and leaves the material points untouched."""
