@@ -376,52 +376,71 @@ __global__ void __launch_bounds__(TPB) k_mass_finish(Batch B) {
 // ---------------------------------------------------------------------------------------------
 // point tractions
 // ---------------------------------------------------------------------------------------------
+// Nodal forces of the point tractions, gathered per node: the points of the buckets whose windows
+// can reach the node are visited in bucket order and, inside a bucket, in the sort's id order, so
+// every node's sum is formed in the same order on every run (no floating-point atomics).  Along a
+// loaded point's normal its face x + lp n takes the grid's linear hat (two nodes: inside the
+// point's GIMP window, or within one cell of an original-MPM point's own), along the other axes
+// the point's own basis; buckets n - 2 .. n + 1 per axis cover both.
 template <int DIM, int SHAPE>
 __global__ void __launch_bounds__(TPB) k_point_force(Batch B, const double* __restrict__ F,
                                                      const double* __restrict__ nrm) {
     PROB_PROLOGUE
-    if (tid >= d->Np) return;
+    if (tid >= d->Nnode) return;
     constexpr int WB = SHAPE ? 3 : 2;
-    const int64_t id = d->idw[tid];
-    double f[DIM];
-    bool any = false;
+    int n[3];
+    node_coords(d, tid, n);
+    int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
     for (int a = 0; a < DIM; ++a) {
-        f[a] = F[id * DIM + a];
-        any |= f[a] != 0.0;
+        clo[a] = n[a] - 2 < 0 ? 0 : n[a] - 2;
+        chi[a] = n[a] + 1 > d->nc[a] - 1 ? d->nc[a] - 1 : n[a] + 1;
     }
-    if (!any) return;
     const double* P = d->pw;
     const int64_t s = d->ps;
-    double w[DIM][3], dw[3], s0v[3];
-    int base[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
-    for (int a = 0; a < DIM; ++a) {
-        const double xa = P[(PX + a) * s + tid], lpa = P[(PLP + a) * s + tid];
-        const double na = nrm ? nrm[id * DIM + a] : 0.0;
-        if (fabs(na) > 0.5) {
-            base[a] = basis_1d<0>(xa + lpa * (na > 0 ? 1.0 : -1.0), 0.0, d->x0[a], d->h, d->nc[a], w[a], dw, s0v);
-            cnt[a] = 2;
-        } else {
-            base[a] = basis_1d<SHAPE>(xa, lpa, d->x0[a], d->h, d->nc[a], w[a], dw, s0v);
-            cnt[a] = WB;
-        }
-    }
-    const int bs = DIM + 1;
-    for (int k2 = 0; k2 < (DIM == 3 ? cnt[2] : 1); ++k2)
-        for (int k1 = 0; k1 < cnt[1]; ++k1)
-            for (int k0 = 0; k0 < cnt[0]; ++k0) {
-                const int kk[3] = {k0, k1, k2};
-                int idx[3] = {0, 0, 0};
-                double sw = 1.0;
-                bool ok = true;
-                for (int a = 0; a < DIM; ++a) {
-                    idx[a] = base[a] + kk[a];
-                    if (idx[a] < 0 || idx[a] >= d->nn[a]) ok = false;
-                    sw *= w[a][kk[a]];
+    double acc[DIM];
+    for (int a = 0; a < DIM; ++a) acc[a] = 0.0;
+    bool hit = false;
+    for (int cz = (DIM == 3 ? clo[2] : 0); cz <= (DIM == 3 ? chi[2] : 0); ++cz)
+        for (int cy = clo[1]; cy <= chi[1]; ++cy)
+            for (int cx = clo[0]; cx <= chi[0]; ++cx) {
+                const int64_t c = cx + (int64_t)d->nc[0] * (cy + (int64_t)d->nc[1] * cz);
+                const int p0 = d->cstart[c], p1 = d->cstart[c + 1];
+                for (int i = p0; i < p1; ++i) {
+                    const int64_t id = d->idw[i];
+                    double f[DIM];
+                    bool any = false;
+                    for (int a = 0; a < DIM; ++a) {
+                        f[a] = F[id * DIM + a];
+                        any |= f[a] != 0.0;
+                    }
+                    if (!any) continue;
+                    double sw = 1.0;
+                    bool in = true;
+                    for (int a = 0; a < DIM && in; ++a) {
+                        double w[3], dw[3], s0v[3];
+                        const double xa = P[(PX + a) * s + i], lpa = P[(PLP + a) * s + i];
+                        const double na = nrm ? nrm[id * DIM + a] : 0.0;
+                        int base, cnt;
+                        if (fabs(na) > 0.5) {
+                            base = basis_1d<0>(xa + lpa * (na > 0 ? 1.0 : -1.0), 0.0, d->x0[a], d->h, d->nc[a], w, dw, s0v);
+                            cnt = 2;
+                        } else {
+                            base = basis_1d<SHAPE>(xa, lpa, d->x0[a], d->h, d->nc[a], w, dw, s0v);
+                            cnt = WB;
+                        }
+                        const int li = n[a] - base;
+                        if (li < 0 || li >= cnt) in = false;
+                        else sw *= w[li];
+                    }
+                    if (!in || sw == 0.0) continue;
+                    for (int a = 0; a < DIM; ++a) acc[a] += sw * f[a];
+                    hit = true;
                 }
-                if (!ok || sw == 0.0) continue;
-                const int64_t pn = pad_index(d, idx[0], idx[1], idx[2]);
-                for (int a = 0; a < DIM; ++a) atomicAdd(&d->fext[pn * bs + a], sw * f[a]);
             }
+    if (!hit) return;
+    const int64_t pn = pad_index(d, n[0], n[1], n[2]);
+    const int bs = DIM + 1;
+    for (int a = 0; a < DIM; ++a) d->fext[pn * bs + a] += acc[a];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -431,7 +450,7 @@ void launch_point_force(const Group& g, const std::vector<const double*>& F, con
                         hipStream_t st) {
     for (size_t q = 0; q < g.ddev.size(); ++q) {
         if (!F[q]) continue;
-        Batch B = make_batch({g.ddev[q]}, {g.np[q]}, TPB);
+        Batch B = make_batch({g.ddev[q]}, {g.nnode[q]}, TPB);
         const dim3 gr(B.pfx[B.n]), tb(TPB);
         if (g.dim == 2 && g.shape == 0) hipLaunchKernelGGL((k_point_force<2, 0>), gr, tb, 0, st, B, F[q], nrm[q]);
         else if (g.dim == 2) hipLaunchKernelGGL((k_point_force<2, 1>), gr, tb, 0, st, B, F[q], nrm[q]);

@@ -15,6 +15,7 @@ The scheduler is written against four callables so that its bookkeeping runs wit
 """
 from __future__ import annotations
 
+import json
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -71,12 +72,13 @@ def serve(requests: Sequence, budget_bytes: int, *, bytes_of: Callable, open_pro
           step_many: Callable, close_problem: Callable, points_of: Callable = lambda r: 0,
           realtime: bool = True, clock: Callable[[], float] = time.perf_counter,
           sleep: Callable[[float], None] = time.sleep, max_active: int = 256,
-          on_finish: Optional[Callable] = None) -> Report:
+          on_finish: Optional[Callable] = None, on_step: Optional[Callable] = None) -> Report:
     """Runs the request stream to completion and returns the report.
 
     realtime: arrivals are honoured on the wall clock (the loop sleeps while nothing is active);
     otherwise the clock skips idle gaps, so arrival order and admission still follow the trace
-    but no time is spent waiting.  ``on_finish(job)`` is called before a finished problem is closed.
+    but no time is spent waiting.  ``on_finish(job)`` is called before a finished problem is closed;
+    ``on_step(job, step, stats, latency_ms)`` after every request step (``jsonl_step_log``).
     """
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     active: List[Job] = []
@@ -123,6 +125,8 @@ def serve(requests: Sequence, budget_bytes: int, *, bytes_of: Callable, open_pro
         keep = []
         for j, st in zip(active, stats):
             rep.step_latency_ms.append((te - ts) * 1e3)
+            if on_step is not None:
+                on_step(j, j.steps_done + 1, st, (te - ts) * 1e3)
             j.newton += int(st.get("newton_iters", 0))
             rep.particle_updates += int(points_of(j.req)) * int(st.get("newton_iters", 0))
             j.krylov += int(st.get("krylov_total", 0))
@@ -149,6 +153,19 @@ def serve(requests: Sequence, budget_bytes: int, *, bytes_of: Callable, open_pro
         active = keep
     rep.wall_s = clock() - t0
     return rep
+
+
+def jsonl_step_log(fh) -> Callable:
+    """An ``on_step`` callback that writes one JSON line per request step to the text stream fh:
+    the request id, step index, status, batch latency, and what the runtime reports for the step
+    (Newton iterations and their block-wise residual history, Krylov iterations per Newton
+    iteration, phase times)."""
+    def log(job, step, st, latency_ms):
+        rec = {"request": getattr(job.req, "rid", None), "step": int(step), "latency_ms": float(latency_ms)}
+        for k, v in st.items():
+            rec[k] = [float(x) if isinstance(x, float) else int(x) for x in v] if isinstance(v, (list, tuple)) else v
+        fh.write(json.dumps(rec) + "\n")
+    return log
 
 
 def gpu_backend(precision: int, workload_cache: Optional[Dict] = None, **over):

@@ -401,6 +401,33 @@ def test_checkpoint_resume_bitwise(name):
         b.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", ["footing2d_qs_gimp", "footing3d_mg", "harmonic_footing", "terzaghi_point_load"])
+def test_repeat_runs_bitwise_identical(name, precision):
+    """Five fresh runs of the same steps leave bit-identical states: the hot path has no
+    floating-point atomics (reductions run in a fixed order, the largest nodal mass is an integer
+    maximum, point tractions are gathered per node in the sort's order), so results do not depend
+    on how the GPU schedules the work."""
+    B = _binding()
+    make, _ = STEP_CASES[name]
+    ref = None
+    for rep in range(5):
+        w = make()
+        p = B.Problem.from_workload(w, precision=precision)
+        try:
+            for n in (1, 2, 3):
+                p.step(w.dt, w.bc(n))
+            got = {k: p.get(k) for k in ("x", "u", "p", "sig", "v", "pd")}
+        finally:
+            p.close()
+        if ref is None:
+            ref = got
+            print(f"[repeat] case={name} precision={precision} np={w.particles.n}", flush=True)
+        else:
+            for k in got:
+                assert np.array_equal(got[k], ref[k]), (rep, k)
+
+
 def test_checkpoint_mismatch_refused():
     """A checkpoint of another problem (other point count and grid), a truncated one and one with
     a damaged header are refused with PPMPM_E_INVALID, and the problem keeps its points."""

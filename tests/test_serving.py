@@ -90,6 +90,22 @@ def test_failure_retires_request_and_frees_budget():
     assert [e[:2] for e in log] == [("open", 0), ("close", 0), ("open", 1), ("close", 1)]
 
 
+def test_jsonl_step_log():
+    """One JSON line per request step, failed steps included, with the runtime's statistics."""
+    import io
+    import json
+    clock = FakeClock()
+    reqs = [FakeReq(0, 0.0, 40, 3), FakeReq(1, 0.0, 40, 4, fail_at=2)]
+    fh = io.StringIO()
+    rep = S.serve(reqs, 100, clock=clock, sleep=clock.sleep, realtime=False, on_step=S.jsonl_step_log(fh),
+                  **_fake_backend(clock, 100, []))
+    lines = [json.loads(x) for x in fh.getvalue().splitlines()]
+    assert len(lines) == len(rep.step_latency_ms) == 3 + 2
+    assert [(x["request"], x["step"], x["status"]) for x in lines if x["request"] == 1] == [(1, 1, 0), (1, 2, 1)]
+    assert [x["step"] for x in lines if x["request"] == 0] == [1, 2, 3]
+    assert all(x["newton_iters"] == 3 and x["krylov_total"] == 10 and x["latency_ms"] > 0 for x in lines)
+
+
 def test_skip_idle_gaps_when_not_realtime():
     clock = FakeClock()
     reqs = [FakeReq(0, 0.0, 10, 1), FakeReq(1, 100.0, 10, 1)]
