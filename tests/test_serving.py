@@ -106,6 +106,14 @@ def test_jsonl_step_log():
     assert all(x["newton_iters"] == 3 and x["krylov_total"] == 10 and x["latency_ms"] > 0 for x in lines)
 
 
+def test_zero_budget_rejects_everything():
+    clock = FakeClock()
+    reqs = [FakeReq(0, 0.0, 10, 2), FakeReq(1, 0.1, 20, 1)]
+    log = []
+    rep = S.serve(reqs, 0, clock=clock, sleep=clock.sleep, realtime=False, **_fake_backend(clock, 0, log))
+    assert rep.rejected == 2 and rep.completed == 0 and log == [] and rep.peak_bytes == 0
+
+
 def test_skip_idle_gaps_when_not_realtime():
     clock = FakeClock()
     reqs = [FakeReq(0, 0.0, 10, 1), FakeReq(1, 100.0, 10, 1)]
