@@ -446,6 +446,42 @@ def serve_bench(nreq, realtime):
     }
 
 
+def dynamic_bench():
+    """The undrained dynamic GIMP footing (config 2: 64 x 64 cells, 16,384 points, k = 1e-16,
+    Newmark 1/4, 1/2) over 10 steps and the harmonic strip footing of Sec. 5.2 over its first 100
+    steps, FP64 then mixed, both with the diagonal-inverse Schur block their workloads select: time
+    per step and the Newton / Krylov counts (Table 1: three Newton iterations and 12-17 Krylov
+    iterations per Newton iteration at step 100)."""
+    import torch
+    from paper_1905_00671_amd import binding as B
+    from paper_1905_00671_amd import workloads as W
+    out = {}
+    for key, make, nst in (("footing2d_undrained", lambda: W.config(2), 10),
+                           ("harmonic_footing", W.harmonic_footing, 100)):
+        o = {}
+        for pk, prec in (("fp64", 0), ("mixed", 1)):
+            w = make()
+            bcs = [w.bc(n) for n in range(1, nst + 1)]
+            p = B.Problem.from_workload(w, precision=prec)
+            try:
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                sts = [p.step(w.dt, bcs[n]) for n in range(nst)]
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t
+            finally:
+                p.close()
+            o[pk] = dict(ms_per_step=1e3 * el / nst, newton_iters=sum(x["newton_iters"] for x in sts),
+                         krylov_iters=sum(x["krylov_total"] for x in sts),
+                         max_krylov_per_newton=max(max(x["krylov_iters"]) for x in sts),
+                         last_step=dict(step=nst, newton=sts[-1]["newton_iters"], krylov=sts[-1]["krylov_iters"]))
+            log(f"{key} {pk}: {json.dumps(o[pk])}")
+        o["workload"] = f"{w.name}: {w.particles.n} points, {nst} steps, dt={w.dt} s, schur={w.options.schur}"
+        o["mixed_vs_fp64"] = o["fp64"]["ms_per_step"] / o["mixed"]["ms_per_step"]
+        out[key] = o
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -532,6 +568,7 @@ def main():
         sub["workload"] = DESCR[other]
         line[other] = sub
         line["serving"] = serve_bench(args.serve_requests, not args.serve_no_wait)
+        line["dynamic"] = dynamic_bench()
     if not args.no_parity:
         line["parity"] = parity_check(name)
     if cpu is not None:
