@@ -4,7 +4,7 @@ oracle; the runs take minutes to hours on one core, too long for a GPU test).
 
   config 2  undrained dynamic GIMP footing, 64 x 64 cells (16,384 points), Newmark beta = 1/4,
             gamma = 1/2, k = 1e-16, all 100 steps, with the PPP term (tau_W) and without it;
-            the mixed path over the first 10 steps
+            the mixed path over the first 40 steps
   config 3  the 2D GIMP quasi-static footing at h = 0.0625 m on a 128 x 64-cell replica, seeds
             0-4 (k = 10^(-14 + 4u) per seed, from drained to undrained), 4 steps
   config 4  the 3D trilinear footing on a 24^3-cell replica (110,592 points), all 20 steps; the
@@ -96,13 +96,17 @@ def test_config2_fp64_without_ppp():
 
 
 def test_config2_mixed_prefix():
-    """The mixed path on config 2 with the workload's diagonal-inverse Schur block: with the
-    fixed-stress diagonal the FP32 solves left the pressure block nearly unreduced (its residual
-    is ~1e-5 of the momentum one, below the FP32 solves' 1e-6 target) and Newton stalled."""
+    """The mixed path on config 2 with the workload's diagonal-inverse Schur block over its first
+    40 steps (each must converge; the state is compared with the oracle's at step 10, the
+    reference snapshot among them): with the fixed-stress diagonal the FP32 solves left the
+    pressure block nearly unreduced (its residual is ~1e-5 of the momentum one, below the FP32
+    solves' 1e-6 target) and Newton stalled in the first step.  At step 43, where the FP64
+    BiCGStab needs restarts after a breakdown, the FP32 solves stall with the pressure residual at
+    ~2e-8 of its start and Newton does not reach 1e-8: the mixed path covers steps 1-42."""
     ref = _load("config2_tauW")
     w = W.config(2)
-    print(f"[config 2 mixed] {w.particles.n} points, 10 steps", flush=True)
-    _run(w, ref, 10, 1, 1e-6, 1e-5)
+    print(f"[config 2 mixed] {w.particles.n} points, 40 steps", flush=True)
+    _run(w, ref, 40, 1, 1e-6, 1e-5)
 
 
 @pytest.mark.parametrize("seed", range(5))
