@@ -493,6 +493,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="headline workload only (no 2D footing, serving stream or FP64 Krylov control)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving stream")
+    ap.add_argument("--dynamic-only", action="store_true",
+                    help="only the dynamic workloads (undrained footing, harmonic footing)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-no-wait", action="store_true", help="skip idle gaps between arrivals")
     ap.add_argument("--calibrate-mb", type=int, default=0,
@@ -505,7 +507,7 @@ def main():
         sys.exit(2)
     name = args.workload
     cpu = None
-    if not args.no_cpu_baseline and not args.serve_only:
+    if not args.no_cpu_baseline and not args.serve_only and not args.dynamic_only:
         log("CPU oracle baseline (one pinned core) before the GPU is used")
         cpu = cpu_baseline(name)
         log(f"cpu_baseline: {json.dumps(cpu)}")
@@ -518,6 +520,13 @@ def main():
         line.update(metric="serving: particle-steps/s with continuous batching; p50/p99 step and request latency",
                     value=line["fp64"]["particle_steps_per_s"], unit="particle-steps/s", n_gpus=1,
                     higher_is_better=True, dtype="f64", data="synthetic")
+        print(json.dumps(line))
+        return
+    if args.dynamic_only:
+        line = dynamic_bench()
+        h = line["harmonic_footing"]
+        line.update(metric="harmonic footing (Sec. 5.2): ms per time step", value=h["fp64"]["ms_per_step"],
+                    unit="ms/step", n_gpus=1, higher_is_better=False, dtype="f64", data="synthetic")
         print(json.dumps(line))
         return
     if args.calibrate_mb > 0:

@@ -15,8 +15,8 @@
 // Point tractions: point q carries the force F_q (traction times its share of the loaded
 // boundary) on the face of its domain whose outward normal is the coordinate axis n_q; along that
 // axis the grid's hat is evaluated on the face x_a + lp_a n_a, along the others the point's own
-// 1D basis.  The few loaded points add their nodal forces with atomics (rounding-order effects
-// only).
+// 1D basis.  Each node gathers the forces of the loaded points in the buckets that can reach it,
+// in the sort's order, so its sum is formed in the same order on every run.
 #include "ppmpm_internal.hpp"
 #include "launch.hpp"
 #include "solver_common.hpp"
@@ -78,14 +78,14 @@ __device__ __forceinline__ void block_sum(double* v, double* out) {
     __syncthreads();
 }
 
-// Sum over the problem's node blocks of partial slot k (NV slots per block), in thread 0 of a
-// one-block kernel: thread t adds blocks t, t + TPB, ..., then block_sum.
+// Sum over the problem's node blocks of partial slots off .. off + nv_used - 1 (NV slots per
+// block), in thread 0: thread t adds blocks t, t + TPB, ..., then block_sum.
 template <int NV>
-__device__ __forceinline__ void sum_blocks(const Dev* d, int64_t nblk, int nv_used, double* out) {
+__device__ __forceinline__ void sum_blocks(const Dev* d, int64_t nblk, int nv_used, double* out, int off = 0) {
     double v[NV];
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
     for (int64_t i = threadIdx.x; i < nblk; i += TPB)
-        for (int k = 0; k < nv_used; ++k) v[k] += d->mpart[i * NV + k];
+        for (int k = 0; k < nv_used; ++k) v[k] += d->mpart[i * NV + off + k];
     block_sum<NV>(v, out);
 }
 
@@ -269,23 +269,25 @@ __global__ void __launch_bounds__(TPB) k_mass_q(Batch B) {
         for (int k = 0; k < MCOL; ++k) d->mpart[lb * 3 * MCOL + k] = out[k];
 }
 
-__global__ void k_mass_alpha(Batch B) {
-    const Dev* d = B.d[blockIdx.x];
-    if (!d->cons || mglob(d)[MG_ALLDONE] != 0.0) return;
-    double s[3 * MCOL];
-    sum_blocks<3 * MCOL>(d, node_blocks(d), d->ncol, s);
-    if (threadIdx.x == 0)
-        for (int c = 0; c < d->ncol; ++c) {
-            double* m = mcol(d, c);
-            m[MS_ALPHA] = (m[MS_DONE] != 0.0 || s[c] == 0.0) ? 0.0 : m[MS_RZ] / s[c];
-        }
-}
-
-// x += alpha d, r -= alpha q, z = r / M_lumped on heavy rows; partials (r.z, r.r)
+// alpha = (r.z) / (d.q) per column, formed by every block from k_mass_q's partials (the same sum
+// in the same order in each), then x += alpha d, r -= alpha q, z = r / M_lumped on heavy rows;
+// partials (r.z, r.r) in slots MCOL .. 3 MCOL - 1, past the (d.q) ones that other blocks may
+// still be reading
 __global__ void __launch_bounds__(TPB) k_mass_xr(Batch B) {
     PROB_PROLOGUE
     const int64_t N = d->Nnode;
-    const bool run = d->cons && mglob(d)[MG_ALLDONE] == 0.0;
+    const bool run = d->cons && mglob(d)[MG_ALLDONE] == 0.0;   // uniform over the block
+    __shared__ double alpha[MCOL];
+    {
+        double s[3 * MCOL];
+        if (run) sum_blocks<3 * MCOL>(d, node_blocks(d), d->ncol, s);
+        if (threadIdx.x == 0 && run)
+            for (int c = 0; c < d->ncol; ++c) {
+                const double* m = mcol(d, c);
+                alpha[c] = (m[MS_DONE] != 0.0 || s[c] == 0.0) ? 0.0 : m[MS_RZ] / s[c];
+            }
+        __syncthreads();
+    }
     double v[2 * MCOL];
     for (int k = 0; k < 2 * MCOL; ++k) v[k] = 0.0;
     if (run && tid < N && d->mheavy[tid]) {
@@ -293,7 +295,7 @@ __global__ void __launch_bounds__(TPB) k_mass_xr(Batch B) {
         node_coords(d, tid, n);
         const double m = d->M[pad_index(d, n[0], n[1], n[2])];
         for (int c = 0; c < d->ncol; ++c) {
-            const double al = mcol(d, c)[MS_ALPHA];
+            const double al = alpha[c];
             const int64_t k = c * N + tid;
             d->mx[k] += al * d->md[k];
             const double r = d->mr[k] - al * d->mq[k];
@@ -307,14 +309,14 @@ __global__ void __launch_bounds__(TPB) k_mass_xr(Batch B) {
     double out[2 * MCOL];
     block_sum<2 * MCOL>(v, out);
     if (threadIdx.x == 0 && run)
-        for (int k = 0; k < 2 * MCOL; ++k) d->mpart[lb * 3 * MCOL + k] = out[k];
+        for (int k = 0; k < 2 * MCOL; ++k) d->mpart[lb * 3 * MCOL + MCOL + k] = out[k];
 }
 
 __global__ void k_mass_beta(Batch B) {
     const Dev* d = B.d[blockIdx.x];
     if (!d->cons || mglob(d)[MG_ALLDONE] != 0.0) return;
     double s[3 * MCOL];
-    sum_blocks<3 * MCOL>(d, node_blocks(d), 2 * d->ncol, s);
+    sum_blocks<3 * MCOL>(d, node_blocks(d), 2 * d->ncol, s, MCOL);
     if (threadIdx.x == 0) {
         bool all = true;
         for (int c = 0; c < d->ncol; ++c) {
@@ -476,7 +478,6 @@ static ppmpm_status mass_solve_t(const Group& g, const std::vector<const Dev*>& 
     while (!done) {
         for (int k = 0; k < MASS_CHECK; ++k) {
             hipLaunchKernelGGL((k_mass_q<DIM, R>), gn, tb, 0, st, Bn);
-            hipLaunchKernelGGL(k_mass_alpha, g1, tb, 0, st, B1);
             hipLaunchKernelGGL(k_mass_xr, gn, tb, 0, st, Bn);
             hipLaunchKernelGGL(k_mass_beta, g1, tb, 0, st, B1);
             hipLaunchKernelGGL(k_mass_d, gn, tb, 0, st, Bn);
