@@ -91,6 +91,17 @@ __device__ __forceinline__ void sum_blocks(const Dev* d, int64_t nblk, int nv_us
 
 __device__ __forceinline__ int64_t node_blocks(const Dev* d) { return (d->Nnode + TPB - 1) / TPB; }
 
+// NS consecutive partial slots first .. first + NS - 1 summed over the problem's node blocks, in
+// thread 0: per slot the same additions in the same order as sum_blocks<3 MCOL>
+template <int NS>
+__device__ __forceinline__ void sum_slots(const Dev* d, int64_t nblk, int first, double* out) {
+    double v[NS];
+    for (int k = 0; k < NS; ++k) v[k] = 0.0;
+    for (int64_t i = threadIdx.x; i < nblk; i += TPB)
+        for (int k = 0; k < NS; ++k) v[k] += d->mpart[i * 3 * MCOL + first + k];
+    block_sum<NS>(v, out);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -240,76 +251,77 @@ __global__ void k_mass_scal0(Batch B) {
     }
 }
 
-// q = M d on heavy rows (d is 0 on the other nodes); partials (d.q)
+// One CG iteration is k_mass_q, k_mass_xr, k_mass_beta, k_mass_d.  The vector kernels run one
+// block per (run of TPB nodes, mapped field blockIdx.y): on the small grids of the consistent
+// mapping the fields would otherwise be serial work of one thread per node.  Each (block, field)
+// partial is the same sum over the same nodes in the same tree order as one slot of a block
+// reduction over all fields.
+
+// q = M d on heavy rows (d is 0 on the other nodes); partial (d.q) in slot c
 template <int DIM, int R>
 __global__ void __launch_bounds__(TPB) k_mass_q(Batch B) {
     PROB_PROLOGUE
     constexpr int SW = 2 * R + 1;
     constexpr int S = DIM == 2 ? SW * SW : SW * SW * SW;
+    const int c = blockIdx.y;
     const int64_t N = d->Nnode;
-    const bool run = d->cons && mglob(d)[MG_ALLDONE] == 0.0;
-    double v[MCOL];
-    for (int k = 0; k < MCOL; ++k) v[k] = 0.0;
-    if (run && tid < N && d->mheavy[tid]) {
+    if (!d->cons || mglob(d)[MG_ALLDONE] != 0.0 || c >= d->ncol) return;   // uniform over the block
+    double v = 0.0;
+    if (tid < N && d->mheavy[tid]) {
         int n[3];
         node_coords(d, tid, n);
-        for (int c = 0; c < d->ncol; ++c) {
-            double q = 0.0;
-            for (int e = 0; e < S; ++e) {
-                const int64_t k = stencil_nbr<DIM, R>(d, n, e);
-                if (k >= 0) q += d->mrow[e * N + tid] * d->md[c * N + k];
-            }
-            d->mq[c * N + tid] = q;
-            v[c] = d->md[c * N + tid] * q;
+        double q = 0.0;
+        for (int e = 0; e < S; ++e) {
+            const int64_t k = stencil_nbr<DIM, R>(d, n, e);
+            if (k >= 0) q += d->mrow[e * N + tid] * d->md[c * N + k];
         }
+        d->mq[c * N + tid] = q;
+        v = d->md[c * N + tid] * q;
     }
-    double out[MCOL];
-    block_sum<MCOL>(v, out);
-    if (threadIdx.x == 0 && run)
-        for (int k = 0; k < MCOL; ++k) d->mpart[lb * 3 * MCOL + k] = out[k];
+    double out[1];
+    block_sum<1>(&v, out);
+    if (threadIdx.x == 0) d->mpart[lb * 3 * MCOL + c] = out[0];
 }
 
-// alpha = (r.z) / (d.q) per column, formed by every block from k_mass_q's partials (the same sum
+// alpha = (r.z) / (d.q) of field c, formed by every block from k_mass_q's partials (the same sum
 // in the same order in each), then x += alpha d, r -= alpha q, z = r / M_lumped on heavy rows;
-// partials (r.z, r.r) in slots MCOL .. 3 MCOL - 1, past the (d.q) ones that other blocks may
-// still be reading
+// partials (r.z, r.r) in slots MCOL + 2c, MCOL + 2c + 1, past the (d.q) ones that other blocks
+// may still be reading
 __global__ void __launch_bounds__(TPB) k_mass_xr(Batch B) {
     PROB_PROLOGUE
+    const int c = blockIdx.y;
     const int64_t N = d->Nnode;
-    const bool run = d->cons && mglob(d)[MG_ALLDONE] == 0.0;   // uniform over the block
-    __shared__ double alpha[MCOL];
+    if (!d->cons || mglob(d)[MG_ALLDONE] != 0.0 || c >= d->ncol) return;   // uniform over the block
+    __shared__ double alpha;
     {
-        double s[3 * MCOL];
-        if (run) sum_blocks<3 * MCOL>(d, node_blocks(d), d->ncol, s);
-        if (threadIdx.x == 0 && run)
-            for (int c = 0; c < d->ncol; ++c) {
-                const double* m = mcol(d, c);
-                alpha[c] = (m[MS_DONE] != 0.0 || s[c] == 0.0) ? 0.0 : m[MS_RZ] / s[c];
-            }
+        double s[1];
+        sum_slots<1>(d, node_blocks(d), c, s);
+        if (threadIdx.x == 0) {
+            const double* m = mcol(d, c);
+            alpha = (m[MS_DONE] != 0.0 || s[0] == 0.0) ? 0.0 : m[MS_RZ] / s[0];
+        }
         __syncthreads();
     }
-    double v[2 * MCOL];
-    for (int k = 0; k < 2 * MCOL; ++k) v[k] = 0.0;
-    if (run && tid < N && d->mheavy[tid]) {
+    double v[2] = {0.0, 0.0};
+    if (tid < N && d->mheavy[tid]) {
         int n[3];
         node_coords(d, tid, n);
         const double m = d->M[pad_index(d, n[0], n[1], n[2])];
-        for (int c = 0; c < d->ncol; ++c) {
-            const double al = alpha[c];
-            const int64_t k = c * N + tid;
-            d->mx[k] += al * d->md[k];
-            const double r = d->mr[k] - al * d->mq[k];
-            const double z = r / m;
-            d->mr[k] = r;
-            d->mz[k] = z;
-            v[2 * c] = r * z;
-            v[2 * c + 1] = r * r;
-        }
+        const int64_t k = c * N + tid;
+        d->mx[k] += alpha * d->md[k];
+        const double r = d->mr[k] - alpha * d->mq[k];
+        const double z = r / m;
+        d->mr[k] = r;
+        d->mz[k] = z;
+        v[0] = r * z;
+        v[1] = r * r;
     }
-    double out[2 * MCOL];
-    block_sum<2 * MCOL>(v, out);
-    if (threadIdx.x == 0 && run)
-        for (int k = 0; k < 2 * MCOL; ++k) d->mpart[lb * 3 * MCOL + MCOL + k] = out[k];
+    double out[2];
+    block_sum<2>(v, out);
+    if (threadIdx.x == 0) {
+        d->mpart[lb * 3 * MCOL + MCOL + 2 * c] = out[0];
+        d->mpart[lb * 3 * MCOL + MCOL + 2 * c + 1] = out[1];
+    }
 }
 
 __global__ void k_mass_beta(Batch B) {
@@ -339,14 +351,13 @@ __global__ void k_mass_beta(Batch B) {
 
 __global__ void __launch_bounds__(TPB) k_mass_d(Batch B) {
     PROB_PROLOGUE
+    const int c = blockIdx.y;
     const int64_t N = d->Nnode;
-    if (tid >= N || !d->cons || !d->mheavy[tid]) return;
-    for (int c = 0; c < d->ncol; ++c) {
-        const double* m = mcol(d, c);
-        if (m[MS_DONE] != 0.0) continue;   // converged column: alpha stays 0
-        const int64_t k = c * N + tid;
-        d->md[k] = d->mz[k] + m[MS_BETA] * d->md[k];
-    }
+    if (tid >= N || !d->cons || c >= d->ncol || !d->mheavy[tid]) return;
+    const double* m = mcol(d, c);
+    if (m[MS_DONE] != 0.0) return;   // converged field: alpha stays 0
+    const int64_t k = c * N + tid;
+    d->md[k] = d->mz[k] + m[MS_BETA] * d->md[k];
 }
 
 // mapped fields back into the nodal arrays; constrained velocity / acceleration components start
@@ -472,15 +483,18 @@ static ppmpm_status mass_solve_t(const Group& g, const std::vector<const Dev*>& 
     hipLaunchKernelGGL(k_mass_init, gn, tb, 0, st, Bn);
     hipLaunchKernelGGL((k_mass_r0<DIM, R>), gn, tb, 0, st, Bn);
     hipLaunchKernelGGL(k_mass_scal0, g1, tb, 0, st, B1);
+    int ncol = 1;
+    for (auto* h : hc) ncol = std::max(ncol, h->ncol);
+    const dim3 gc(Bn.pfx[Bn.n], ncol);
     std::vector<double> flag(hc.size());
     int it = 0;
     bool done = false;
     while (!done) {
         for (int k = 0; k < MASS_CHECK; ++k) {
-            hipLaunchKernelGGL((k_mass_q<DIM, R>), gn, tb, 0, st, Bn);
-            hipLaunchKernelGGL(k_mass_xr, gn, tb, 0, st, Bn);
+            hipLaunchKernelGGL((k_mass_q<DIM, R>), gc, tb, 0, st, Bn);
+            hipLaunchKernelGGL(k_mass_xr, gc, tb, 0, st, Bn);
             hipLaunchKernelGGL(k_mass_beta, g1, tb, 0, st, B1);
-            hipLaunchKernelGGL(k_mass_d, gn, tb, 0, st, Bn);
+            hipLaunchKernelGGL(k_mass_d, gc, tb, 0, st, Bn);
         }
         it += MASS_CHECK;
         for (size_t q = 0; q < hc.size(); ++q)
