@@ -327,8 +327,8 @@ __global__ void __launch_bounds__(TPB) k_mass_xr(Batch B) {
 __global__ void k_mass_beta(Batch B) {
     const Dev* d = B.d[blockIdx.x];
     if (!d->cons || mglob(d)[MG_ALLDONE] != 0.0) return;
-    double s[3 * MCOL];
-    sum_blocks<3 * MCOL>(d, node_blocks(d), 2 * d->ncol, s, MCOL);
+    double s[2 * MCOL];
+    sum_slots<2 * MCOL>(d, node_blocks(d), MCOL, s);   // (r.z, r.r) of every field
     if (threadIdx.x == 0) {
         bool all = true;
         for (int c = 0; c < d->ncol; ++c) {
